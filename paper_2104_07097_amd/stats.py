@@ -1,0 +1,91 @@
+"""Host-side statistics for judging samplers: effective sample size and
+Kolmogorov-Smirnov distances.
+
+The ESS estimator follows the multi-chain recipe of Gelman et al.,
+*Bayesian Data Analysis* (3rd ed., S11.5) as used by Stan: split each chain
+in half, pool within- and between-chain variances, and sum the
+autocorrelations with Geyer's initial monotone sequence (Geyer 1992,
+"Practical Markov chain Monte Carlo").  Autocovariances come from FFTs.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _autocov(x: np.ndarray) -> np.ndarray:
+    """Biased autocovariance of each row of x (chains x draws), all lags."""
+    c, t = x.shape
+    x = x - x.mean(axis=1, keepdims=True)
+    size = 1
+    while size < 2 * t:
+        size *= 2
+    f = np.fft.rfft(x, n=size, axis=1)
+    ac = np.fft.irfft(f * np.conj(f), n=size, axis=1)[:, :t]
+    return ac / t
+
+
+def ess(draws: np.ndarray) -> float:
+    """Effective sample size of one scalar quantity.
+
+    draws: array (chains, iterations).  Returns the multi-chain ESS
+    (split chains, Geyer initial monotone sequence)."""
+    draws = np.asarray(draws, dtype=np.float64)
+    if draws.ndim == 1:
+        draws = draws[None, :]
+    c, t = draws.shape
+    half = t // 2
+    if half < 4:
+        return float(c * t)
+    x = np.concatenate([draws[:, :half], draws[:, t - half:]], axis=0)
+    m, n = x.shape
+    acov = _autocov(x)
+    chain_mean = x.mean(axis=1)
+    chain_var = acov[:, 0] * n / (n - 1.0)
+    w = chain_var.mean()
+    b_over_n = chain_mean.var(ddof=1) if m > 1 else 0.0
+    var_plus = w * (n - 1.0) / n + b_over_n
+    if not var_plus > 0:
+        return float(m * n)
+    rho = 1.0 - (w - acov.mean(axis=0)) / var_plus
+    rho[0] = 1.0
+    # Geyer: pair sums P_k = rho_{2k} + rho_{2k+1}, stop at the first
+    # non-positive pair, then enforce monotone decrease.
+    pairs = []
+    k = 0
+    while 2 * k + 1 < n:
+        p = rho[2 * k] + rho[2 * k + 1]
+        if p <= 0:
+            break
+        pairs.append(p)
+        k += 1
+    pairs = np.minimum.accumulate(np.array(pairs)) if pairs else np.array([1.0])
+    tau = -1.0 + 2.0 * pairs.sum()
+    tau = max(tau, 1.0 / np.log10(m * n))
+    return float(m * n / tau)
+
+
+def min_marginal_ess(samples: np.ndarray) -> tuple[float, np.ndarray]:
+    """samples: (iterations, chains, n).  Returns (min over coordinates, per-coordinate ESS)."""
+    samples = np.asarray(samples, dtype=np.float64)
+    per = np.array([ess(samples[:, :, j].T) for j in range(samples.shape[2])])
+    return float(per.min()), per
+
+
+def ks_distance(sample: np.ndarray, cdf) -> float:
+    """One-sample Kolmogorov-Smirnov distance sup |F_n - F|."""
+    x = np.sort(np.asarray(sample, dtype=np.float64))
+    k = x.size
+    f = cdf(x)
+    upper = np.arange(1, k + 1) / k - f
+    lower = f - np.arange(0, k) / k
+    return float(max(upper.max(), lower.max()))
+
+
+def ks_two_sample(a: np.ndarray, b: np.ndarray) -> float:
+    """Two-sample Kolmogorov-Smirnov distance."""
+    a = np.sort(np.asarray(a, dtype=np.float64))
+    b = np.sort(np.asarray(b, dtype=np.float64))
+    grid = np.concatenate([a, b])
+    fa = np.searchsorted(a, grid, side="right") / a.size
+    fb = np.searchsorted(b, grid, side="right") / b.size
+    return float(np.abs(fa - fb).max())

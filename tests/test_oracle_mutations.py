@@ -1,0 +1,85 @@
+"""Plants plausible mistakes in a copy of the oracle (on the CPU) and checks
+that the pins catch every one: each mutant must fail at least one pin."""
+import os
+
+import pytest
+
+import oracle as oracle_pkg
+from oracle import TAG_DIR, Oracle, load
+
+from . import test_oracle_chord as chord
+from . import test_oracle_precond as precond
+from . import test_oracle_projection as proj
+from . import test_oracle_rng as rng
+from . import test_oracle_sampler as sampler
+
+PINS = [
+    rng.test_philox_published_kat,
+    lambda o: rng.test_stream_layout(o, 12345678901234, TAG_DIR, 77, 3, 5),
+    rng.test_uniforms_open_and_uniform,
+    rng.test_gauss_distribution,
+    lambda o: chord.test_interval_worked_example(o, 2.0, 7.5, 6.9),
+    chord.test_hypercube_closed_form,
+    chord.test_bisection_brute_force,
+    proj.test_simplex_closed_form,
+    lambda o: proj.test_projector_invariants(o, 40, 5, 1),
+    sampler.test_simplex_stationary_from_exact_start,
+    sampler.test_simplex_cut_small_feasible,
+    precond.test_nll_matches_scipy,
+    precond.test_gradient_finite_differences,
+    precond.test_adam_closed_form,
+    precond.test_direction_covariance,
+]
+
+MUTANTS = {
+    "philox_multiplier": ("0xD2511F53u", "0xD2511F55u"),
+    "philox_rounds": ("round < 10", "round < 9"),
+    "uniform_bits": (">> 12;", ">> 11;"),
+    "box_muller_radius": ("sqrt(-2.0 * log(ua))", "sqrt(-log(ua))"),
+    "box_muller_pairing": ("(j & 1) ? radius * sin(angle) : radius * cos(angle)",
+                           "(j & 1) ? radius * cos(angle) : radius * sin(angle)"),
+    "counter_words": ("ctr[1] = (uint32_t)chain;", "ctr[1] = (uint32_t)block;"),
+    "chord_min_as_max": ("if (r < hi) hi = r;", "if (r > lo) hi = r;"),
+    "chord_sign_sets": ("if (g > 0.0) {", "if (g < 0.0) {"),
+    "theta_formula": ("theta = lo + u * (hi - lo);", "theta = lo + u * hi;"),
+    "update_sign": ("x[j] = x[j] + theta * d[j];", "x[j] = x[j] - theta * d[j];"),
+    "projection_sign": ("P[i * n + j] -= v;", "P[i * n + j] += v;"),
+    "projection_no_inverse": ("cholesky_solve(m_eq, L, col);", ";"),
+    "projection_skipped": ("d[i] = v;", "d[i] = h[i];"),
+    "precond_scale": ("h[j] = v + exp(log_sigma[j]) * h[j];",
+                      "h[j] = v + exp(2.0 * log_sigma[j]) * h[j];"),
+    "nll_grad_factor": ("grad_U[i * r + a] = v;", "grad_U[i * r + a] = 0.5 * v;"),
+    "nll_logdet": ("logdet += 2.0 * log(L[i * n + i]);", "logdet += log(L[i * n + i]);"),
+    "adam_bias": ("double mh = m1[i] / c1;", "double mh = m1[i];"),
+}
+
+
+def _fails(o, pin):
+    try:
+        pin(o)
+    except AssertionError:
+        return True
+    except Exception:  # a crash or error also counts as caught
+        return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle_pkg.SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} must be unique"
+    mutated = tmp_path / "mhar_ref.c"
+    mutated.write_text(src.replace(old, new))
+    (tmp_path / "mhar_ref.h").write_text(open(os.path.join(oracle_pkg.HERE, "mhar_ref.h")).read())
+    lib_path = str(tmp_path / "libmut.so")
+    import subprocess
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", "-o",
+                    lib_path, str(mutated), "-lm"], check=True)
+    o = Oracle(load(lib_path))
+    assert any(_fails(o, pin) for pin in PINS), f"no pin caught mutant {name}"
+
+
+def test_unmutated_oracle_passes_all_pins():
+    o = Oracle()
+    assert not any(_fails(o, pin) for pin in PINS)
