@@ -1,0 +1,197 @@
+/*
+ * mhar.h -- C ABI of libmhar, a Matrix Hit-and-Run (MHAR) sampler for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem (paper S2.1): sample uniformly from
+ *     Delta = { x in R^n : A x <= b,  A_eq x = b_eq }
+ * with z hit-and-run walks advanced together (paper S4, Alg. 2).  One step
+ * of every walk k:
+ *   1. h ~ N(0, I_n) from a counter-based Philox4x32-10 stream, Box-Muller
+ *      pairs (paper S4.3, Lemma 4.1);
+ *   2. d = P h with P = I - A_eq^T (A_eq A_eq^T)^{-1} A_eq when m_eq > 0
+ *      (paper S3.2, Lemma 3.1), applied in factored form;
+ *   3. line set: lambda_max = min over a_i d > 0 of (b_i - a_i x)/(a_i d),
+ *      lambda_min = max over a_i d < 0 (paper S4.4, Lemma 4.2);
+ *   4. theta = lambda_min + U (lambda_max - lambda_min), U ~ U(0,1) from the
+ *      THETA stream; x <- x + theta d (paper S4.5, Lemma 4.3).
+ * The products A D run on the matrix cores in the chosen precision; they only
+ * screen which rows can bound each chord.  The bounding rows are then
+ * evaluated exactly in FP64 with the formula of step 3, so the chord (and
+ * the trajectory) is that of FP64 arithmetic in every precision mode.
+ *
+ * Random streams (identical definition in any conforming implementation):
+ *   key     = (seed & 0xffffffff, seed >> 32)
+ *   counter = (block, chain_id, step & 0xffffffff, tag | (step >> 32) << 4)
+ *   tags: DIR = 0 (directions), THETA = 1 (chord position), LOWRANK = 2
+ *   uniform: 52 high bits u of (w_hi << 32 | w_lo) -> (u + 1/2) 2^-52
+ *   normal j of a stream: block j/2, u_a from words (0,1), u_b from (2,3);
+ *   sqrt(-2 ln u_a) * (cos if j even else sin)(2 pi u_b)
+ *   theta's U: block 0 of the THETA stream, words (0,1).
+ *   chain_id = chain_offset + k, so chains can be split across calls (or
+ *   devices) without changing any trajectory.
+ *
+ * Conventions
+ *   - Matrices are row-major.  State matrices are (z x n): row k = walk k.
+ *   - "dev" pointers are HIP device pointers; "host" pointers host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls enqueue work on it and return without synchronising, except
+ *     where a call says it synchronises.
+ *   - The caller owns every buffer it passes in.  The library never
+ *     allocates device memory: create calls take a caller-provided device
+ *     workspace whose size the matching *_workspace_size call reports, and
+ *     which must stay valid until the handle is destroyed.  Handles are
+ *     small host objects freed by the destroy calls.
+ *   - Every call returns a status (0 = MHAR_OK, negative = error).  No call
+ *     aborts; the text of the last error of the calling thread is available
+ *     from mhar_last_error().  Argument and shape errors are reported before
+ *     any work is enqueued.
+ *   - Conditions found on the device are per-walk status bits (below),
+ *     read with mhar_get_state / mhar_sync; a flagged walk stays where it is
+ *     for that step (theta = 0) and keeps going.
+ */
+#ifndef MHAR_H
+#define MHAR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MHAR_OK = 0,
+    MHAR_E_INVALID_ARG = -1,    /* null pointer, bad option value */
+    MHAR_E_SHAPE = -2,          /* sizes out of the supported range */
+    MHAR_E_RANK_DEFICIENT = -3, /* A_eq rows linearly dependent (pivot of A_eq A_eq^T <= 1e-12 max diag) */
+    MHAR_E_NOT_INTERIOR = -4,   /* a start point is not strictly inside Delta */
+    MHAR_E_WORKSPACE = -5,      /* workspace too small or misaligned (256 B) */
+    MHAR_E_HIP = -6,            /* a HIP runtime call failed */
+    MHAR_E_UNSUPPORTED = -7,    /* no kernel for this configuration */
+    MHAR_E_STATE = -8           /* call not valid for the handle's state */
+} mhar_status_t;
+
+/* Precision of the matrix-core product A D (the screening product).  The
+ * chord itself is always evaluated in FP64. */
+typedef enum {
+    MHAR_FP64 = 0,   /* FP64 MFMA */
+    MHAR_FP32 = 1,   /* FP32 MFMA */
+    MHAR_BF16X3 = 2  /* A and D split into bf16 hi + lo; hi*hi + hi*lo + lo*hi, FP32 accumulate */
+} mhar_precision_t;
+
+/* per-walk status bits */
+enum {
+    MHAR_CHAIN_OK = 0,
+    MHAR_CHAIN_UNBOUNDED = 1,   /* no row bounds the line on one side (Delta assumed bounded, S2.1) */
+    MHAR_CHAIN_DEGENERATE = 2,  /* lambda_max <= lambda_min */
+    MHAR_CHAIN_NONFINITE = 4,   /* NaN/Inf in theta or the state */
+    MHAR_CHAIN_INFEASIBLE = 8   /* exact FP64 slack below -1e-12 max(1,|b_i|) */
+};
+
+typedef struct {
+    int32_t precision;        /* mhar_precision_t, default MHAR_FP32 */
+    int32_t recompute_every;  /* R >= 1: exact FP64 recompute of the slack b - A X every R steps (default 50) */
+    int32_t steps_per_launch; /* 0 = automatic; bounds the steps one kernel launch runs */
+    int32_t reserved[5];      /* must be 0 */
+} mhar_options_t;
+
+typedef struct mhar_problem* mhar_problem_t;
+typedef struct mhar_chains* mhar_chains_t;
+
+/* Diagnostics of one chains handle, accumulated since creation. */
+typedef struct {
+    uint64_t steps;             /* steps taken by every walk */
+    uint64_t chain_steps;       /* walks x steps */
+    uint64_t exact_rows;        /* rows evaluated exactly in FP64 (candidates of the screening) */
+    uint64_t recomputes;        /* exact slack recomputes */
+} mhar_stats_t;
+
+/* library version as major*10000 + minor*100 + patch */
+int32_t mhar_version(void);
+/* static text for a status code */
+const char* mhar_status_string(int32_t status);
+/* text of the last error raised on the calling thread ("" if none) */
+const char* mhar_last_error(void);
+/* fill *opt with the defaults */
+mhar_status_t mhar_options_default(mhar_options_t* opt);
+
+/* ---------------------------------------------------------------------- */
+/* Problem: the polytope (paper S2.1) and its one-time setup              */
+/* ---------------------------------------------------------------------- */
+
+/* Device workspace bytes needed by mhar_problem_create for these sizes.
+ * Supported: 1 <= n <= 1152, 1 <= m <= 2^24, 0 <= m_eq < n, m_eq <= 64. */
+mhar_status_t mhar_problem_workspace_size(int64_t n, int64_t m, int64_t m_eq,
+                                          const mhar_options_t* opt, size_t* bytes);
+
+/* Copy the polytope into the workspace and run the one-time setup: FP64
+ * copy of A (rows padded), row norms, the operand form of A for the chosen
+ * precision and, when m_eq > 0, the Cholesky factor of A_eq A_eq^T and
+ * W = A_eq^T (A_eq A_eq^T)^{-1} (paper S3.2; the explicit inverse of the
+ * paper is replaced by triangular solves).
+ *   A    dev, m x n FP64;  b dev, m;  A_eq dev, m_eq x n FP64 or NULL;
+ *   b_eq dev, m_eq or NULL;  opt host or NULL (defaults);
+ *   workspace dev, 256-byte aligned, ws_bytes >= the workspace size.
+ * Synchronises `stream` once (to report MHAR_E_RANK_DEFICIENT); the input
+ * arrays may be freed when it returns. */
+mhar_status_t mhar_problem_create(int64_t n, int64_t m, const double* A, const double* b,
+                                  int64_t m_eq, const double* A_eq, const double* b_eq,
+                                  const mhar_options_t* opt, void* workspace, size_t ws_bytes,
+                                  void* stream, mhar_problem_t* out);
+
+/* Write the dense projection P = I - W A_eq (n x n FP64, dev) -- the
+ * matrix the paper precomputes (S3.2) -- for inspection. */
+mhar_status_t mhar_problem_get_projection(mhar_problem_t problem, double* P, void* stream);
+
+mhar_status_t mhar_problem_destroy(mhar_problem_t problem);
+
+/* ---------------------------------------------------------------------- */
+/* Chains: z walks on one problem (paper Alg. 2)                          */
+/* ---------------------------------------------------------------------- */
+
+/* Device workspace bytes for z walks on `problem` (z >= 1). */
+mhar_status_t mhar_chains_workspace_size(mhar_problem_t problem, int64_t z, size_t* bytes);
+
+/* Start z walks at X0 (dev, z x n FP64), global chain ids chain_offset..,
+ * Philox key `seed`, step counter 0.  Every start point must be strictly
+ * interior: b - A x > 0 and |A_eq x - b_eq|_inf <= 1e-9 (Alg. 2 starts from
+ * a strictly inner point), else MHAR_E_NOT_INTERIOR.  Synchronises `stream`
+ * once for that check.  chain_offset + z must not exceed 2^32. */
+mhar_status_t mhar_chains_create(mhar_problem_t problem, int64_t z, const double* X0,
+                                 uint64_t seed, uint64_t chain_offset, void* workspace,
+                                 size_t ws_bytes, void* stream, mhar_chains_t* out);
+
+/* Enqueue `steps` MHAR iterations of every walk (steps >= 0). */
+mhar_status_t mhar_step(mhar_chains_t chains, int64_t steps, void* stream);
+
+/* Like mhar_step, and also store the states of walks 0 .. chain_count-1
+ * after every stride-th step of this call into out (dev, FP64,
+ * (steps/stride) x chain_count x n): the paper's thinned collection of
+ * samples (Alg. 2, thinning factor = stride). */
+mhar_status_t mhar_record(mhar_chains_t chains, int64_t steps, int64_t stride,
+                          int64_t chain_count, double* out, void* stream);
+
+/* Copy the current states (dev z x n FP64, may be NULL) and the per-walk
+ * status bits (dev int32 z, may be NULL). */
+mhar_status_t mhar_get_state(mhar_chains_t chains, double* X, int32_t* status, void* stream);
+
+/* Replace the states with X (dev z x n FP64) and set the step counter;
+ * the slack is recomputed exactly and the status bits cleared.  Used to
+ * resume from a checkpoint.  The states are not re-validated. */
+mhar_status_t mhar_set_state(mhar_chains_t chains, const double* X, uint64_t step, void* stream);
+
+/* Current step counter (host, no synchronisation). */
+mhar_status_t mhar_get_step(mhar_chains_t chains, uint64_t* step);
+
+/* Synchronise `stream` and return the OR of all per-walk status bits. */
+mhar_status_t mhar_sync(mhar_chains_t chains, void* stream, int32_t* any_flags);
+
+/* Synchronise `stream` and read the diagnostics counters. */
+mhar_status_t mhar_get_stats(mhar_chains_t chains, void* stream, mhar_stats_t* stats);
+
+mhar_status_t mhar_chains_destroy(mhar_chains_t chains);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHAR_H */

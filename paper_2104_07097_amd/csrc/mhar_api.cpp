@@ -1,0 +1,538 @@
+// mhar_api.cpp -- host runtime behind the C ABI of include/mhar.h:
+// argument checking, workspace planning, handle state and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mhar.h"
+#include "mhar_internal.hpp"
+
+using namespace mhar;
+
+struct mhar_problem {
+    int n, m, m_pad, lda, m_eq, prec, R, steps_per_launch;
+    float eps_g, u_s;
+    double *A64, *b64, *Aeq, *beq, *WT;
+    float *A32, *rownorm, *absb;
+    __bf16 *Ahi, *Alo;
+    int* status;
+    int live_chains;
+};
+
+struct mhar_chains {
+    mhar_problem* p;
+    int z, z_pad;
+    uint64_t seed;
+    uint32_t chain_offset;
+    uint64_t step;
+    int pending, T, since;
+    uint64_t recomputes;
+    double *X, *D, *theta, *E;
+    void *S, *G;
+    float* L;
+    int* flags;
+    unsigned long long* counters;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mhar_status_t fail(mhar_status_t code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+mhar_status_t hip_fail(hipError_t e, const char* what)
+{
+    return fail(MHAR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define MHAR_HIP(call, what)                             \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+// Sequential carving of a workspace into 256-byte aligned pieces.
+struct Carver {
+    char* base;
+    size_t used = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T> T* take(size_t count)
+    {
+        used = (size_t)round_up((int64_t)used, 256);
+        T* p = base ? (T*)(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+struct ProblemDims {
+    int n, m, m_pad, lda, m_eq;
+};
+
+mhar_status_t check_options(const mhar_options_t* opt, mhar_options_t* out)
+{
+    mhar_options_default(out);
+    if (!opt) return MHAR_OK;
+    if (opt->precision < MHAR_FP64 || opt->precision > MHAR_BF16X3)
+        return fail(MHAR_E_INVALID_ARG, "options.precision must be MHAR_FP64, MHAR_FP32 or MHAR_BF16X3");
+    if (opt->recompute_every < 1)
+        return fail(MHAR_E_INVALID_ARG, "options.recompute_every must be >= 1");
+    if (opt->recompute_every > 100000)
+        return fail(MHAR_E_INVALID_ARG, "options.recompute_every must be <= 100000");
+    if (opt->steps_per_launch < 0)
+        return fail(MHAR_E_INVALID_ARG, "options.steps_per_launch must be >= 0");
+    for (int i = 0; i < 5; ++i)
+        if (opt->reserved[i] != 0) return fail(MHAR_E_INVALID_ARG, "options.reserved must be 0");
+    *out = *opt;
+    return MHAR_OK;
+}
+
+mhar_status_t check_dims(int64_t n, int64_t m, int64_t m_eq, ProblemDims* d)
+{
+    if (n < 1 || n > kMaxN)
+        return fail(MHAR_E_SHAPE, "n must be in [1, " + std::to_string(kMaxN) + "]");
+    if (m < 1 || m > (int64_t(1) << 24)) return fail(MHAR_E_SHAPE, "m must be in [1, 2^24]");
+    if (m_eq < 0 || m_eq > kMaxMeq || m_eq >= n)
+        return fail(MHAR_E_SHAPE, "m_eq must be in [0, min(64, n-1)]");
+    d->n = (int)n;
+    d->m = (int)m;
+    d->m_eq = (int)m_eq;
+    d->m_pad = (int)round_up(m, kRowGroup);
+    d->lda = (int)round_up(n, kKAlign);
+    return MHAR_OK;
+}
+
+size_t carve_problem(const ProblemDims& d, int prec, void* ws, mhar_problem* p)
+{
+    Carver c(ws);
+    mhar_problem tmp{};
+    mhar_problem* q = p ? p : &tmp;
+    size_t mat = (size_t)d.m_pad * d.lda;
+    q->A64 = c.take<double>(mat);
+    q->A32 = prec == MHAR_FP32 ? c.take<float>(mat) : nullptr;
+    q->Ahi = prec == MHAR_BF16X3 ? c.take<__bf16>(mat) : nullptr;
+    q->Alo = prec == MHAR_BF16X3 ? c.take<__bf16>(mat) : nullptr;
+    q->b64 = c.take<double>(d.m_pad);
+    q->rownorm = c.take<float>(d.m_pad);
+    q->absb = c.take<float>(d.m_pad);
+    size_t eq = (size_t)std::max(d.m_eq, 1) * d.lda;
+    q->Aeq = c.take<double>(eq);
+    q->beq = c.take<double>(std::max(d.m_eq, 1));
+    q->WT = c.take<double>(eq);
+    q->status = c.take<int>(64);
+    return c.used;
+}
+
+size_t carve_chains(const mhar_problem* p, int z_pad, void* ws, mhar_chains* ch)
+{
+    Carver c(ws);
+    mhar_chains tmp{};
+    mhar_chains* q = ch ? ch : &tmp;
+    size_t rows = (size_t)z_pad * p->lda;
+    size_t st = p->prec == MHAR_FP64 ? sizeof(double) : sizeof(float);
+    q->X = c.take<double>(rows);
+    q->D = c.take<double>(rows);
+    q->S = c.take<char>((size_t)z_pad * p->m_pad * st);
+    q->G = c.take<char>((size_t)z_pad * p->m_pad * st);
+    q->L = c.take<float>((size_t)(z_pad / kChainTile) * (p->m_pad / kRowGroup) * 2 * kChainTile);
+    q->theta = c.take<double>(z_pad);
+    q->E = c.take<double>(z_pad);
+    q->flags = c.take<int>(z_pad);
+    q->counters = c.take<unsigned long long>(8);
+    return c.used;
+}
+
+float eps_for(int prec, int n)
+{
+    // error coefficient of the screening product: |G_hat - G| <= eps ||a|| ||d||,
+    // with a factor 2 of headroom over the standard rounding-error bounds
+    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    double e;
+    if (prec == MHAR_FP64) e = 2.0 * (n + 3) * u64;
+    else if (prec == MHAR_FP32) e = 2.0 * (n + 3) * u32;
+    else e = 2.0 * (3.03 * std::ldexp(1.0, -16) + (3.0 * n + 3) * u32);
+    return (float)(e * (1.0 + 1e-6));
+}
+
+void advance_schedule(mhar_chains* c, int64_t steps)
+{
+    for (int64_t s = 0; s < steps; ++s) {
+        c->pending = 1;
+        c->T += 1;
+        c->since += 1;
+        if (c->since >= c->p->R) {
+            c->pending = 0;
+            c->T = 2;
+            c->since = 0;
+            c->recomputes += 1;
+        }
+    }
+    c->step += (uint64_t)steps;
+}
+
+StepArgs make_args(const mhar_chains* c)
+{
+    const mhar_problem* p = c->p;
+    StepArgs a{};
+    a.n = p->n;
+    a.m = p->m;
+    a.m_pad = p->m_pad;
+    a.lda = p->lda;
+    a.m_eq = p->m_eq;
+    a.A64 = p->A64;
+    a.A32 = p->A32;
+    a.Ahi = p->Ahi;
+    a.Alo = p->Alo;
+    a.b64 = p->b64;
+    a.rownorm = p->rownorm;
+    a.absb = p->absb;
+    a.Aeq = p->Aeq;
+    a.WT = p->WT;
+    a.z = c->z;
+    a.z_pad = c->z_pad;
+    a.X = c->X;
+    a.D = c->D;
+    a.S = c->S;
+    a.G = c->G;
+    a.L = c->L;
+    a.theta = c->theta;
+    a.E = c->E;
+    a.flags = c->flags;
+    a.counters = c->counters;
+    a.seed = c->seed;
+    a.chain_offset = c->chain_offset;
+    a.step0 = c->step;
+    a.pending0 = c->pending;
+    a.T0 = c->T;
+    a.since0 = c->since;
+    a.R = p->R;
+    a.eps_g = p->eps_g;
+    a.u_s = p->u_s;
+    return a;
+}
+
+int64_t auto_chunk(const mhar_problem* p)
+{
+    int64_t work = (int64_t)p->m_pad * p->lda;
+    int64_t chunk = (int64_t(1) << 29) / std::max<int64_t>(work, 1);
+    return std::min<int64_t>(std::max<int64_t>(chunk, 1), 100000);
+}
+
+// run `steps` steps (and the optional leading recompute), in launches of at
+// most steps_per_launch steps each
+mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, double* rec_out,
+                        int64_t stride, int64_t rec_chains, hipStream_t stream)
+{
+    const mhar_problem* p = c->p;
+    int64_t chunk = p->steps_per_launch > 0 ? p->steps_per_launch : auto_chunk(p);
+    int64_t done = 0;
+    if (recompute_first) {
+        StepArgs a = make_args(c);
+        a.steps = 0;
+        a.recompute_first = 1;
+        MHAR_HIP(launch_steps(p->prec, a, stream), "launch of the step kernel");
+        c->pending = 0;
+        c->T = 2;
+        c->since = 0;
+        c->recomputes += 1;
+    }
+    while (done < steps) {
+        int64_t k = std::min(chunk, steps - done);
+        StepArgs a = make_args(c);
+        a.steps = (int)k;
+        a.recompute_first = 0;
+        if (rec_out) {
+            a.rec_out = rec_out;
+            a.rec_stride = (int)stride;
+            a.rec_chains = (int)rec_chains;
+            a.rec_s_base = done;
+        }
+        MHAR_HIP(launch_steps(p->prec, a, stream), "launch of the step kernel");
+        advance_schedule(c, k);
+        done += k;
+    }
+    return MHAR_OK;
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t mhar_version(void) { return 100; }
+
+const char* mhar_status_string(int32_t s)
+{
+    switch (s) {
+    case MHAR_OK: return "ok";
+    case MHAR_E_INVALID_ARG: return "invalid argument";
+    case MHAR_E_SHAPE: return "unsupported shape";
+    case MHAR_E_RANK_DEFICIENT: return "equality rows are linearly dependent";
+    case MHAR_E_NOT_INTERIOR: return "start point not strictly interior";
+    case MHAR_E_WORKSPACE: return "workspace too small or misaligned";
+    case MHAR_E_HIP: return "HIP runtime error";
+    case MHAR_E_UNSUPPORTED: return "unsupported configuration";
+    case MHAR_E_STATE: return "invalid handle state";
+    default: return "unknown status";
+    }
+}
+
+const char* mhar_last_error(void) { return g_last_error.c_str(); }
+
+mhar_status_t mhar_options_default(mhar_options_t* opt)
+{
+    if (!opt) return fail(MHAR_E_INVALID_ARG, "opt is NULL");
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = MHAR_FP32;
+    opt->recompute_every = 50;
+    opt->steps_per_launch = 0;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_problem_workspace_size(int64_t n, int64_t m, int64_t m_eq,
+                                          const mhar_options_t* opt, size_t* bytes)
+{
+    if (!bytes) return fail(MHAR_E_INVALID_ARG, "bytes is NULL");
+    mhar_options_t o;
+    mhar_status_t st = check_options(opt, &o);
+    if (st) return st;
+    ProblemDims d;
+    st = check_dims(n, m, m_eq, &d);
+    if (st) return st;
+    *bytes = carve_problem(d, o.precision, nullptr, nullptr);
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_problem_create(int64_t n, int64_t m, const double* A, const double* b,
+                                  int64_t m_eq, const double* A_eq, const double* b_eq,
+                                  const mhar_options_t* opt, void* workspace, size_t ws_bytes,
+                                  void* stream_, mhar_problem_t* out)
+{
+    if (!out) return fail(MHAR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!A || !b) return fail(MHAR_E_INVALID_ARG, "A and b must be device pointers");
+    if (m_eq > 0 && (!A_eq || !b_eq)) return fail(MHAR_E_INVALID_ARG, "A_eq and b_eq required when m_eq > 0");
+    mhar_options_t o;
+    mhar_status_t st = check_options(opt, &o);
+    if (st) return st;
+    ProblemDims d;
+    st = check_dims(n, m, m_eq, &d);
+    if (st) return st;
+    if (!workspace || !aligned256(workspace)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    size_t need = carve_problem(d, o.precision, nullptr, nullptr);
+    if (ws_bytes < need) return fail(MHAR_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+
+    hipStream_t stream = (hipStream_t)stream_;
+    mhar_problem* p = new mhar_problem{};
+    p->n = d.n;
+    p->m = d.m;
+    p->m_pad = d.m_pad;
+    p->lda = d.lda;
+    p->m_eq = d.m_eq;
+    p->prec = o.precision;
+    p->R = o.recompute_every;
+    p->steps_per_launch = o.steps_per_launch;
+    p->eps_g = eps_for(o.precision, d.n);
+    p->u_s = o.precision == MHAR_FP64 ? std::ldexp(1.0f, -53) : std::ldexp(1.0f, -24);
+    carve_problem(d, o.precision, workspace, p);
+
+    hipError_t e = launch_convert_problem(p->prec, p->n, p->m, p->m_pad, p->lda, A, b, p->A64,
+                                          p->A32, p->Ahi, p->Alo, p->b64, p->rownorm, p->absb,
+                                          stream);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "problem conversion");
+    }
+    int bad = 0;
+    if (p->m_eq > 0) {
+        e = launch_eq_setup(p->n, p->lda, p->m_eq, A_eq, b_eq, p->Aeq, p->beq, p->WT, p->status, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&bad, p->status, sizeof(int), hipMemcpyDeviceToHost, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(e, "problem setup");
+    }
+    if (bad) {
+        delete p;
+        return fail(MHAR_E_RANK_DEFICIENT, "A_eq A_eq^T is singular to working precision");
+    }
+    *out = p;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_problem_get_projection(mhar_problem_t p, double* P, void* stream)
+{
+    if (!p || !P) return fail(MHAR_E_INVALID_ARG, "problem and P must be non-NULL");
+    if (p->m_eq == 0) {
+        // identity
+        MHAR_HIP(launch_dense_projection(p->n, p->lda, 0, p->Aeq, p->WT, P, (hipStream_t)stream),
+                 "projection kernel");
+        return MHAR_OK;
+    }
+    MHAR_HIP(launch_dense_projection(p->n, p->lda, p->m_eq, p->Aeq, p->WT, P, (hipStream_t)stream),
+             "projection kernel");
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_problem_destroy(mhar_problem_t p)
+{
+    if (!p) return MHAR_OK;
+    if (p->live_chains > 0) return fail(MHAR_E_STATE, "destroy the chains of this problem first");
+    delete p;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_chains_workspace_size(mhar_problem_t p, int64_t z, size_t* bytes)
+{
+    if (!p || !bytes) return fail(MHAR_E_INVALID_ARG, "problem and bytes must be non-NULL");
+    if (z < 1 || z > (int64_t(1) << 31)) return fail(MHAR_E_SHAPE, "z must be in [1, 2^31]");
+    *bytes = carve_chains(p, (int)round_up(z, kChainTile), nullptr, nullptr);
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_chains_create(mhar_problem_t p, int64_t z, const double* X0, uint64_t seed,
+                                 uint64_t chain_offset, void* workspace, size_t ws_bytes,
+                                 void* stream_, mhar_chains_t* out)
+{
+    if (!out) return fail(MHAR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p || !X0) return fail(MHAR_E_INVALID_ARG, "problem and X0 must be non-NULL");
+    if (z < 1 || z > (int64_t(1) << 31)) return fail(MHAR_E_SHAPE, "z must be in [1, 2^31]");
+    if (chain_offset + (uint64_t)z > (uint64_t(1) << 32))
+        return fail(MHAR_E_SHAPE, "chain_offset + z must not exceed 2^32");
+    if (!workspace || !aligned256(workspace)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    const int z_pad = (int)round_up(z, kChainTile);
+    size_t need = carve_chains(p, z_pad, nullptr, nullptr);
+    if (ws_bytes < need) return fail(MHAR_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    hipStream_t stream = (hipStream_t)stream_;
+
+    mhar_chains* c = new mhar_chains{};
+    c->p = p;
+    c->z = (int)z;
+    c->z_pad = z_pad;
+    c->seed = seed;
+    c->chain_offset = (uint32_t)chain_offset;
+    carve_chains(p, z_pad, workspace, c);
+    auto cleanup = [&](mhar_status_t code) {
+        delete c;
+        return code;
+    };
+    hipError_t e = launch_fill_i32((int*)c->theta, (int64_t)z_pad * 2, 0, stream);
+    if (e == hipSuccess) e = launch_fill_i32((int*)c->E, (int64_t)z_pad * 2, 0, stream);
+    if (e == hipSuccess) e = launch_fill_i32(c->flags, z_pad, 0, stream);
+    if (e == hipSuccess) e = launch_fill_i32((int*)c->counters, 16, 0, stream);
+    if (e == hipSuccess) e = launch_fill_i32((int*)c->D, (int64_t)z_pad * p->lda * 2, 0, stream);
+    if (e == hipSuccess) e = launch_copy_states(p->n, p->lda, c->z, z_pad, X0, c->X, stream);
+    if (e == hipSuccess && p->m_eq > 0)
+        e = launch_eq_residual(p->n, p->lda, c->z, p->m_eq, p->Aeq, p->beq, c->X, c->flags, stream);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "chain setup"));
+    mhar_status_t st = run_steps(c, 0, 1, nullptr, 0, 0, stream);
+    if (st) return cleanup(st);
+    std::vector<int> fl(c->z);
+    e = hipMemcpyAsync(fl.data(), c->flags, sizeof(int) * c->z, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "interior check"));
+    for (int k = 0; k < c->z; ++k)
+        if (fl[k] & (kNotInterior | kInfeasible))
+            return cleanup(fail(MHAR_E_NOT_INTERIOR, "start point of walk " + std::to_string(k) +
+                                                           " is not strictly interior"));
+    c->recomputes = 0;
+    p->live_chains += 1;
+    *out = c;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_step(mhar_chains_t c, int64_t steps, void* stream)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (steps < 0) return fail(MHAR_E_INVALID_ARG, "steps must be >= 0");
+    return run_steps(c, steps, 0, nullptr, 0, 0, (hipStream_t)stream);
+}
+
+mhar_status_t mhar_record(mhar_chains_t c, int64_t steps, int64_t stride, int64_t chain_count,
+                          double* out, void* stream)
+{
+    if (!c || !out) return fail(MHAR_E_INVALID_ARG, "chains and out must be non-NULL");
+    if (steps < 0 || stride < 1 || stride > (int64_t(1) << 30))
+        return fail(MHAR_E_INVALID_ARG, "need steps >= 0 and 1 <= stride <= 2^30");
+    if (chain_count < 1 || chain_count > c->z) return fail(MHAR_E_INVALID_ARG, "chain_count must be in [1, z]");
+    return run_steps(c, steps, 0, out, stride, chain_count, (hipStream_t)stream);
+}
+
+mhar_status_t mhar_get_state(mhar_chains_t c, double* X, int32_t* status, void* stream)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (X) MHAR_HIP(launch_export_states(c->p->n, c->p->lda, c->z, c->X, X, s), "state export");
+    if (status) MHAR_HIP(launch_export_flags(c->flags, c->z, status, 1, s), "status export");
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_set_state(mhar_chains_t c, const double* X, uint64_t step, void* stream)
+{
+    if (!c || !X) return fail(MHAR_E_INVALID_ARG, "chains and X must be non-NULL");
+    hipStream_t s = (hipStream_t)stream;
+    MHAR_HIP(launch_copy_states(c->p->n, c->p->lda, c->z, c->z_pad, X, c->X, s), "state import");
+    MHAR_HIP(launch_fill_i32(c->flags, c->z_pad, 0, s), "status reset");
+    MHAR_HIP(launch_fill_i32((int*)c->theta, (int64_t)c->z_pad * 2, 0, s), "theta reset");
+    c->step = step;
+    mhar_status_t st = run_steps(c, 0, 1, nullptr, 0, 0, s);
+    if (st) return st;
+    MHAR_HIP(launch_export_flags(c->flags, c->z_pad, c->flags, 1, s), "status reset");
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_get_step(mhar_chains_t c, uint64_t* step)
+{
+    if (!c || !step) return fail(MHAR_E_INVALID_ARG, "chains and step must be non-NULL");
+    *step = c->step;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_sync(mhar_chains_t c, void* stream, int32_t* any_flags)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int> fl(c->z);
+    MHAR_HIP(hipMemcpyAsync(fl.data(), c->flags, sizeof(int) * c->z, hipMemcpyDeviceToHost, s), "status read");
+    MHAR_HIP(hipStreamSynchronize(s), "stream synchronize");
+    int acc = 0;
+    for (int v : fl) acc |= v;
+    if (any_flags) *any_flags = acc & 15;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_get_stats(mhar_chains_t c, void* stream, mhar_stats_t* stats)
+{
+    if (!c || !stats) return fail(MHAR_E_INVALID_ARG, "chains and stats must be non-NULL");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long cnt[8];
+    MHAR_HIP(hipMemcpyAsync(cnt, c->counters, sizeof(cnt), hipMemcpyDeviceToHost, s), "counter read");
+    MHAR_HIP(hipStreamSynchronize(s), "stream synchronize");
+    stats->steps = c->step;
+    stats->chain_steps = c->step * (uint64_t)c->z;
+    stats->exact_rows = cnt[0];
+    stats->recomputes = c->recomputes;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_chains_destroy(mhar_chains_t c)
+{
+    if (!c) return MHAR_OK;
+    c->p->live_chains -= 1;
+    delete c;
+    return MHAR_OK;
+}
+
+}  // extern "C"

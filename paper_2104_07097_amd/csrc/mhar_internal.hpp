@@ -1,0 +1,101 @@
+// mhar_internal.hpp -- data layouts and kernel launchers shared by the host
+// runtime (mhar_api.cpp) and the kernels (mhar_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mhar {
+
+constexpr int kChainTile = 16;   // walks per workgroup (MFMA N)
+constexpr int kWaves = 8;        // waves per workgroup
+constexpr int kThreads = 64 * kWaves;
+constexpr int kRowGroup = 64;    // rows one wave handles per pass (4 MFMA row blocks)
+constexpr int kKAlign = 32;      // padded row length (K) granularity
+constexpr int kMaxN = 1152;      // LDS holds 16 padded FP64 rows of length <= kMaxN
+constexpr int kMaxMeq = 64;
+
+enum Prec { kFP64 = 0, kFP32 = 1, kBF16X3 = 2 };
+
+// per-walk status bits (same values as the public header)
+constexpr int kUnbounded = 1;
+constexpr int kDegenerate = 2;
+constexpr int kNonFinite = 4;
+constexpr int kInfeasible = 8;
+constexpr int kNotInterior = 16;  // internal: start point not strictly inside
+
+inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Slack / screening-product buffers are stored per chain tile in the order
+// the matrix cores produce them: for tile t, 16-row block q, output slot r
+// and lane l (group g = l/16, walk c = l%16), index ((t*Q + q)*4 + r)*64 + l,
+// Q = m_pad / 16.  The row of that entry is 16 q + out_row(g, r), which
+// depends on the product precision (FP64 orders the slots differently).
+
+struct StepArgs {
+    // problem
+    int n, m, m_pad, lda, m_eq;
+    const double* A64;      // m_pad x lda, zero padded
+    const float* A32;       // m_pad x lda (FP32 mode)
+    const __bf16* Ahi;      // m_pad x lda (BF16X3 mode)
+    const __bf16* Alo;
+    const double* b64;      // m_pad (padding rows: 1)
+    const float* rownorm;   // m_pad, ||a_i|| rounded up (padding rows: 0)
+    const float* absb;      // m_pad, |b_i| rounded up
+    const double* Aeq;      // m_eq x lda
+    const double* WT;       // m_eq x lda: rows of (A_eq A_eq^T)^{-1} A_eq
+    // chains
+    int z, z_pad;
+    double* X;              // z_pad x lda
+    double* D;              // z_pad x lda
+    void* S;                // slack, tile-fragment order, FP64 (FP64 mode) or FP32
+    void* G;                // last screening product, same order and type
+    float* L;               // per tile: (m_pad/64) x 2 x 16 lower bounds of the chord ratios
+    double* theta;          // z_pad, last theta
+    double* E;              // z_pad, slack drift coefficient
+    int* flags;             // z_pad
+    unsigned long long* counters;  // [0] exact rows evaluated
+    uint64_t seed;
+    uint32_t chain_offset;
+    uint64_t step0;
+    int steps;
+    int recompute_first;    // run the exact slack recompute before the first step
+    int pending0;           // a deferred slack update from the previous step is due
+    int T0;                 // rounding count of the slack since the last recompute
+    int since0;             // steps since the last recompute
+    int R;                  // recompute period
+    float eps_g;            // |G_hat - G| <= eps_g ||a|| ||d||
+    float u_s;              // unit roundoff of the slack storage
+    // recording
+    double* rec_out;
+    int rec_stride;
+    int rec_chains;
+    int64_t rec_s_base;
+};
+
+size_t step_lds_bytes(int prec, int lda);
+hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream);
+
+// one-time setup
+hipError_t launch_convert_problem(int prec, int n, int m, int m_pad, int lda, const double* A,
+                                  const double* b, double* A64, float* A32, __bf16* Ahi,
+                                  __bf16* Alo, double* b64, float* rownorm, float* absb,
+                                  hipStream_t stream);
+hipError_t launch_eq_setup(int n, int lda, int m_eq, const double* Aeq_in, const double* beq_in,
+                           double* Aeq, double* beq, double* WT, int* status,
+                           hipStream_t stream);
+hipError_t launch_dense_projection(int n, int lda, int m_eq, const double* Aeq, const double* WT,
+                                   double* P, hipStream_t stream);
+hipError_t launch_copy_states(int n, int lda, int z, int z_pad, const double* src_zn,
+                              double* X, hipStream_t stream);
+hipError_t launch_export_states(int n, int lda, int z, const double* X, double* dst_zn,
+                                hipStream_t stream);
+hipError_t launch_eq_residual(int n, int lda, int z, int m_eq, const double* Aeq,
+                              const double* beq, const double* X, int* flags,
+                              hipStream_t stream);
+hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t stream);
+hipError_t launch_export_flags(const int* flags, int z, int32_t* out, int clear_internal,
+                               hipStream_t stream);
+
+}  // namespace mhar

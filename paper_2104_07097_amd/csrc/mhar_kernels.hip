@@ -1,0 +1,859 @@
+// mhar_kernels.hip -- HIP kernels of the Matrix Hit-and-Run step for gfx950.
+//
+// One workgroup owns a tile of 16 walks and every constraint row, and runs
+// many steps per launch.  Per step (paper Alg. 2 with S4.3-S4.5):
+//   A. directions: Philox4x32-10 -> Box-Muller normals (S4.3), projection
+//      d = h - W (A_eq h) onto null(A_eq) (S3.2, factored form of P);
+//      written as FP64 rows and as the matrix-core operand tile in LDS;
+//   B. screening: G = A D on the matrix cores (FP64 / FP32 / BF16x3), fused
+//      with the deferred slack update s <- s - theta_prev G_prev and with
+//      interval bounds of every ratio s_i / g_i (S4.4, Lemma 4.2): a
+//      certified upper bound U of each chord end and, per 64-row group, the
+//      least lower bound L;
+//   D. exact chord: rows whose lower bound does not exceed U are the only
+//      rows that can attain the chord end; they are evaluated exactly in
+//      FP64 (s_i = b_i - a_i x, g_i = a_i d, sequential sums, no
+//      contraction), giving lambda_min / lambda_max; theta is drawn
+//      uniformly between them (S4.5) and x <- x + theta d;
+//   E. every R steps: exact FP64 recompute of the slack s = b - A X on the
+//      matrix cores, which also resets the drift bound.
+#include <math.h>
+
+#include "mhar_device.hpp"
+#include "mhar_internal.hpp"
+
+namespace mhar {
+
+namespace {
+
+constexpr float kInf = __builtin_huge_valf();
+constexpr double kInfD = __builtin_huge_val();
+constexpr float kLowShrink = 1.0f - 0x1.0p-20f;  // turns rounded lower bounds into safe ones
+constexpr float kHighGrow = 1.0f + 0x1.0p-20f;
+
+struct ChainLds {
+    double theta[kChainTile];
+    double E[kChainTile];
+    double dnorm[kChainTile];
+    double y[kChainTile * kMaxMeq];
+    unsigned up[kChainTile];
+    unsigned um[kChainTile];
+    int flags[kChainTile];
+    unsigned long long exact;
+};
+
+__host__ __device__ inline int x_ld(int lda) { return lda + 2; }     // FP64 LDS row stride
+__host__ __device__ inline int f32_ld(int lda) { return lda + 4; }   // FP32 LDS row stride
+__host__ __device__ inline int bf_ld(int lda) { return lda + 8; }    // bf16 LDS row stride
+
+__host__ __device__ inline size_t big_bytes(int lda)
+{
+    return (size_t)kChainTile * x_ld(lda) * sizeof(double);
+}
+
+// Interval bounds of the two chord-end ratios of one (row, walk) entry.
+//   s, g   : approximate slack and directional derivative
+//   dl     : bound on |s_hat - s|;  e: bound on |g_hat - g|
+// plus side (g > 0):   lo_p <= s/g <= hi_p   (hi_p finite only if g surely > 0)
+// minus side (g < 0):  lo_m <= s/(-g) <= hi_m
+__device__ __forceinline__ void ratio_bounds(float s, float g, float dl, float e, float& lo_p,
+                                             float& hi_p, float& lo_m, float& hi_m)
+{
+    float s_lo = fmaxf(s - dl, 0.0f);
+    float s_hi = s + dl;
+    float g_hi = g + e, g_lo = g - e;    // g in [g_lo, g_hi]
+    lo_p = (g_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(g_hi) * kLowShrink : kInf;
+    hi_p = (g_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(g_lo) * kHighGrow : kInf;
+    float n_hi = -g_lo, n_lo = -g_hi;    // -g in [n_lo, n_hi]
+    lo_m = (n_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(n_hi) * kLowShrink : kInf;
+    hi_m = (n_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(n_lo) * kHighGrow : kInf;
+}
+
+template <int P> struct Op;
+template <> struct Op<kFP64> {
+    typedef double state_t;
+    static constexpr bool f64 = true;
+};
+template <> struct Op<kFP32> {
+    typedef float state_t;
+    static constexpr bool f64 = false;
+};
+template <> struct Op<kBF16X3> {
+    typedef float state_t;
+    static constexpr bool f64 = false;
+};
+
+// index of (row, walk c) in a tile-fragment buffer for a product precision
+template <bool F64>
+__device__ __forceinline__ size_t frag_index(int tile, int Q, int row, int c)
+{
+    int q = row >> 4, w = row & 15;
+    int g = F64 ? (w & 3) : (w >> 2);
+    int r = F64 ? (w >> 2) : (w & 3);
+    return (((size_t)tile * Q + q) * 4 + r) * 64 + g * 16 + c;
+}
+
+// ---------------------------------------------------------------------------
+// Phase A: directions of the 16 walks of this tile at `step`.
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ void make_directions(const StepArgs& a, ChainLds* cs, unsigned char* big, int c0,
+                                uint64_t step)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = a.n, lda = a.lda;
+    const int npairs = (n + 1) >> 1;
+    for (int item = tid; item < kChainTile * npairs; item += kThreads) {
+        int cl = item / npairs, p = item - cl * npairs;
+        int chain = c0 + cl;
+        if (chain >= a.z) continue;
+        Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step,
+                                (uint32_t)p);
+        double ev, od;
+        gauss_pair(w, ev, od);
+        double* drow = a.D + (size_t)chain * lda;
+        drow[2 * p] = ev;
+        if (2 * p + 1 < n) drow[2 * p + 1] = od;
+    }
+    if (a.m_eq > 0) {
+        __syncthreads();
+        // y = A_eq h for every walk; one wave per (walk, equality row)
+        for (int pr = wave; pr < kChainTile * a.m_eq; pr += kWaves) {
+            int cl = pr / a.m_eq, p = pr - cl * a.m_eq;
+            int chain = c0 + cl;
+            double v = 0.0;
+            if (chain < a.z) {
+                const double* er = a.Aeq + (size_t)p * lda;
+                const double* hr = a.D + (size_t)chain * lda;
+                for (int j = lane; j < n; j += 64) v = fma(er[j], hr[j], v);
+            }
+            v = wave_sum(v);
+            if (lane == 0) cs->y[cl * kMaxMeq + p] = v;
+        }
+        __syncthreads();
+        // d = h - W y,  W^T rows = (A_eq A_eq^T)^{-1} A_eq
+        for (int item = tid; item < kChainTile * n; item += kThreads) {
+            int cl = item / n, j = item - cl * n;
+            int chain = c0 + cl;
+            if (chain >= a.z) continue;
+            double* dp = a.D + (size_t)chain * lda + j;
+            double v = *dp;
+            for (int p = 0; p < a.m_eq; ++p) v = fma(-a.WT[(size_t)p * lda + j], cs->y[cl * kMaxMeq + p], v);
+            *dp = v;
+        }
+    }
+    __syncthreads();
+    // norms of d (wave per walk)
+    for (int cl = wave; cl < kChainTile; cl += kWaves) {
+        int chain = c0 + cl;
+        double v = 0.0;
+        if (chain < a.z) {
+            const double* dr = a.D + (size_t)chain * lda;
+            for (int j = lane; j < n; j += 64) v = fma(dr[j], dr[j], v);
+        }
+        v = wave_sum(v);
+        if (lane == 0) cs->dnorm[cl] = sqrt(v);
+    }
+    // operand tile in LDS
+    if (P == kFP64) {
+        double* Dt = (double*)big;
+        const int ld = x_ld(lda);
+        for (int item = tid; item < kChainTile * lda; item += kThreads) {
+            int cl = item / lda, j = item - cl * lda;
+            int chain = c0 + cl;
+            Dt[cl * ld + j] = (chain < a.z && j < n) ? a.D[(size_t)chain * lda + j] : 0.0;
+        }
+    } else if (P == kFP32) {
+        float* Dt = (float*)big;
+        const int ld = f32_ld(lda);
+        for (int item = tid; item < kChainTile * lda; item += kThreads) {
+            int cl = item / lda, j = item - cl * lda;
+            int chain = c0 + cl;
+            Dt[cl * ld + j] = (chain < a.z && j < n) ? (float)a.D[(size_t)chain * lda + j] : 0.0f;
+        }
+    } else {
+        __bf16* Dh = (__bf16*)big;
+        const int ld = bf_ld(lda);
+        __bf16* Dl = Dh + kChainTile * ld;
+        for (int item = tid; item < kChainTile * lda; item += kThreads) {
+            int cl = item / lda, j = item - cl * lda;
+            int chain = c0 + cl;
+            float v = (chain < a.z && j < n) ? (float)a.D[(size_t)chain * lda + j] : 0.0f;
+            __bf16 hi, lo;
+            split_bf16(v, hi, lo);
+            Dh[cl * ld + j] = hi;
+            Dl[cl * ld + j] = lo;
+        }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Phase B: screening product and fused epilogue over all rows.
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int tile, int c0,
+                       int pending, int T)
+{
+    typedef typename Op<P>::state_t st_t;
+    constexpr bool F64 = Op<P>::f64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int lda = a.lda, Q = a.m_pad >> 4;
+    const int ngroups = a.m_pad / kRowGroup;
+    st_t* S = (st_t*)a.S;
+    st_t* Gb = (st_t*)a.G;
+    float* Lt = a.L + (size_t)tile * ngroups * 2 * kChainTile;
+
+    const bool active = (c0 + c) < a.z;
+    const float ed = active ? (float)(cs->dnorm[c] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+    const float Ek = (float)cs->E[c] * kHighGrow;
+    const st_t th = (st_t)cs->theta[c];
+    const float bscale = a.u_s * (float)T * kHighGrow;
+    float up = kInf, um = kInf;
+
+    for (int row0 = wave * kRowGroup; row0 < a.m_pad; row0 += kWaves * kRowGroup) {
+        float acc32[4][4];
+        double acc64[4][4];
+        if (P == kFP32) {
+            const float* Dt = (const float*)big;
+            const int ld = f32_ld(lda);
+            f32x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+            for (int k0 = 0; k0 < lda; k0 += 32) {
+                const float4* bp = (const float4*)(Dt + c * ld + k0 + 8 * g);
+                float4 b0 = bp[0], b1 = bp[1];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const float4* ap = (const float4*)(a.A32 + (size_t)(row0 + 16 * rb + c) * lda + k0 + 8 * g);
+                    float4 a0 = ap[0], a1 = ap[1];
+                    acc[rb] = mma_f32(a0.x, b0.x, acc[rb]);
+                    acc[rb] = mma_f32(a0.y, b0.y, acc[rb]);
+                    acc[rb] = mma_f32(a0.z, b0.z, acc[rb]);
+                    acc[rb] = mma_f32(a0.w, b0.w, acc[rb]);
+                    acc[rb] = mma_f32(a1.x, b1.x, acc[rb]);
+                    acc[rb] = mma_f32(a1.y, b1.y, acc[rb]);
+                    acc[rb] = mma_f32(a1.z, b1.z, acc[rb]);
+                    acc[rb] = mma_f32(a1.w, b1.w, acc[rb]);
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc32[rb][r] = acc[rb][r];
+        } else if (P == kBF16X3) {
+            const __bf16* Dh = (const __bf16*)big;
+            const int ld = bf_ld(lda);
+            const __bf16* Dl = Dh + kChainTile * ld;
+            f32x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+            for (int k0 = 0; k0 < lda; k0 += 32) {
+                bf16x8 bh = *(const bf16x8*)(Dh + c * ld + k0 + 8 * g);
+                bf16x8 bl = *(const bf16x8*)(Dl + c * ld + k0 + 8 * g);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    size_t off = (size_t)(row0 + 16 * rb + c) * lda + k0 + 8 * g;
+                    bf16x8 ah = *(const bf16x8*)(a.Ahi + off);
+                    bf16x8 al = *(const bf16x8*)(a.Alo + off);
+                    acc[rb] = mma_bf16(al, bh, acc[rb]);
+                    acc[rb] = mma_bf16(ah, bl, acc[rb]);
+                    acc[rb] = mma_bf16(ah, bh, acc[rb]);
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc32[rb][r] = acc[rb][r];
+        } else {
+            const double* Dt = (const double*)big;
+            const int ld = x_ld(lda);
+            f64x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+            for (int k0 = 0; k0 < lda; k0 += 16) {
+                const double2* bp = (const double2*)(Dt + c * ld + k0 + 4 * g);
+                double2 b0 = bp[0], b1 = bp[1];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const double2* ap = (const double2*)(a.A64 + (size_t)(row0 + 16 * rb + c) * lda + k0 + 4 * g);
+                    double2 a0 = ap[0], a1 = ap[1];
+                    acc[rb] = mma_f64(a0.x, b0.x, acc[rb]);
+                    acc[rb] = mma_f64(a0.y, b0.y, acc[rb]);
+                    acc[rb] = mma_f64(a1.x, b1.x, acc[rb]);
+                    acc[rb] = mma_f64(a1.y, b1.y, acc[rb]);
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[rb][r] = acc[rb][r];
+        }
+
+        float lp = kInf, lm = kInf;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int q = (row0 >> 4) + rb;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
+                const int row = 16 * q + out_row<F64>(g, r);
+                st_t gv = F64 ? (st_t)acc64[rb][r] : (st_t)acc32[rb][r];
+                st_t sv = S[idx];
+                if (pending) {
+                    sv = fma(-th, Gb[idx], sv);
+                    S[idx] = sv;
+                }
+                Gb[idx] = gv;
+                const float na = a.rownorm[row];
+                float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                float e = na * ed;
+                const float s32 = (float)sv, g32 = (float)gv;
+                if (F64) {
+                    dl = fmaf(fabsf(s32), 0x1.0p-23f, dl);
+                    e = fmaf(fabsf(g32), 0x1.0p-23f, e);
+                }
+                float lo_p, hi_p, lo_m, hi_m;
+                ratio_bounds(s32, g32, dl, e, lo_p, hi_p, lo_m, hi_m);
+                up = fminf(up, hi_p);
+                um = fminf(um, hi_m);
+                lp = fminf(lp, lo_p);
+                lm = fminf(lm, lo_m);
+            }
+        }
+        // per-group least lower bounds, one value per walk
+        lp = fminf(lp, __shfl_xor(lp, 16, 64));
+        lp = fminf(lp, __shfl_xor(lp, 32, 64));
+        lm = fminf(lm, __shfl_xor(lm, 16, 64));
+        lm = fminf(lm, __shfl_xor(lm, 32, 64));
+        if (g == 0) {
+            const int grp = row0 / kRowGroup;
+            Lt[(grp * 2 + 0) * kChainTile + c] = lp;
+            Lt[(grp * 2 + 1) * kChainTile + c] = lm;
+        }
+    }
+    up = fminf(up, __shfl_xor(up, 16, 64));
+    up = fminf(up, __shfl_xor(up, 32, 64));
+    um = fminf(um, __shfl_xor(um, 16, 64));
+    um = fminf(um, __shfl_xor(um, 32, 64));
+    if (g == 0) {
+        atomicMin(&cs->up[c], __float_as_uint(up));
+        atomicMin(&cs->um[c], __float_as_uint(um));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Phase D: exact chords of the candidate rows, theta, state update.
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, uint64_t step,
+                             int64_t s_rel, int T)
+{
+    typedef typename Op<P>::state_t st_t;
+    constexpr bool F64 = Op<P>::f64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = a.n, lda = a.lda, Q = a.m_pad >> 4;
+    const int ngroups = a.m_pad / kRowGroup;
+    const st_t* S = (const st_t*)a.S;
+    const st_t* Gb = (const st_t*)a.G;
+    const float* Lt = a.L + (size_t)tile * ngroups * 2 * kChainTile;
+    const float bscale = a.u_s * (float)T * kHighGrow;
+    const double u64 = 0x1.0p-53;
+
+    for (int cl = wave; cl < kChainTile; cl += kWaves) {
+        const int chain = c0 + cl;
+        if (chain >= a.z) {
+            if (lane == 0) cs->theta[cl] = 0.0;
+            continue;
+        }
+        const float up = __uint_as_float(cs->up[cl]);
+        const float um = __uint_as_float(cs->um[cl]);
+        const float ed = (float)(cs->dnorm[cl] * (double)a.eps_g) * kHighGrow + 1e-30f;
+        const float Ek = (float)cs->E[cl] * kHighGrow;
+        const double* xr = a.X + (size_t)chain * lda;
+        const double* dr = a.D + (size_t)chain * lda;
+        double lmax = kInfD, lmin = -kInfD;
+        int fl = 0;
+        unsigned long long nex = 0;
+        for (int qb = 0; qb < ngroups; qb += 64) {
+            const int q = qb + lane;
+            bool need = false;
+            if (q < ngroups)
+                need = (Lt[(q * 2 + 0) * kChainTile + cl] <= up) ||
+                       (Lt[(q * 2 + 1) * kChainTile + cl] <= um);
+            unsigned long long mask = __ballot(need);
+            while (mask) {
+                const int qq = qb + __ffsll((long long)mask) - 1;
+                mask &= mask - 1;
+                const int row = qq * kRowGroup + lane;
+                const size_t idx = frag_index<F64>(tile, Q, row, cl);
+                const float s32 = (float)S[idx], g32 = (float)Gb[idx];
+                const float na = a.rownorm[row];
+                float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                float e = na * ed;
+                if (F64) {
+                    dl = fmaf(fabsf(s32), 0x1.0p-23f, dl);
+                    e = fmaf(fabsf(g32), 0x1.0p-23f, e);
+                }
+                float lo_p, hi_p, lo_m, hi_m;
+                ratio_bounds(s32, g32, dl, e, lo_p, hi_p, lo_m, hi_m);
+                const bool cand = (row < a.m) && ((lo_p <= up) || (lo_m <= um));
+                nex += __popcll(__ballot(cand));
+                if (cand) {
+                    // the line-set formula of S4.4, in the operation order of a
+                    // sequential FP64 evaluation
+                    const double* ar = a.A64 + (size_t)row * lda;
+                    const double bi = a.b64[row];
+                    double s = bi;
+                    for (int j = 0; j < n; ++j) s = __dsub_rn(s, __dmul_rn(ar[j], xr[j]));
+                    double gg = 0.0;
+                    for (int j = 0; j < n; ++j) gg = __dadd_rn(gg, __dmul_rn(ar[j], dr[j]));
+                    if (s < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
+                    if (s < 0.0) s = 0.0;
+                    if (gg > 0.0) lmax = fmin(lmax, s / gg);
+                    else if (gg < 0.0) lmin = fmax(lmin, s / gg);
+                }
+            }
+        }
+        lmax = wave_min(lmax);
+        lmin = wave_max(lmin);
+        for (int o = 32; o > 0; o >>= 1) fl |= __shfl_xor(fl, o, 64);
+
+        double th = 0.0;
+        if (lmax == kInfD || lmin == -kInfD) {
+            fl |= kUnbounded;
+        } else if (!(lmax > lmin)) {
+            fl |= kDegenerate;
+        } else {
+            Block4 w = stream_block(a.seed, kTagTheta, a.chain_offset + (uint32_t)chain, step, 0);
+            double u = open_unit(w.w0, w.w1);
+            th = __dadd_rn(lmin, __dmul_rn(u, __dsub_rn(lmax, lmin)));
+        }
+        double xo = 0.0, xn2 = 0.0;
+        bool finite = isfinite(th);
+        double* xw = a.X + (size_t)chain * lda;
+        const bool rec = a.rec_stride > 0 && chain < a.rec_chains &&
+                         ((a.rec_s_base + s_rel + 1) % a.rec_stride) == 0;
+        double* rp = rec ? a.rec_out + ((size_t)((a.rec_s_base + s_rel + 1) / a.rec_stride - 1) *
+                                            a.rec_chains + chain) * n
+                         : nullptr;
+        for (int j = lane; j < n; j += 64) {
+            double xv = xw[j];
+            double xnew = __dadd_rn(xv, __dmul_rn(th, dr[j]));
+            xw[j] = xnew;
+            if (rec) rp[j] = xnew;
+            xo = fma(xv, xv, xo);
+            xn2 = fma(xnew, xnew, xn2);
+            finite = finite && isfinite(xnew);
+        }
+        xo = wave_sum(xo);
+        xn2 = wave_sum(xn2);
+        finite = __all(finite);
+        if (!finite) fl |= kNonFinite;
+        if (lane == 0) {
+            const double dn = cs->dnorm[cl], at = fabs(th);
+            const double us = (double)a.u_s;
+            double E = cs->E[cl];
+            E += at * dn * ((double)a.eps_g + 2.0 * us);
+            E += 2.0 * u64 * (sqrt(xo) + at * dn);
+            E += us * (1.0 + 0x1.0p-20) * sqrt(xn2);
+            cs->E[cl] = E;
+            cs->theta[cl] = th;
+            cs->flags[cl] |= fl;
+            cs->exact += nex;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Phase E: exact FP64 slack s = b - A X for the 16 walks (matrix cores).
+// ---------------------------------------------------------------------------
+template <int P>
+__device__ void recompute_slack(const StepArgs& a, ChainLds* cs, unsigned char* big, int tile,
+                                int c0)
+{
+    typedef typename Op<P>::state_t st_t;
+    constexpr bool F64 = Op<P>::f64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int n = a.n, lda = a.lda, Q = a.m_pad >> 4;
+    st_t* S = (st_t*)a.S;
+    double* Xt = (double*)big;
+    const int ld = x_ld(lda);
+    __syncthreads();
+    for (int item = tid; item < kChainTile * lda; item += kThreads) {
+        int cl = item / lda, j = item - cl * lda;
+        int chain = c0 + cl;
+        Xt[cl * ld + j] = (chain < a.z && j < n) ? a.X[(size_t)chain * lda + j] : 0.0;
+    }
+    __syncthreads();
+    // drift coefficient after an exact recompute
+    for (int cl = wave; cl < kChainTile; cl += kWaves) {
+        double v = 0.0;
+        for (int j = lane; j < n; j += 64) v = fma(Xt[cl * ld + j], Xt[cl * ld + j], v);
+        v = wave_sum(v);
+        if (lane == 0)
+            cs->E[cl] = ((double)a.u_s * (1.0 + 0x1.0p-20) + (2.0 * n + 4.0) * 0x1.0p-53) * sqrt(v);
+    }
+    const bool active = (c0 + c) < a.z;
+    int fl = 0;
+    for (int row0 = wave * kRowGroup; row0 < a.m_pad; row0 += kWaves * kRowGroup) {
+        f64x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+        for (int k0 = 0; k0 < lda; k0 += 16) {
+            const double2* bp = (const double2*)(Xt + c * ld + k0 + 4 * g);
+            double2 b0 = bp[0], b1 = bp[1];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const double2* ap = (const double2*)(a.A64 + (size_t)(row0 + 16 * rb + c) * lda + k0 + 4 * g);
+                double2 a0 = ap[0], a1 = ap[1];
+                acc[rb] = mma_f64(a0.x, b0.x, acc[rb]);
+                acc[rb] = mma_f64(a0.y, b0.y, acc[rb]);
+                acc[rb] = mma_f64(a1.x, b1.x, acc[rb]);
+                acc[rb] = mma_f64(a1.y, b1.y, acc[rb]);
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + 16 * rb + out_row<true>(g, r);
+                const double bi = a.b64[row];
+                const double s = bi - acc[rb][r];
+                if (active && row < a.m) {
+                    if (!(s > 0.0)) fl |= kNotInterior;
+                    if (s < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
+                }
+                S[frag_index<F64>(tile, Q, row, c)] = (st_t)s;
+            }
+        }
+    }
+    if (fl) atomicOr(&cs->flags[c], fl);
+    __syncthreads();
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void mhar_steps_kernel(StepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned char* big = smem;
+    ChainLds* cs = (ChainLds*)(smem + big_bytes(a.lda));
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x;
+    const int c0 = tile * kChainTile;
+
+    if (tid < kChainTile) {
+        const int chain = c0 + tid;
+        cs->theta[tid] = a.theta[chain];
+        cs->E[tid] = a.E[chain];
+        cs->flags[tid] = 0;
+    }
+    if (tid == 0) cs->exact = 0;
+    __syncthreads();
+
+    int pending = a.pending0, T = a.T0, since = a.since0;
+    if (a.recompute_first) {
+        recompute_slack<P>(a, cs, big, tile, c0);
+        pending = 0;
+        T = 2;
+        since = 0;
+    }
+    for (int s = 0; s < a.steps; ++s) {
+        const uint64_t step = a.step0 + (uint64_t)s;
+        if (tid < kChainTile) {
+            cs->up[tid] = __float_as_uint(kInf);
+            cs->um[tid] = __float_as_uint(kInf);
+        }
+        make_directions<P>(a, cs, big, c0, step);
+        screen<P>(a, cs, big, tile, c0, pending, T);
+        __syncthreads();
+        exact_chords<P>(a, cs, tile, c0, step, s, T);
+        __syncthreads();
+        pending = 1;
+        T += 1;
+        since += 1;
+        if (since >= a.R) {
+            recompute_slack<P>(a, cs, big, tile, c0);
+            pending = 0;
+            T = 2;
+            since = 0;
+        }
+    }
+    __syncthreads();
+    if (tid < kChainTile) {
+        const int chain = c0 + tid;
+        a.theta[chain] = cs->theta[tid];
+        a.E[chain] = cs->E[tid];
+        if (cs->flags[tid] && chain < a.z) atomicOr(&a.flags[chain], cs->flags[tid]);
+    }
+    if (tid == 0 && cs->exact) atomicAdd(&a.counters[0], cs->exact);
+}
+
+// ---------------------------------------------------------------------------
+// One-time setup kernels
+// ---------------------------------------------------------------------------
+
+// FP64 copy with padding, operand form, row norms and |b| (both rounded up).
+__global__ void convert_problem_kernel(int prec, int n, int m, int m_pad, int lda,
+                                       const double* __restrict__ A, const double* __restrict__ b,
+                                       double* A64, float* A32, __bf16* Ahi, __bf16* Alo,
+                                       double* b64, float* rownorm, float* absb)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (row >= m_pad) return;
+    const bool real = row < m;
+    double ss = 0.0;
+    for (int j = lane; j < lda; j += 64) {
+        double v = (real && j < n) ? A[(size_t)row * n + j] : 0.0;
+        A64[(size_t)row * lda + j] = v;
+        if (prec == kFP32) A32[(size_t)row * lda + j] = (float)v;
+        if (prec == kBF16X3) {
+            __bf16 hi, lo;
+            split_bf16((float)v, hi, lo);
+            Ahi[(size_t)row * lda + j] = hi;
+            Alo[(size_t)row * lda + j] = lo;
+        }
+        ss = fma(v, v, ss);
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) {
+        double bv = real ? b[row] : 1.0;
+        b64[row] = bv;
+        rownorm[row] = real ? (float)(sqrt(ss) * (1.0 + 0x1.0p-20)) : 0.0f;
+        absb[row] = (float)(fabs(bv) * (1.0 + 0x1.0p-20));
+    }
+}
+
+// Equality setup in one workgroup: G = A_eq A_eq^T, Cholesky G = L L^T
+// (pivot <= 1e-12 max diag G: rank deficient), W^T = G^{-1} A_eq.
+__global__ void eq_setup_kernel(int n, int lda, int m_eq, const double* __restrict__ Aeq_in,
+                                const double* __restrict__ beq_in, double* Aeq, double* beq,
+                                double* WT, int* status)
+{
+    __shared__ double Gs[kMaxMeq * kMaxMeq];
+    __shared__ int bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int item = tid; item < m_eq * lda; item += nt) {
+        int p = item / lda, j = item - p * lda;
+        Aeq[item] = j < n ? Aeq_in[(size_t)p * n + j] : 0.0;
+    }
+    for (int p = tid; p < m_eq; p += nt) beq[p] = beq_in[p];
+    __syncthreads();
+    for (int pq = tid; pq < m_eq * m_eq; pq += nt) {
+        int p = pq / m_eq, q = pq - p * m_eq;
+        double v = 0.0;
+        for (int j = 0; j < n; ++j) v = fma(Aeq[(size_t)p * lda + j], Aeq[(size_t)q * lda + j], v);
+        Gs[pq] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double md = 0.0;
+        for (int i = 0; i < m_eq; ++i) md = fmax(md, Gs[i * m_eq + i]);
+        bad = 0;
+        for (int j = 0; j < m_eq && !bad; ++j) {
+            double piv = Gs[j * m_eq + j];
+            for (int k = 0; k < j; ++k) piv -= Gs[j * m_eq + k] * Gs[j * m_eq + k];
+            if (!(piv > 1e-12 * md)) {
+                bad = 1;
+                break;
+            }
+            double ljj = sqrt(piv);
+            Gs[j * m_eq + j] = ljj;
+            for (int i = j + 1; i < m_eq; ++i) {
+                double v = Gs[i * m_eq + j];
+                for (int k = 0; k < j; ++k) v -= Gs[i * m_eq + k] * Gs[j * m_eq + k];
+                Gs[i * m_eq + j] = v / ljj;
+            }
+        }
+        *status = bad;
+    }
+    __syncthreads();
+    if (bad) return;
+    double y[kMaxMeq];
+    for (int j = tid; j < lda; j += nt) {
+        for (int p = 0; p < m_eq; ++p) y[p] = Aeq[(size_t)p * lda + j];
+        for (int i = 0; i < m_eq; ++i) {
+            double v = y[i];
+            for (int k = 0; k < i; ++k) v -= Gs[i * m_eq + k] * y[k];
+            y[i] = v / Gs[i * m_eq + i];
+        }
+        for (int i = m_eq - 1; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < m_eq; ++k) v -= Gs[k * m_eq + i] * y[k];
+            y[i] = v / Gs[i * m_eq + i];
+        }
+        for (int p = 0; p < m_eq; ++p) WT[(size_t)p * lda + j] = y[p];
+    }
+}
+
+__global__ void dense_projection_kernel(int n, int lda, int m_eq, const double* __restrict__ Aeq,
+                                        const double* __restrict__ WT, double* P)
+{
+    const int64_t total = (int64_t)n * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        double v = 0.0;
+        for (int p = 0; p < m_eq; ++p) v = fma(WT[(size_t)p * lda + i], Aeq[(size_t)p * lda + j], v);
+        P[e] = (i == j ? 1.0 : 0.0) - v;
+    }
+}
+
+__global__ void copy_states_kernel(int n, int lda, int z, int z_pad, const double* __restrict__ src,
+                                   double* X)
+{
+    const int64_t total = (int64_t)z_pad * lda;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int k = (int)(e / lda), j = (int)(e - (int64_t)k * lda);
+        X[e] = (k < z && j < n) ? src[(size_t)k * n + j] : 0.0;
+    }
+}
+
+__global__ void export_states_kernel(int n, int lda, int z, const double* __restrict__ X, double* dst)
+{
+    const int64_t total = (int64_t)z * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int k = (int)(e / n), j = (int)(e - (int64_t)k * n);
+        dst[e] = X[(size_t)k * lda + j];
+    }
+}
+
+__global__ void eq_residual_kernel(int n, int lda, int z, int m_eq, const double* __restrict__ Aeq,
+                                   const double* __restrict__ beq, const double* __restrict__ X,
+                                   int* flags)
+{
+    const int lane = threadIdx.x & 63;
+    const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (k >= z) return;
+    int bad = 0;
+    for (int p = 0; p < m_eq; ++p) {
+        double v = 0.0;
+        for (int j = lane; j < n; j += 64) v = fma(Aeq[(size_t)p * lda + j], X[(size_t)k * lda + j], v);
+        v = wave_sum(v);
+        if (!(fabs(v - beq[p]) <= 1e-9)) bad = 1;
+    }
+    if (lane == 0 && bad) atomicOr(&flags[k], kNotInterior);
+}
+
+__global__ void fill_i32_kernel(int* p, int64_t count, int value)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = value;
+}
+
+__global__ void export_flags_kernel(const int* flags, int z, int32_t* out, int clear_internal)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < z; k += gridDim.x * blockDim.x) {
+        int v = flags[k];
+        out[k] = clear_internal ? (v & 15) : v;
+    }
+}
+
+inline int grid_for(int64_t total, int threads)
+{
+    int64_t g = (total + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > 65535) g = 65535;
+    return (int)g;
+}
+
+}  // namespace
+
+size_t step_lds_bytes(int prec, int lda)
+{
+    (void)prec;
+    return big_bytes(lda) + sizeof(ChainLds);
+}
+
+template <int P>
+static hipError_t launch_steps_t(const StepArgs& a, hipStream_t stream)
+{
+    const size_t lds = step_lds_bytes(P, a.lda);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)mhar_steps_kernel<P>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(mhar_steps_kernel<P>, dim3(a.z_pad / kChainTile), dim3(kThreads), lds,
+                       stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream)
+{
+    switch (prec) {
+    case kFP64: return launch_steps_t<kFP64>(a, stream);
+    case kFP32: return launch_steps_t<kFP32>(a, stream);
+    case kBF16X3: return launch_steps_t<kBF16X3>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_convert_problem(int prec, int n, int m, int m_pad, int lda, const double* A,
+                                  const double* b, double* A64, float* A32, __bf16* Ahi,
+                                  __bf16* Alo, double* b64, float* rownorm, float* absb,
+                                  hipStream_t stream)
+{
+    const int rows_per_block = 4;
+    hipLaunchKernelGGL(convert_problem_kernel, dim3((m_pad + rows_per_block - 1) / rows_per_block),
+                       dim3(64 * rows_per_block), 0, stream, prec, n, m, m_pad, lda, A, b, A64, A32,
+                       Ahi, Alo, b64, rownorm, absb);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq_setup(int n, int lda, int m_eq, const double* Aeq_in, const double* beq_in,
+                           double* Aeq, double* beq, double* WT, int* status, hipStream_t stream)
+{
+    hipLaunchKernelGGL(eq_setup_kernel, dim3(1), dim3(256), 0, stream, n, lda, m_eq, Aeq_in,
+                       beq_in, Aeq, beq, WT, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_projection(int n, int lda, int m_eq, const double* Aeq, const double* WT,
+                                   double* P, hipStream_t stream)
+{
+    hipLaunchKernelGGL(dense_projection_kernel, dim3(grid_for((int64_t)n * n, 256)), dim3(256), 0,
+                       stream, n, lda, m_eq, Aeq, WT, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_states(int n, int lda, int z, int z_pad, const double* src, double* X,
+                              hipStream_t stream)
+{
+    hipLaunchKernelGGL(copy_states_kernel, dim3(grid_for((int64_t)z_pad * lda, 256)), dim3(256),
+                       0, stream, n, lda, z, z_pad, src, X);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_states(int n, int lda, int z, const double* X, double* dst,
+                                hipStream_t stream)
+{
+    hipLaunchKernelGGL(export_states_kernel, dim3(grid_for((int64_t)z * n, 256)), dim3(256), 0,
+                       stream, n, lda, z, X, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_eq_residual(int n, int lda, int z, int m_eq, const double* Aeq,
+                              const double* beq, const double* X, int* flags, hipStream_t stream)
+{
+    hipLaunchKernelGGL(eq_residual_kernel, dim3((z + 3) / 4), dim3(256), 0, stream, n, lda, z,
+                       m_eq, Aeq, beq, X, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t stream)
+{
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, stream, p,
+                       count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_flags(const int* flags, int z, int32_t* out, int clear_internal,
+                               hipStream_t stream)
+{
+    hipLaunchKernelGGL(export_flags_kernel, dim3(grid_for(z, 256)), dim3(256), 0, stream, flags,
+                       z, out, clear_internal);
+    return hipGetLastError();
+}
+
+}  // namespace mhar

@@ -1,0 +1,263 @@
+"""Python binding of libmhar (include/mhar.h): argument marshalling only.
+
+Every step of the sampler runs in the HIP library.  The functions named
+``mhar_*`` mirror the C entry points one to one (plain integers and device
+pointers); ``Problem`` and ``Chains`` are thin conveniences that take torch
+tensors on a HIP device, allocate the device workspaces with torch and pass
+the current torch stream.  There is no fallback: if the library is missing
+and cannot be built, importing the binding fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import build as _build
+
+OK = 0
+E_INVALID_ARG = -1
+E_SHAPE = -2
+E_RANK_DEFICIENT = -3
+E_NOT_INTERIOR = -4
+E_WORKSPACE = -5
+E_HIP = -6
+E_UNSUPPORTED = -7
+E_STATE = -8
+
+FP64 = 0
+FP32 = 1
+BF16X3 = 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+CHAIN_UNBOUNDED = 1
+CHAIN_DEGENERATE = 2
+CHAIN_NONFINITE = 4
+CHAIN_INFEASIBLE = 8
+
+
+class MharError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("recompute_every", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_uint64), ("chain_steps", ctypes.c_uint64),
+                ("exact_rows", ctypes.c_uint64), ("recomputes", ctypes.c_uint64)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_st = ctypes.c_int32
+
+# name -> (restype, argtypes), exactly the declarations of include/mhar.h
+SIGNATURES = {
+    "mhar_version": (ctypes.c_int32, []),
+    "mhar_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "mhar_last_error": (ctypes.c_char_p, []),
+    "mhar_options_default": (_st, [ctypes.POINTER(Options)]),
+    "mhar_problem_workspace_size": (_st, [_i64, _i64, _i64, ctypes.POINTER(Options),
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "mhar_problem_create": (_st, [_i64, _i64, _vp, _vp, _i64, _vp, _vp, ctypes.POINTER(Options),
+                                  _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]),
+    "mhar_problem_get_projection": (_st, [_vp, _vp, _vp]),
+    "mhar_problem_destroy": (_st, [_vp]),
+    "mhar_chains_workspace_size": (_st, [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)]),
+    "mhar_chains_create": (_st, [_vp, _i64, _vp, _u64, _u64, _vp, ctypes.c_size_t, _vp,
+                                 ctypes.POINTER(_vp)]),
+    "mhar_step": (_st, [_vp, _i64, _vp]),
+    "mhar_record": (_st, [_vp, _i64, _i64, _i64, _vp, _vp]),
+    "mhar_get_state": (_st, [_vp, _vp, _vp, _vp]),
+    "mhar_set_state": (_st, [_vp, _vp, _u64, _vp]),
+    "mhar_get_step": (_st, [_vp, ctypes.POINTER(_u64)]),
+    "mhar_sync": (_st, [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]),
+    "mhar_get_stats": (_st, [_vp, _vp, ctypes.POINTER(Stats)]),
+    "mhar_chains_destroy": (_st, [_vp]),
+}
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load(path: str | None = None):
+    """Load libmhar (building it first only if no built library exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _build.LIB
+    if not os.path.exists(p):
+        _build.build(p)
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != OK:
+        lib = load()
+        raise MharError(code, lib.mhar_last_error().decode() or lib.mhar_status_string(code).decode())
+
+
+def _make_module_functions():
+    # module-level functions with the C names (marshalling only)
+    def make(name):
+        def f(*args):
+            return getattr(load(), name)(*args)
+        f.__name__ = name
+        f.__doc__ = f"Calls {name} of libmhar (see include/mhar.h)."
+        return f
+    return {name: make(name) for name in SIGNATURES}
+
+
+globals().update(_make_module_functions())
+
+
+def options(precision="fp32", recompute_every=50, steps_per_launch=0) -> Options:
+    o = Options()
+    _check(load().mhar_options_default(ctypes.byref(o)))
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.recompute_every = int(recompute_every)
+    o.steps_per_launch = int(steps_per_launch)
+    return o
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(torch, nbytes, device):
+    buf = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off, int(nbytes)
+
+
+class Problem:
+    """{x : A x <= b, A_eq x = b_eq} set up on the device (mhar_problem_create)."""
+
+    def __init__(self, A, b, A_eq=None, b_eq=None, precision="fp32", recompute_every=50,
+                 steps_per_launch=0):
+        import torch
+        self.torch = torch
+        lib = load()
+        self.device = A.device
+        A = A.to(torch.float64).contiguous()
+        b = b.to(torch.float64).contiguous()
+        m, n = A.shape
+        m_eq = 0
+        if A_eq is not None:
+            A_eq = A_eq.to(device=self.device, dtype=torch.float64).contiguous()
+            b_eq = b_eq.to(device=self.device, dtype=torch.float64).contiguous()
+            m_eq = A_eq.shape[0]
+        self.n, self.m, self.m_eq = n, m, m_eq
+        self.opt = options(precision, recompute_every, steps_per_launch)
+        sz = ctypes.c_size_t()
+        _check(lib.mhar_problem_workspace_size(n, m, m_eq, ctypes.byref(self.opt), ctypes.byref(sz)))
+        self._ws, ptr, nbytes = _workspace(torch, sz.value, self.device)
+        h = ctypes.c_void_p()
+        _check(lib.mhar_problem_create(n, m, A.data_ptr(), b.data_ptr(), m_eq,
+                                       A_eq.data_ptr() if m_eq else None,
+                                       b_eq.data_ptr() if m_eq else None, ctypes.byref(self.opt),
+                                       ptr, nbytes, _stream(torch, self.device), ctypes.byref(h)))
+        self.handle = h
+
+    def projection(self):
+        P = self.torch.empty((self.n, self.n), dtype=self.torch.float64, device=self.device)
+        _check(load().mhar_problem_get_projection(self.handle, P.data_ptr(),
+                                                   _stream(self.torch, self.device)))
+        return P
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().mhar_problem_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Chains:
+    """z walks on a Problem (mhar_chains_create and the per-step calls)."""
+
+    def __init__(self, problem: Problem, X0, seed=0, chain_offset=0):
+        torch = problem.torch
+        self.torch = torch
+        self.problem = problem
+        lib = load()
+        X0 = X0.to(device=problem.device, dtype=torch.float64).contiguous()
+        self.z = X0.shape[0]
+        sz = ctypes.c_size_t()
+        _check(lib.mhar_chains_workspace_size(problem.handle, self.z, ctypes.byref(sz)))
+        self._ws, ptr, nbytes = _workspace(torch, sz.value, problem.device)
+        h = ctypes.c_void_p()
+        _check(lib.mhar_chains_create(problem.handle, self.z, X0.data_ptr(), seed, chain_offset, ptr,
+                                      nbytes, _stream(torch, problem.device), ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def stream(self):
+        return _stream(self.torch, self.problem.device)
+
+    def step(self, steps: int):
+        _check(load().mhar_step(self.handle, int(steps), self.stream))
+
+    def record(self, steps: int, stride: int, chain_count: int):
+        out = self.torch.empty((int(steps) // int(stride), int(chain_count), self.problem.n),
+                               dtype=self.torch.float64, device=self.problem.device)
+        _check(load().mhar_record(self.handle, int(steps), int(stride), int(chain_count),
+                                  out.data_ptr(), self.stream))
+        return out
+
+    def state(self):
+        X = self.torch.empty((self.z, self.problem.n), dtype=self.torch.float64,
+                             device=self.problem.device)
+        st = self.torch.empty(self.z, dtype=self.torch.int32, device=self.problem.device)
+        _check(load().mhar_get_state(self.handle, X.data_ptr(), st.data_ptr(), self.stream))
+        return X, st
+
+    def set_state(self, X, step: int):
+        X = X.to(device=self.problem.device, dtype=self.torch.float64).contiguous()
+        _check(load().mhar_set_state(self.handle, X.data_ptr(), int(step), self.stream))
+        self._keep = X
+
+    def step_count(self) -> int:
+        v = ctypes.c_uint64()
+        _check(load().mhar_get_step(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def sync(self) -> int:
+        f = ctypes.c_int32()
+        _check(load().mhar_sync(self.handle, self.stream, ctypes.byref(f)))
+        return f.value
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(load().mhar_get_stats(self.handle, self.stream, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().mhar_chains_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

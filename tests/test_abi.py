@@ -1,0 +1,74 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point that
+include/mhar.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2104_07097_amd import mhar
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "mhar.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mhar_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = mhar.load()
+    names = _declared_functions()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_the_header():
+    assert set(_declared_functions()) == set(mhar.SIGNATURES)
+
+
+def test_options_and_strings():
+    o = mhar.options("bf16x3", 7, 3)
+    assert (o.precision, o.recompute_every, o.steps_per_launch) == (mhar.BF16X3, 7, 3)
+    lib = mhar.load()
+    assert lib.mhar_version() >= 100
+    assert lib.mhar_status_string(mhar.E_NOT_INTERIOR).decode() == "start point not strictly interior"
+
+
+@pytest.mark.parametrize("n,m,m_eq,code", [(0, 10, 0, mhar.E_SHAPE), (5, 0, 0, mhar.E_SHAPE),
+                                           (2000, 10, 0, mhar.E_SHAPE), (5, 10, 5, mhar.E_SHAPE),
+                                           (100, 10, 65, mhar.E_SHAPE)])
+def test_workspace_size_rejects_bad_shapes(n, m, m_eq, code):
+    lib = mhar.load()
+    o = mhar.options()
+    sz = ctypes.c_size_t()
+    assert lib.mhar_problem_workspace_size(n, m, m_eq, ctypes.byref(o), ctypes.byref(sz)) == code
+    assert lib.mhar_last_error().decode()
+
+
+def test_workspace_size_and_bad_options():
+    lib = mhar.load()
+    sz = ctypes.c_size_t()
+    assert lib.mhar_problem_workspace_size(100, 2000, 0, None, ctypes.byref(sz)) == mhar.OK
+    # FP32 default: FP64 + FP32 copies of the padded A dominate
+    assert sz.value >= 2048 * 128 * 12
+    o = mhar.options()
+    o.recompute_every = 0
+    assert lib.mhar_problem_workspace_size(10, 20, 0, ctypes.byref(o), ctypes.byref(sz)) == mhar.E_INVALID_ARG
+    o = mhar.options()
+    o.precision = 9
+    assert lib.mhar_problem_workspace_size(10, 20, 0, ctypes.byref(o), ctypes.byref(sz)) == mhar.E_INVALID_ARG
+
+
+def test_create_rejects_null_and_misaligned():
+    lib = mhar.load()
+    h = ctypes.c_void_p()
+    assert lib.mhar_problem_create(10, 20, None, None, 0, None, None, None, None, 0, None,
+                                   ctypes.byref(h)) == mhar.E_INVALID_ARG
+    # misaligned workspace pointer is refused before any device work
+    assert lib.mhar_problem_create(10, 20, 256, 512, 0, None, None, None, 1025, 1 << 20, None,
+                                   ctypes.byref(h)) == mhar.E_WORKSPACE
+    assert lib.mhar_step(None, 1, None) == mhar.E_INVALID_ARG
+    assert lib.mhar_chains_destroy(None) == mhar.OK
