@@ -27,6 +27,7 @@ struct mhar_problem {
 struct mhar_chains {
     mhar_problem* p;
     int z, z_pad;
+    int split;  // > 0: register-resident kernel with this many workgroups per walk tile
     uint64_t seed;
     uint32_t chain_offset;
     uint64_t step;
@@ -37,6 +38,10 @@ struct mhar_chains {
     float* L;
     int* flags;
     unsigned long long* counters;
+    float* gU;
+    unsigned long long* gL;
+    unsigned* gbar;
+    int* gerr;
 };
 
 namespace {
@@ -148,6 +153,11 @@ size_t carve_chains(const mhar_problem* p, int z_pad, void* ws, mhar_chains* ch)
     q->E = c.take<double>(z_pad);
     q->flags = c.take<int>(z_pad);
     q->counters = c.take<unsigned long long>(8);
+    const size_t tiles = (size_t)z_pad / kChainTile;
+    q->gU = c.take<float>(tiles * 3 * 2 * kChainTile);
+    q->gL = c.take<unsigned long long>(tiles * 3 * 2 * kChainTile);
+    q->gbar = c.take<unsigned>(tiles);
+    q->gerr = c.take<int>(64);
     return c.used;
 }
 
@@ -217,6 +227,11 @@ StepArgs make_args(const mhar_chains* c)
     a.R = p->R;
     a.eps_g = p->eps_g;
     a.u_s = p->u_s;
+    a.split = c->split > 0 ? c->split : 1;
+    a.gU = c->gU;
+    a.gL = c->gL;
+    a.gbar = c->gbar;
+    a.gerr = c->gerr;
     return a;
 }
 
@@ -225,6 +240,21 @@ int64_t auto_chunk(const mhar_problem* p)
     int64_t work = (int64_t)p->m_pad * p->lda;
     int64_t chunk = (int64_t(1) << 29) / std::max<int64_t>(work, 1);
     return std::min<int64_t>(std::max<int64_t>(chunk, 1), 100000);
+}
+
+hipError_t launch_any(const mhar_chains* c, const StepArgs& a, hipStream_t stream)
+{
+    if (c->split <= 0) return launch_steps(c->p->prec, a, stream);
+    if (c->split > 1) {
+        // fresh exchange slots and arrival counters for this launch
+        const int64_t tiles = c->z_pad / kChainTile;
+        hipError_t e = launch_fill_i32((int*)c->gU, tiles * 3 * 2 * kChainTile, 0x7f800000, stream);
+        if (e == hipSuccess)
+            e = launch_fill_u64(c->gL, tiles * 3 * 2 * kChainTile, 0x7FF0000000000000ull, stream);
+        if (e == hipSuccess) e = launch_fill_i32((int*)c->gbar, tiles, 0, stream);
+        if (e != hipSuccess) return e;
+    }
+    return launch_resident(c->p->prec, a, stream);
 }
 
 // run `steps` steps (and the optional leading recompute), in launches of at
@@ -239,7 +269,7 @@ mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, doub
         StepArgs a = make_args(c);
         a.steps = 0;
         a.recompute_first = 1;
-        MHAR_HIP(launch_steps(p->prec, a, stream), "launch of the step kernel");
+        MHAR_HIP(launch_any(c, a, stream), "launch of the step kernel");
         c->pending = 0;
         c->T = 2;
         c->since = 0;
@@ -256,7 +286,7 @@ mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, doub
             a.rec_chains = (int)rec_chains;
             a.rec_s_base = done;
         }
-        MHAR_HIP(launch_steps(p->prec, a, stream), "launch of the step kernel");
+        MHAR_HIP(launch_any(c, a, stream), "launch of the step kernel");
         advance_schedule(c, k);
         done += k;
     }
@@ -424,6 +454,7 @@ mhar_status_t mhar_chains_create(mhar_problem_t p, int64_t z, const double* X0, 
     c->seed = seed;
     c->chain_offset = (uint32_t)chain_offset;
     carve_chains(p, z_pad, workspace, c);
+    c->split = resident_split(p->prec, p->lda, p->m_pad, z_pad);
     auto cleanup = [&](mhar_status_t code) {
         delete c;
         return code;
@@ -432,6 +463,7 @@ mhar_status_t mhar_chains_create(mhar_problem_t p, int64_t z, const double* X0, 
     if (e == hipSuccess) e = launch_fill_i32((int*)c->E, (int64_t)z_pad * 2, 0, stream);
     if (e == hipSuccess) e = launch_fill_i32(c->flags, z_pad, 0, stream);
     if (e == hipSuccess) e = launch_fill_i32((int*)c->counters, 16, 0, stream);
+    if (e == hipSuccess) e = launch_fill_i32(c->gerr, 64, 0, stream);
     if (e == hipSuccess) e = launch_fill_i32((int*)c->D, (int64_t)z_pad * p->lda * 2, 0, stream);
     if (e == hipSuccess) e = launch_copy_states(p->n, p->lda, c->z, z_pad, X0, c->X, stream);
     if (e == hipSuccess && p->m_eq > 0)
@@ -505,8 +537,11 @@ mhar_status_t mhar_sync(mhar_chains_t c, void* stream, int32_t* any_flags)
     if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
     hipStream_t s = (hipStream_t)stream;
     std::vector<int> fl(c->z);
+    int gerr = 0;
     MHAR_HIP(hipMemcpyAsync(fl.data(), c->flags, sizeof(int) * c->z, hipMemcpyDeviceToHost, s), "status read");
+    MHAR_HIP(hipMemcpyAsync(&gerr, c->gerr, sizeof(int), hipMemcpyDeviceToHost, s), "status read");
     MHAR_HIP(hipStreamSynchronize(s), "stream synchronize");
+    if (gerr) return fail(MHAR_E_HIP, "a workgroup group wait timed out; the states are not valid");
     int acc = 0;
     for (int v : fl) acc |= v;
     if (any_flags) *any_flags = acc & 15;

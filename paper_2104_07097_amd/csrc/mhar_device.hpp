@@ -130,4 +130,27 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+constexpr float kInf = __builtin_huge_valf();
+constexpr double kInfD = __builtin_huge_val();
+constexpr float kLowShrink = 1.0f - 0x1.0p-20f;  // turns rounded lower bounds into safe ones
+constexpr float kHighGrow = 1.0f + 0x1.0p-20f;
+
+// Interval bounds of the two chord-end ratios of one (row, walk) entry.
+//   s, g   : approximate slack and directional derivative
+//   dl     : bound on |s_hat - s|;  e: bound on |g_hat - g|
+// plus side (g > 0):   lo_p <= s/g <= hi_p   (hi_p finite only if g surely > 0)
+// minus side (g < 0):  lo_m <= s/(-g) <= hi_m
+__device__ __forceinline__ void ratio_bounds(float s, float g, float dl, float e, float& lo_p,
+                                             float& hi_p, float& lo_m, float& hi_m)
+{
+    float s_lo = fmaxf(s - dl, 0.0f);
+    float s_hi = s + dl;
+    float g_hi = g + e, g_lo = g - e;    // g in [g_lo, g_hi]
+    lo_p = (g_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(g_hi) * kLowShrink : kInf;
+    hi_p = (g_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(g_lo) * kHighGrow : kInf;
+    float n_hi = -g_lo, n_lo = -g_hi;    // -g in [n_lo, n_hi]
+    lo_m = (n_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(n_hi) * kLowShrink : kInf;
+    hi_m = (n_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(n_lo) * kHighGrow : kInf;
+}
+
 }  // namespace mhar

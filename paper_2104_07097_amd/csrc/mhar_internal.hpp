@@ -67,6 +67,13 @@ struct StepArgs {
     int R;                  // recompute period
     float eps_g;            // |G_hat - G| <= eps_g ||a|| ||d||
     float u_s;              // unit roundoff of the slack storage
+    // row split of the resident kernel (workgroups per walk tile) and the
+    // device-scope exchange buffers of a split launch
+    int split;
+    float* gU;                     // per tile: 3 slots x 2 x 16 bound bits
+    unsigned long long* gL;        // per tile: 3 slots x 2 x 16 exact chord-end bits
+    unsigned* gbar;                // per tile: arrival counter
+    int* gerr;                     // set when a group wait timed out
     // recording
     double* rec_out;
     int rec_stride;
@@ -75,6 +82,10 @@ struct StepArgs {
 };
 
 size_t step_lds_bytes(int prec, int lda);
+// register-resident kernel for small problems (FP32 / BF16X3, lda <= 256,
+// m_pad <= 16 x 512): number of workgroups per walk tile, 0 = not usable
+int resident_split(int prec, int lda, int m_pad, int z_pad);
+hipError_t launch_resident(int prec, const StepArgs& a, hipStream_t stream);
 hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream);
 
 // one-time setup
@@ -95,6 +106,8 @@ hipError_t launch_eq_residual(int n, int lda, int z, int m_eq, const double* Aeq
                               const double* beq, const double* X, int* flags,
                               hipStream_t stream);
 hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t stream);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long value,
+                           hipStream_t stream);
 hipError_t launch_export_flags(const int* flags, int z, int32_t* out, int clear_internal,
                                hipStream_t stream);
 

@@ -26,11 +26,6 @@ namespace mhar {
 
 namespace {
 
-constexpr float kInf = __builtin_huge_valf();
-constexpr double kInfD = __builtin_huge_val();
-constexpr float kLowShrink = 1.0f - 0x1.0p-20f;  // turns rounded lower bounds into safe ones
-constexpr float kHighGrow = 1.0f + 0x1.0p-20f;
-
 struct ChainLds {
     double theta[kChainTile];
     double E[kChainTile];
@@ -49,24 +44,6 @@ __host__ __device__ inline int bf_ld(int lda) { return lda + 8; }    // bf16 LDS
 __host__ __device__ inline size_t big_bytes(int lda)
 {
     return (size_t)kChainTile * x_ld(lda) * sizeof(double);
-}
-
-// Interval bounds of the two chord-end ratios of one (row, walk) entry.
-//   s, g   : approximate slack and directional derivative
-//   dl     : bound on |s_hat - s|;  e: bound on |g_hat - g|
-// plus side (g > 0):   lo_p <= s/g <= hi_p   (hi_p finite only if g surely > 0)
-// minus side (g < 0):  lo_m <= s/(-g) <= hi_m
-__device__ __forceinline__ void ratio_bounds(float s, float g, float dl, float e, float& lo_p,
-                                             float& hi_p, float& lo_m, float& hi_m)
-{
-    float s_lo = fmaxf(s - dl, 0.0f);
-    float s_hi = s + dl;
-    float g_hi = g + e, g_lo = g - e;    // g in [g_lo, g_hi]
-    lo_p = (g_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(g_hi) * kLowShrink : kInf;
-    hi_p = (g_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(g_lo) * kHighGrow : kInf;
-    float n_hi = -g_lo, n_lo = -g_hi;    // -g in [n_lo, n_hi]
-    lo_m = (n_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(n_hi) * kLowShrink : kInf;
-    hi_m = (n_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(n_lo) * kHighGrow : kInf;
 }
 
 template <int P> struct Op;
@@ -739,6 +716,13 @@ __global__ void fill_i32_kernel(int* p, int64_t count, int value)
         p[e] = value;
 }
 
+__global__ void fill_u64_kernel(unsigned long long* p, int64_t count, unsigned long long value)
+{
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = value;
+}
+
 __global__ void export_flags_kernel(const int* flags, int z, int32_t* out, int clear_internal)
 {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < z; k += gridDim.x * blockDim.x) {
@@ -845,6 +829,14 @@ hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t stream)
 {
     hipLaunchKernelGGL(fill_i32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, stream, p,
                        count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long value,
+                           hipStream_t stream)
+{
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(count, 256)), dim3(256), 0, stream, p, count,
+                       value);
     return hipGetLastError();
 }
 

@@ -1,0 +1,694 @@
+// mhar_resident.hip -- register-resident MHAR step kernel for small problems
+// (n <= 256, m <= 8192) on gfx950.
+//
+// Same method as mhar_kernels.hip (paper Alg. 2, S4.3-S4.5: directions,
+// screening product on the matrix cores, certified bounds, exact FP64 chord
+// of the candidate rows, theta, update), laid out so that nothing but A
+// leaves the chip between steps:
+//   * the slack tile (rows of this workgroup x 16 walks) lives in registers
+//     and is updated eagerly (s <- s - theta g) as soon as theta is known;
+//   * the states X and directions D of the 16 walks live in LDS as FP64;
+//   * the screening product G stays in the accumulators of the step;
+//   * candidate rows for the exact evaluation are staged into LDS with
+//     wide loads, then each lane runs one sequential FP64 dot product;
+//   * A is streamed with a register double buffer over a fully unrolled
+//     (row block, K chunk) loop;
+//   * the rows of a walk tile are split over `split` workgroups of 512
+//     rows each (one per CU); per step they combine the certified bounds
+//     and the exact chord ends of their walks through device-scope atomics
+//     at two group barriers.  The grid is launched cooperatively, so all
+//     workgroups of a group are resident; every wait is bounded in time and
+//     raises an error flag instead of hanging.
+#include <math.h>
+
+#include "mhar_device.hpp"
+#include "mhar_internal.hpp"
+
+namespace mhar {
+
+namespace {
+
+constexpr int kCandBatch = 8;  // most candidate rows staged per wave per batch
+__host__ __device__ constexpr int cand_batch(int lda) { return lda <= 128 ? 8 : 4; }
+
+struct ResLds {
+    double theta[kChainTile];
+    double E[kChainTile];
+    double dnorm[kChainTile];
+    double y[kChainTile * kMaxMeq];
+    unsigned long long lmax_bits[kChainTile];   // exact lambda_max >= 0 as ordered bits
+    unsigned long long nlmin_bits[kChainTile];  // exact -lambda_min >= 0 as ordered bits
+    unsigned up[kChainTile];
+    unsigned um[kChainTile];
+    int flags[kChainTile];
+    int cand_row[kWaves][kCandBatch];
+    int cand_chain[kWaves][kCandBatch];
+    unsigned long long mask[kWaves][16];   // candidate ballots of each wave's 16 output slots
+    unsigned long long exact;
+    int ok;
+};
+
+__host__ __device__ inline int res_xld(int lda) { return lda + 2; }
+__host__ __device__ inline int res_fld(int lda) { return lda + 4; }
+__host__ __device__ inline int res_bld(int lda) { return lda + 8; }
+
+struct ResLayout {
+    size_t x_off, d_off, op_off, cb_off, st_off, total;
+};
+
+__host__ __device__ inline ResLayout res_layout(int prec, int lda)
+{
+    ResLayout L;
+    size_t o = 0;
+    auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
+    L.x_off = o;
+    o = al(o + (size_t)kChainTile * res_xld(lda) * 8);
+    L.d_off = o;
+    o = al(o + (size_t)kChainTile * res_xld(lda) * 8);
+    L.op_off = o;
+    if (prec == kFP32) o = al(o + (size_t)kChainTile * res_fld(lda) * 4);
+    else o = al(o + (size_t)2 * kChainTile * res_bld(lda) * 2);
+    L.cb_off = o;
+    o = al(o + (size_t)kWaves * cand_batch(lda) * lda * 8);
+    L.st_off = o;
+    o = al(o + sizeof(ResLds));
+    L.total = o;
+    return L;
+}
+
+// Group barrier of the `split` workgroups that share a walk tile.  All
+// exchange traffic uses relaxed device-scope atomics, which are performed at
+// the device coherence point; a thread only arrives after the atomics it
+// issued have returned (their results are consumed), so no device-scope
+// fence is needed (such fences write back and invalidate the XCD's L2).
+// The wait is bounded by ~1 s of wall clock; returns false if it timed out
+// or another group failed.
+__device__ bool group_barrier(unsigned* cnt, unsigned target, int* err, int* ok_lds)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                break;
+            }
+            if (wall_clock64() - t0 > 100000000ull) {
+                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+        }
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    return *ok_lds != 0;
+}
+
+template <int P, int NK>
+__global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int lda = NK * 32;
+    const ResLayout LY = res_layout(P, lda);
+    double* Xt = (double*)(smem + LY.x_off);
+    double* Dt = (double*)(smem + LY.d_off);
+    unsigned char* op = smem + LY.op_off;
+    double* Cb = (double*)(smem + LY.cb_off);
+    ResLds* cs = (ResLds*)(smem + LY.st_off);
+    constexpr int xld = lda + 2;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    // XCD-aware placement: consecutive workgroup ids go to different XCDs,
+    // so the `split` workgroups of one tile are taken from the same XCD.
+    const int split = a.split;
+    int tile, slice;
+    if (split > 1 && (gridDim.x % (8 * split)) == 0) {
+        const int xcd = blockIdx.x & 7, k = blockIdx.x >> 3;
+        tile = (k / split) * 8 + xcd;
+        slice = k % split;
+    } else {
+        tile = blockIdx.x / split;
+        slice = blockIdx.x % split;
+    }
+    const int c0 = tile * kChainTile;
+    const int n = a.n, m = a.m, m_pad = a.m_pad;
+    const int row0 = slice * kWaves * kRowGroup + wave * kRowGroup;  // this wave's 64 rows
+    const bool rows_live = row0 < m_pad;
+    const bool active_c = (c0 + c) < a.z;
+    unsigned long long* gL = a.gL + (size_t)tile * 3 * 2 * kChainTile;
+    unsigned* gbar = a.gbar + tile;
+    unsigned nbar = 0;
+    const double u64 = 0x1.0p-53;
+
+    // ---- load the tile state ----
+    for (int item = tid; item < kChainTile * xld; item += kThreads) {
+        const int cl = item / xld, j = item - cl * xld;
+        const int chain = c0 + cl;
+        Xt[item] = (chain < a.z && j < n) ? a.X[(size_t)chain * a.lda + j] : 0.0;
+        Dt[item] = 0.0;
+    }
+    if (tid < kChainTile) {
+        cs->theta[tid] = a.theta[c0 + tid];
+        cs->E[tid] = a.E[c0 + tid];
+        cs->flags[tid] = 0;
+    }
+    if (tid == 0) cs->exact = 0;
+    __syncthreads();
+
+    float S[4][4];   // slack of rows row0 + 16 rb + 4 g + r, walk c
+    int T = 2, since = a.since0;
+    bool recompute_now = true;   // the slack never crosses a launch boundary
+    for (int s = 0;; ++s) {
+        if (recompute_now) {
+            // exact FP64 slack b - A x of this wave's rows (FP64 matrix cores)
+            for (int cl = wave; cl < kChainTile; cl += kWaves) {
+                double v = 0.0;
+                for (int j = lane; j < n; j += 64) v = fma(Xt[cl * xld + j], Xt[cl * xld + j], v);
+                v = wave_sum(v);
+                if (lane == 0)
+                    cs->E[cl] = ((double)a.u_s * (1.0 + 0x1.0p-20) + (2.0 * n + 4.0) * u64) * sqrt(v);
+            }
+            int fl = 0;
+            if (rows_live) {
+                f64x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+                for (int k0 = 0; k0 < lda; k0 += 16) {
+                    const double2* bp = (const double2*)(Xt + c * xld + k0 + 4 * g);
+                    const double2 b0 = bp[0], b1 = bp[1];
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const double2* ap = (const double2*)(a.A64 + (size_t)(row0 + 16 * rb + c) * a.lda + k0 + 4 * g);
+                        const double2 a0 = ap[0], a1 = ap[1];
+                        acc[rb] = mma_f64(a0.x, b0.x, acc[rb]);
+                        acc[rb] = mma_f64(a0.y, b0.y, acc[rb]);
+                        acc[rb] = mma_f64(a1.x, b1.x, acc[rb]);
+                        acc[rb] = mma_f64(a1.y, b1.y, acc[rb]);
+                    }
+                }
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    float sv[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        // FP64 output: lane (g, c) slot r holds row 4r + g
+                        const int row = row0 + 16 * rb + 4 * r + g;
+                        const double bi = a.b64[row];
+                        const double sx = bi - acc[rb][r];
+                        if (active_c && row < m) {
+                            if (!(sx > 0.0)) fl |= kNotInterior;
+                            if (sx < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
+                        }
+                        sv[r] = (float)sx;
+                    }
+                    // operand order: lane (g, c) slot r holds row 4g + r, the
+                    // value of lane (r, c) slot g
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float v0 = __shfl(sv[0], 16 * r + c, 64);
+                        const float v1 = __shfl(sv[1], 16 * r + c, 64);
+                        const float v2 = __shfl(sv[2], 16 * r + c, 64);
+                        const float v3 = __shfl(sv[3], 16 * r + c, 64);
+                        S[rb][r] = g == 0 ? v0 : g == 1 ? v1 : g == 2 ? v2 : v3;
+                    }
+                }
+            }
+            if (fl) atomicOr(&cs->flags[c], fl);
+            T = 2;
+            if (s > 0) since = 0;
+            recompute_now = false;
+            __syncthreads();
+        }
+        if (s >= a.steps) break;
+        const uint64_t step = a.step0 + (uint64_t)s;
+
+        // ---------------- A: directions ----------------
+        const int npairs = (n + 1) >> 1;
+        for (int item = tid; item < kChainTile * npairs; item += kThreads) {
+            const int cl = item / npairs, p = item - cl * npairs;
+            const int chain = c0 + cl;
+            if (chain >= a.z) continue;
+            Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step, (uint32_t)p);
+            double ev, od;
+            gauss_pair(w, ev, od);
+            Dt[cl * xld + 2 * p] = ev;
+            if (2 * p + 1 < n) Dt[cl * xld + 2 * p + 1] = od;
+        }
+        if (tid < kChainTile) {
+            cs->up[tid] = __float_as_uint(kInf);
+            cs->um[tid] = __float_as_uint(kInf);
+            cs->lmax_bits[tid] = __double_as_longlong(kInfD);
+            cs->nlmin_bits[tid] = __double_as_longlong(kInfD);
+        }
+        __syncthreads();
+        if (a.m_eq > 0) {
+            for (int pr = wave; pr < kChainTile * a.m_eq; pr += kWaves) {
+                const int cl = pr / a.m_eq, p = pr - cl * a.m_eq;
+                double v = 0.0;
+                if (c0 + cl < a.z) {
+                    const double* er = a.Aeq + (size_t)p * a.lda;
+                    for (int j = lane; j < n; j += 64) v = fma(er[j], Dt[cl * xld + j], v);
+                }
+                v = wave_sum(v);
+                if (lane == 0) cs->y[cl * kMaxMeq + p] = v;
+            }
+            __syncthreads();
+            for (int item = tid; item < kChainTile * n; item += kThreads) {
+                const int cl = item / n, j = item - cl * n;
+                if (c0 + cl >= a.z) continue;
+                double v = Dt[cl * xld + j];
+                for (int p = 0; p < a.m_eq; ++p) v = fma(-a.WT[(size_t)p * a.lda + j], cs->y[cl * kMaxMeq + p], v);
+                Dt[cl * xld + j] = v;
+            }
+            __syncthreads();
+        }
+        for (int cl = wave; cl < kChainTile; cl += kWaves) {
+            double v = 0.0;
+            for (int j = lane; j < n; j += 64) v = fma(Dt[cl * xld + j], Dt[cl * xld + j], v);
+            v = wave_sum(v);
+            if (lane == 0) cs->dnorm[cl] = sqrt(v);
+        }
+        if (P == kFP32) {
+            float* Ot = (float*)op;
+            constexpr int fld = lda + 4;
+            for (int item = tid; item < kChainTile * lda; item += kThreads) {
+                const int cl = item / lda, j = item - cl * lda;
+                Ot[cl * fld + j] = (float)Dt[cl * xld + j];
+            }
+        } else {
+            __bf16* Oh = (__bf16*)op;
+            constexpr int bld = lda + 8;
+            __bf16* Ol = Oh + kChainTile * bld;
+            for (int item = tid; item < kChainTile * lda; item += kThreads) {
+                const int cl = item / lda, j = item - cl * lda;
+                __bf16 hi, lo;
+                split_bf16((float)Dt[cl * xld + j], hi, lo);
+                Oh[cl * bld + j] = hi;
+                Ol[cl * bld + j] = lo;
+            }
+        }
+        __syncthreads();
+
+        // ---------------- B: screening product (this wave's 64 rows) ----------------
+        f32x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+        if (rows_live) {
+            if (P == kFP32) {
+                const float* Ot = (const float*)op;
+                constexpr int fld = lda + 4;
+                float4 buf[2][8];
+                auto load = [&](float4* dst, int kc) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const float4* ap = (const float4*)(a.A32 + (size_t)(row0 + 16 * rb + c) * a.lda + kc * 32 + 8 * g);
+                        dst[2 * rb] = ap[0];
+                        dst[2 * rb + 1] = ap[1];
+                    }
+                };
+                load(buf[0], 0);
+#pragma unroll
+                for (int kc = 0; kc < NK; ++kc) {
+                    if (kc + 1 < NK) load(buf[(kc + 1) & 1], kc + 1);
+                    const float4* bp = (const float4*)(Ot + c * fld + kc * 32 + 8 * g);
+                    const float4 b0 = bp[0], b1 = bp[1];
+                    const float4* cur = buf[kc & 1];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float bv = e < 4 ? (&b0.x)[e] : (&b1.x)[e - 4];
+#pragma unroll
+                        for (int rb = 0; rb < 4; ++rb) {
+                            const float av = e < 4 ? (&cur[2 * rb].x)[e] : (&cur[2 * rb + 1].x)[e - 4];
+                            acc[rb] = mma_f32(av, bv, acc[rb]);
+                        }
+                    }
+                }
+            } else {
+                const __bf16* Oh = (const __bf16*)op;
+                constexpr int bld = lda + 8;
+                const __bf16* Ol = Oh + kChainTile * bld;
+                bf16x8 buf[2][8];
+                auto load = [&](bf16x8* dst, int kc) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const size_t off = (size_t)(row0 + 16 * rb + c) * a.lda + kc * 32 + 8 * g;
+                        dst[2 * rb] = *(const bf16x8*)(a.Ahi + off);
+                        dst[2 * rb + 1] = *(const bf16x8*)(a.Alo + off);
+                    }
+                };
+                load(buf[0], 0);
+#pragma unroll
+                for (int kc = 0; kc < NK; ++kc) {
+                    if (kc + 1 < NK) load(buf[(kc + 1) & 1], kc + 1);
+                    const bf16x8 bh = *(const bf16x8*)(Oh + c * bld + kc * 32 + 8 * g);
+                    const bf16x8 bl = *(const bf16x8*)(Ol + c * bld + kc * 32 + 8 * g);
+                    const bf16x8* cur = buf[kc & 1];
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) acc[rb] = mma_bf16(cur[2 * rb + 1], bh, acc[rb]);
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) acc[rb] = mma_bf16(cur[2 * rb], bl, acc[rb]);
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) acc[rb] = mma_bf16(cur[2 * rb], bh, acc[rb]);
+                }
+            }
+        }
+
+        // ---------------- screening: certified bounds, candidate masks ----------------
+        // Every workgroup screens its rows with its own upper bounds of the
+        // chord ends; they can only exceed the bounds over all rows, so the
+        // candidate set is a superset of the one the global bound would give.
+        const float ed = active_c ? (float)(cs->dnorm[c] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+        const float Ek = (float)cs->E[c] * kHighGrow;
+        const float bscale = a.u_s * (float)T * kHighGrow;
+        float lo_p[4][4], lo_m[4][4];
+        {
+            float up = kInf, um = kInf;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = row0 + 16 * rb + 4 * g + r;
+                    float hp = kInf, hm = kInf;
+                    lo_p[rb][r] = kInf;
+                    lo_m[rb][r] = kInf;
+                    if (rows_live && row < m) {
+                        const float na = a.rownorm[row];
+                        const float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                        ratio_bounds(S[rb][r], acc[rb][r], dl, na * ed, lo_p[rb][r], hp, lo_m[rb][r], hm);
+                    }
+                    up = fminf(up, hp);
+                    um = fminf(um, hm);
+                }
+            up = fminf(up, __shfl_xor(up, 16, 64));
+            up = fminf(up, __shfl_xor(up, 32, 64));
+            um = fminf(um, __shfl_xor(um, 16, 64));
+            um = fminf(um, __shfl_xor(um, 32, 64));
+            if (g == 0) {
+                atomicMin(&cs->up[c], __float_as_uint(up));
+                atomicMin(&cs->um[c], __float_as_uint(um));
+            }
+        }
+        __syncthreads();
+        {
+            const float Up = __uint_as_float(cs->up[c]), Um = __uint_as_float(cs->um[c]);
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = row0 + 16 * rb + 4 * g + r;
+                    const bool cand = active_c && row < m && ((lo_p[rb][r] <= Up) || (lo_m[rb][r] <= Um));
+                    const unsigned long long mk = __ballot(cand);
+                    if (lane == 0) cs->mask[wave][rb * 4 + r] = mk;
+                }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        // ---------------- C: exact chords of the candidate rows ----------------
+        {
+            constexpr int CB = cand_batch(lda);
+            double* cb = Cb + (size_t)wave * CB * lda;
+            int slot = 0;
+            unsigned long long mk = cs->mask[wave][0];
+            unsigned long long nex = 0;
+            while (true) {
+                int cnt = 0;
+                while (cnt < CB) {
+                    while (mk == 0 && slot < 15) mk = cs->mask[wave][++slot];
+                    if (mk == 0) break;
+                    const int bit = __ffsll((long long)mk) - 1;
+                    mk &= mk - 1;
+                    if (lane == 0) {
+                        cs->cand_row[wave][cnt] = row0 + 16 * (slot >> 2) + 4 * (bit >> 4) + (slot & 3);
+                        cs->cand_chain[wave][cnt] = bit & 15;
+                    }
+                    ++cnt;
+                }
+                if (cnt == 0) break;
+                nex += cnt;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (int q = 0; q < cnt; ++q) {
+                    const double* ar = a.A64 + (size_t)cs->cand_row[wave][q] * a.lda;
+#pragma unroll
+                    for (int j = 2 * lane; j < lda; j += 128) *(double2*)(cb + q * lda + j) = *(const double2*)(ar + j);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                if (lane < cnt) {
+                    // the line-set formula of S4.4 in the operation order of a
+                    // sequential FP64 evaluation
+                    const int rr = cs->cand_row[wave][lane];
+                    const int cc = cs->cand_chain[wave][lane];
+                    const double* av = cb + lane * lda;
+                    const double* xv = Xt + cc * xld;
+                    const double* dv = Dt + cc * xld;
+                    const double bi = a.b64[rr];
+                    double sx = bi, gx = 0.0;
+                    int j = 0;
+                    for (; j + 4 <= n; j += 4) {
+                        const double a0 = av[j], a1 = av[j + 1], a2 = av[j + 2], a3 = av[j + 3];
+                        const double x0 = xv[j], x1 = xv[j + 1], x2 = xv[j + 2], x3 = xv[j + 3];
+                        const double d0 = dv[j], d1 = dv[j + 1], d2 = dv[j + 2], d3 = dv[j + 3];
+                        sx = __dsub_rn(sx, __dmul_rn(a0, x0));
+                        gx = __dadd_rn(gx, __dmul_rn(a0, d0));
+                        sx = __dsub_rn(sx, __dmul_rn(a1, x1));
+                        gx = __dadd_rn(gx, __dmul_rn(a1, d1));
+                        sx = __dsub_rn(sx, __dmul_rn(a2, x2));
+                        gx = __dadd_rn(gx, __dmul_rn(a2, d2));
+                        sx = __dsub_rn(sx, __dmul_rn(a3, x3));
+                        gx = __dadd_rn(gx, __dmul_rn(a3, d3));
+                    }
+                    for (; j < n; ++j) {
+                        sx = __dsub_rn(sx, __dmul_rn(av[j], xv[j]));
+                        gx = __dadd_rn(gx, __dmul_rn(av[j], dv[j]));
+                    }
+                    int fl = 0;
+                    if (sx < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
+                    if (sx < 0.0) sx = 0.0;
+                    if (gx > 0.0)
+                        atomicMin(&cs->lmax_bits[cc], (unsigned long long)__double_as_longlong(sx / gx));
+                    else if (gx < 0.0)
+                        atomicMin(&cs->nlmin_bits[cc], (unsigned long long)__double_as_longlong(sx / -gx));
+                    if (fl) atomicOr(&cs->flags[cc], fl);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (lane == 0 && nex) atomicAdd(&cs->exact, nex);
+        }
+        __syncthreads();
+        if (split > 1) {
+            // combine the exact chord ends of the group's workgroups
+            const int slot = (int)(step % 3);
+            if (tid < kChainTile) {
+                // results consumed: the atomics have been performed before arrival
+                const unsigned long long o0 = __hip_atomic_fetch_min(
+                    &gL[(slot * 2 + 0) * kChainTile + tid], cs->lmax_bits[tid], __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                const unsigned long long o1 = __hip_atomic_fetch_min(
+                    &gL[(slot * 2 + 1) * kChainTile + tid], cs->nlmin_bits[tid], __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                if ((o0 & o1) == 1ull) cs->ok = 2;
+            }
+            nbar += 1;
+            if (!group_barrier(gbar, nbar * (unsigned)split, a.gerr, &cs->ok)) break;
+            if (tid < kChainTile) {
+                cs->lmax_bits[tid] = __hip_atomic_load(&gL[(slot * 2 + 0) * kChainTile + tid],
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                cs->nlmin_bits[tid] = __hip_atomic_load(&gL[(slot * 2 + 1) * kChainTile + tid],
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            // every workgroup has read the slot of the previous step
+            if (slice == 0 && tid < 2 * kChainTile) {
+                const unsigned long long o = __hip_atomic_exchange(
+                    &gL[(int)((step + 2) % 3) * 2 * kChainTile + tid],
+                    (unsigned long long)__double_as_longlong(kInfD), __ATOMIC_RELAXED,
+                    __HIP_MEMORY_SCOPE_AGENT);
+                if (o == 1ull) cs->ok = 2;
+            }
+        }
+
+        // ---------------- D: theta, eager slack update, state update ----------------
+        if (tid < kChainTile) {
+            const int chain = c0 + tid;
+            double th = 0.0;
+            int fl = 0;
+            if (chain < a.z) {
+                const double lmax = __longlong_as_double((long long)cs->lmax_bits[tid]);
+                const double lmin = -__longlong_as_double((long long)cs->nlmin_bits[tid]);
+                if (lmax == kInfD || lmin == -kInfD) {
+                    fl |= kUnbounded;
+                } else if (!(lmax > lmin)) {
+                    fl |= kDegenerate;
+                } else {
+                    Block4 w = stream_block(a.seed, kTagTheta, a.chain_offset + (uint32_t)chain, step, 0);
+                    const double u = open_unit(w.w0, w.w1);
+                    th = __dadd_rn(lmin, __dmul_rn(u, __dsub_rn(lmax, lmin)));
+                }
+            }
+            cs->theta[tid] = th;
+            if (fl) cs->flags[tid] |= fl;
+        }
+        __syncthreads();
+        {
+            const float th32 = (float)cs->theta[c];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) S[rb][r] = fmaf(-th32, acc[rb][r], S[rb][r]);
+        }
+        for (int cl = wave; cl < kChainTile; cl += kWaves) {
+            const int chain = c0 + cl;
+            if (chain >= a.z) continue;
+            const double th = cs->theta[cl];
+            double xo = 0.0, xn2 = 0.0;
+            bool finite = isfinite(th);
+            const bool rec = slice == 0 && a.rec_stride > 0 && chain < a.rec_chains &&
+                             ((a.rec_s_base + s + 1) % a.rec_stride) == 0;
+            double* rp = rec ? a.rec_out + ((size_t)((a.rec_s_base + s + 1) / a.rec_stride - 1) *
+                                                a.rec_chains + chain) * n
+                             : nullptr;
+            for (int j = lane; j < n; j += 64) {
+                const double xv = Xt[cl * xld + j];
+                const double xnew = __dadd_rn(xv, __dmul_rn(th, Dt[cl * xld + j]));
+                Xt[cl * xld + j] = xnew;
+                if (rec) rp[j] = xnew;
+                xo = fma(xv, xv, xo);
+                xn2 = fma(xnew, xnew, xn2);
+                finite = finite && isfinite(xnew);
+            }
+            xo = wave_sum(xo);
+            xn2 = wave_sum(xn2);
+            finite = __all(finite);
+            if (lane == 0) {
+                const double dn = cs->dnorm[cl], at = fabs(th);
+                const double us = (double)a.u_s;
+                double E = cs->E[cl];
+                E += at * dn * ((double)a.eps_g + 2.0 * us);
+                E += 2.0 * u64 * (sqrt(xo) + at * dn);
+                E += us * (1.0 + 0x1.0p-20) * sqrt(xn2);
+                cs->E[cl] = E;
+                if (!finite) cs->flags[cl] |= kNonFinite;
+            }
+        }
+        __syncthreads();
+        T += 1;
+        since += 1;
+        recompute_now = since >= a.R;
+    }
+
+    // ---- write the tile state back ----
+    __syncthreads();
+    if (slice == 0) {
+        for (int item = tid; item < kChainTile * n; item += kThreads) {
+            const int cl = item / n, j = item - cl * n;
+            const int chain = c0 + cl;
+            if (chain < a.z) a.X[(size_t)chain * a.lda + j] = Xt[cl * xld + j];
+        }
+        if (tid < kChainTile) {
+            a.theta[c0 + tid] = cs->theta[tid];
+            a.E[c0 + tid] = cs->E[tid];
+        }
+    }
+    if (tid < kChainTile) {
+        const int chain = c0 + tid;
+        if (cs->flags[tid] && chain < a.z) atomicOr(&a.flags[chain], cs->flags[tid]);
+    }
+    if (tid == 0 && cs->exact) atomicAdd(&a.counters[0], cs->exact);
+}
+
+template <int P, int NK>
+hipError_t launch_res(const StepArgs& a, hipStream_t stream)
+{
+    const size_t lds = res_layout(P, NK * 32).total;
+    static bool attr_set = false;
+    const void* fn = (const void*)resident_kernel<P, NK>;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const dim3 grid((a.z_pad / kChainTile) * a.split), block(kThreads);
+    if (a.split > 1) {
+        StepArgs copy = a;
+        void* args[] = {&copy};
+        return hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)lds, stream);
+    }
+    hipLaunchKernelGGL((resident_kernel<P, NK>), grid, block, lds, stream, a);
+    return hipGetLastError();
+}
+
+template <int P, int NK>
+int res_blocks_per_cu()
+{
+    int nb = 0;
+    const size_t lds = res_layout(P, NK * 32).total;
+    hipFuncSetAttribute((const void*)resident_kernel<P, NK>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)resident_kernel<P, NK>, kThreads, lds) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+template <int P>
+hipError_t launch_res_nk(const StepArgs& a, hipStream_t stream)
+{
+    switch (a.lda / 32) {
+    case 1: return launch_res<P, 1>(a, stream);
+    case 2: return launch_res<P, 2>(a, stream);
+    case 3: return launch_res<P, 3>(a, stream);
+    case 4: return launch_res<P, 4>(a, stream);
+    case 5: return launch_res<P, 5>(a, stream);
+    case 6: return launch_res<P, 6>(a, stream);
+    case 7: return launch_res<P, 7>(a, stream);
+    case 8: return launch_res<P, 8>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int P>
+int res_occupancy(int lda)
+{
+    switch (lda / 32) {
+    case 1: return res_blocks_per_cu<P, 1>();
+    case 2: return res_blocks_per_cu<P, 2>();
+    case 3: return res_blocks_per_cu<P, 3>();
+    case 4: return res_blocks_per_cu<P, 4>();
+    case 5: return res_blocks_per_cu<P, 5>();
+    case 6: return res_blocks_per_cu<P, 6>();
+    case 7: return res_blocks_per_cu<P, 7>();
+    case 8: return res_blocks_per_cu<P, 8>();
+    default: return 0;
+    }
+}
+
+}  // namespace
+
+int resident_split(int prec, int lda, int m_pad, int z_pad)
+{
+    if (prec != kFP32 && prec != kBF16X3) return 0;
+    if (lda > 256 || res_layout(prec, lda).total > 163840) return 0;
+    const int rows = kWaves * kRowGroup;
+    const int split = (m_pad + rows - 1) / rows;
+    if (split > 16) return 0;
+    if (split == 1) return 1;
+    // a split launch is cooperative: the whole grid must be resident
+    int dev = 0, cus = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+    const int per_cu = prec == kFP32 ? res_occupancy<kFP32>(lda) : res_occupancy<kBF16X3>(lda);
+    const long grid = (long)(z_pad / kChainTile) * split;
+    if (per_cu < 1 || grid > (long)per_cu * cus) return 0;
+    return split;
+}
+
+hipError_t launch_resident(int prec, const StepArgs& a, hipStream_t stream)
+{
+    if (prec == kFP32) return launch_res_nk<kFP32>(a, stream);
+    if (prec == kBF16X3) return launch_res_nk<kBF16X3>(a, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mhar

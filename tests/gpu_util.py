@@ -60,5 +60,8 @@ def small_cases():
         "randpoly": inst.randpoly(n=37, m=300, z=50, seed=11),
         "simplex_cut": inst.simplex_cut(n=30, m_extra=200, m_eq_extra=3, z=40, seed=12),
         "rotbox": inst.rotbox(n=40, m_extra=200, z=33, seed=13)[0],
+        # rows split over 3 workgroups per walk tile (plain and XCD-aware mapping)
+        "split3": inst.randpoly(n=40, m=1300, z=40, seed=14),
+        "split3_xcd": inst.randpoly(n=64, m=1500, z=128, seed=15),
     }
     return cases

@@ -26,7 +26,7 @@ def orc():
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("case", ["cube10", "randpoly", "simplex_cut", "rotbox"])
+@pytest.mark.parametrize("case", ["cube10", "randpoly", "simplex_cut", "rotbox", "split3", "split3_xcd"])
 def test_one_step_parity(orc, case, prec):
     p = gu.small_cases()[case]
     P = gu.oracle_projection(orc, p)
@@ -46,7 +46,7 @@ def test_one_step_parity(orc, case, prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("case", ["cube10", "randpoly", "simplex_cut", "rotbox"])
+@pytest.mark.parametrize("case", ["cube10", "randpoly", "simplex_cut", "rotbox", "split3", "split3_xcd"])
 def test_short_horizon_parity(orc, case, prec):
     p = gu.small_cases()[case]
     P = gu.oracle_projection(orc, p)
