@@ -68,6 +68,10 @@ def _bind(lib):
     lib.mhar_ref_run.restype = ctypes.c_int
     lib.mhar_ref_precond_nll.argtypes = [i64, i64, d, d, i64, d, d, d, d]
     lib.mhar_ref_precond_nll.restype = ctypes.c_int
+    lib.mhar_ref_precond_train_step.argtypes = [i64, i64, d, d, d, d, d, d, i64, d, i64,
+                                                ctypes.c_double, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, d]
+    lib.mhar_ref_precond_train_step.restype = ctypes.c_int
     lib.mhar_ref_adam.argtypes = [i64, d, d, d, d, i64, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
     lib.mhar_ref_adam.restype = None
@@ -180,6 +184,22 @@ class Oracle:
         if rc != OK:
             raise RuntimeError(f"mhar_ref_precond_nll failed: {rc}")
         return nll.value, gU[:, :r], gl
+
+    def precond_train_step(self, V, log_sigma, moments, X, t, lr, beta1=0.9, beta2=0.999,
+                           eps=1e-8):
+        """One scale-free Adam update; moments = (m1V, m2V, m1l, m2l).
+        Returns (V, log_sigma, moments, U), all new arrays."""
+        V, ls = (np.array(a, dtype=np.float64, copy=True) for a in (V, log_sigma))
+        mom = [np.array(a, dtype=np.float64, copy=True) for a in moments]
+        X = _f64(X).reshape(-1, ls.shape[0])
+        n, r = V.shape
+        U = np.empty_like(V)
+        rc = self.lib.mhar_ref_precond_train_step(n, r, _p(V), _p(ls), *(_p(a) for a in mom),
+                                                  X.shape[0], _p(X), t, lr, beta1, beta2, eps,
+                                                  _p(U))
+        if rc != OK:
+            raise RuntimeError(f"mhar_ref_precond_train_step failed: {rc}")
+        return V, ls, tuple(mom), U
 
     def adam(self, param, grad, m1, m2, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         param, grad, m1, m2 = (np.array(a, dtype=np.float64, copy=True) for a in

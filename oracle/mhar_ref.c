@@ -440,3 +440,39 @@ void mhar_ref_adam(int64_t count, double* param, const double* grad, double* m1,
         param[i] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+int mhar_ref_precond_train_step(int64_t n, int64_t r, double* V, double* log_sigma,
+                                double* m1V, double* m2V, double* m1l, double* m2l, int64_t z,
+                                const double* X, int64_t t, double lr, double beta1,
+                                double beta2, double eps, double* U_out)
+{
+    if (n <= 0 || r <= 0 || z <= 0 || !V || !log_sigma || !X || !U_out) return MHAR_REF_E_INVALID_ARG;
+    size_t nr = (size_t)(n * r);
+    double* U = (double*)malloc(sizeof(double) * nr);
+    double* gU = (double*)malloc(sizeof(double) * nr);
+    double* gV = (double*)malloc(sizeof(double) * nr);
+    double* gl = (double*)malloc(sizeof(double) * (size_t)n);
+    double nll = 0.0;
+    int rc = MHAR_REF_OK;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t a = 0; a < r; ++a) U[i * r + a] = exp(log_sigma[i]) * V[i * r + a];
+    rc = mhar_ref_precond_nll(n, r, U, log_sigma, z, X, &nll, gU, gl);
+    if (rc == MHAR_REF_OK) {
+        /* d/dV_ia = exp(l_i) dNLL/dU_ia;  d/dl_i = dNLL/dl_i + sum_a dNLL/dU_ia * U_ia */
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t a = 0; a < r; ++a) {
+                gV[i * r + a] = gU[i * r + a] * exp(log_sigma[i]);
+                gl[i] += gU[i * r + a] * U[i * r + a];
+            }
+        }
+        mhar_ref_adam((int64_t)nr, V, gV, m1V, m2V, t, lr, beta1, beta2, eps);
+        mhar_ref_adam(n, log_sigma, gl, m1l, m2l, t, lr, beta1, beta2, eps);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t a = 0; a < r; ++a) U_out[i * r + a] = exp(log_sigma[i]) * V[i * r + a];
+    }
+    free(U);
+    free(gU);
+    free(gV);
+    free(gl);
+    return rc;
+}

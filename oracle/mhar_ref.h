@@ -102,6 +102,17 @@ int mhar_ref_precond_nll(int64_t n, int64_t r, const double* U, const double* lo
 void mhar_ref_adam(int64_t count, double* param, const double* grad, double* m1,
                    double* m2, int64_t t, double lr, double beta1, double beta2, double eps);
 
+/* One burn-in update of the covariance in the scale-free coordinates
+ * V = diag(exp(-log_sigma)) U.  U is formed as diag(exp(log_sigma)) V, the
+ * NLL gradient (grad_U, grad_l) is taken at the states X (z x n); the chain
+ * rule gives grad_V = diag(exp(log_sigma)) grad_U and grad_l + rowsum(grad_U o U)
+ * for log_sigma; one Adam step moves V (moments m1V, m2V) and log_sigma
+ * (moments m1l, m2l); U_out (n x r) receives diag(exp(log_sigma_new)) V_new. */
+int mhar_ref_precond_train_step(int64_t n, int64_t r, double* V, double* log_sigma,
+                                double* m1V, double* m2V, double* m1l, double* m2l, int64_t z,
+                                const double* X, int64_t t, double lr, double beta1,
+                                double beta2, double eps, double* U_out);
+
 #ifdef __cplusplus
 }
 #endif

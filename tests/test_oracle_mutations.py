@@ -29,6 +29,8 @@ PINS = [
     precond.test_gradient_finite_differences,
     precond.test_adam_closed_form,
     precond.test_direction_covariance,
+    precond.test_train_step_gradient_finite_differences,
+    precond.test_train_step_scale_equivariance,
 ]
 
 MUTANTS = {
@@ -51,6 +53,9 @@ MUTANTS = {
     "nll_grad_factor": ("grad_U[i * r + a] = v;", "grad_U[i * r + a] = 0.5 * v;"),
     "nll_logdet": ("logdet += 2.0 * log(L[i * n + i]);", "logdet += log(L[i * n + i]);"),
     "adam_bias": ("double mh = m1[i] / c1;", "double mh = m1[i];"),
+    "train_chain_scale": ("gV[i * r + a] = gU[i * r + a] * exp(log_sigma[i]);",
+                          "gV[i * r + a] = gU[i * r + a];"),
+    "train_chain_rowsum": ("gl[i] += gU[i * r + a] * U[i * r + a];", ";"),
 }
 
 

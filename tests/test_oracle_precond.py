@@ -3,7 +3,10 @@
 Fixed from outside the oracle by: scipy's multivariate normal log-density
 (NLL = -mean log N(x_k; mean, Sigma) - n/2 log 2 pi), the diagonal closed
 form when U = 0, central finite differences of the NLL for the gradient,
-and the closed-form first two Adam steps."""
+and the closed-form first two Adam steps.  The burn-in update in the
+scale-free coordinates V = diag(exp(-l)) U is pinned by finite differences of
+NLL(diag(exp(l)) V, l) and by its equivariance under a rescaling of the
+states."""
 import math
 
 import numpy as np
@@ -90,3 +93,51 @@ def test_direction_covariance(oracle):
     # plain directions are N(0, I)
     H = np.array([oracle.direction(n, 5, k, t) for k in range(100) for t in range(200)])
     assert np.abs(H.T @ H / H.shape[0] - np.eye(n)).max() <= 0.04
+
+
+def _grad_from_step(oracle, V, ls, X):
+    """(V, l) gradient read off one Adam step with fresh moments: at t = 1 with
+    eps = lr = 1e9 the step is g / (1 + |g| 1e-9), i.e. g to ~1e-9 relative."""
+    z0 = (np.zeros_like(V), np.zeros_like(V), np.zeros_like(ls), np.zeros_like(ls))
+    V1, l1, _, U1 = oracle.precond_train_step(V, ls, z0, X, 1, 1e9, eps=1e9)
+    return V - V1, ls - l1, V1, l1, U1
+
+
+def test_train_step_gradient_finite_differences(oracle):
+    U, ls, X = _problem(n=6, r=2, z=7, seed=5)
+    V = U * np.exp(-ls)[:, None]
+    gV, gl, V1, l1, U1 = _grad_from_step(oracle, V, ls, X)
+
+    def f(V_, l_):
+        return oracle.precond_nll(V_ * np.exp(l_)[:, None], l_, X)[0]
+    h = 1e-6
+    for (i, a) in [(0, 0), (2, 1), (5, 1), (3, 0)]:
+        Vp, Vm = V.copy(), V.copy()
+        Vp[i, a] += h
+        Vm[i, a] -= h
+        fd = (f(Vp, ls) - f(Vm, ls)) / (2 * h)
+        assert abs(fd - gV[i, a]) <= 1e-6 * max(1, abs(fd))
+    for i in range(6):
+        lp, lm = ls.copy(), ls.copy()
+        lp[i] += h
+        lm[i] -= h
+        fd = (f(V, lp) - f(V, lm)) / (2 * h)
+        assert abs(fd - gl[i]) <= 1e-6 * max(1, abs(fd))
+    # the returned factor is the one the new coordinates define
+    assert np.abs(U1 - V1 * np.exp(l1)[:, None]).max() <= 1e-15 * np.abs(U1).max()
+
+
+def test_train_step_scale_equivariance(oracle):
+    # Sigma -> c^2 Sigma for states c X shifts the NLL by a constant, so in the
+    # scale-free coordinates the update moves V identically and l by log c.
+    U, ls, X = _problem(n=5, r=3, z=8, seed=6)
+    V = U * np.exp(-ls)[:, None]
+    mom = tuple(0.1 * np.abs(np.random.default_rng(7).standard_normal(a.shape))
+                for a in (V, V, ls, ls))
+    c = 37.0
+    Va, la, ma, _ = oracle.precond_train_step(V, ls, mom, X, 3, 0.05)
+    Vb, lb, mb, _ = oracle.precond_train_step(V, ls + math.log(c), mom, c * X, 3, 0.05)
+    assert np.abs(Va - Vb).max() <= 1e-12
+    assert np.abs((lb - la) - math.log(c)).max() <= 1e-12
+    for x, y in zip(ma, mb):
+        assert np.abs(x - y).max() <= 1e-12 * max(1.0, np.abs(x).max())
