@@ -106,6 +106,154 @@ def cpu_baseline(p, seconds):
                       f"recomputed every step), {dt:.1f} s on {threads} threads"}
 
 
+def _base_line(value, steps, warmup, sec, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "chain-steps/s", "n_gpus": 1,
+            "steps": steps, "warmup": warmup, "ms_per_step": sec * 1e3 / max(steps, 1),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def _timed_steps(ch, steps):
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ch.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def _make(p, precision, recompute_every=50):
+    import torch
+    from paper_2104_07097_amd import mhar
+    dev = torch.device("cuda:0")
+    t = lambda a: None if a is None else torch.tensor(a, device=dev, dtype=torch.float64)
+    prob = mhar.Problem(t(p.A), t(p.b), t(p.A_eq), t(p.b_eq), precision=precision,
+                        recompute_every=recompute_every)
+    return prob, mhar.Chains(prob, t(p.X0))
+
+
+def bench_simple(args, p, precision, workload, default_steps):
+    steps = args.steps if args.steps != 5000 else default_steps
+    prob, ch = _make(p, precision)
+    ch.step(args.warmup)
+    sec = _timed_steps(ch, steps)
+    st = ch.stats()
+    flags = ch.sync()
+    return _base_line(p.z * steps / sec, steps, args.warmup, sec, precision,
+                      {"workload": workload, "n": p.n, "m": p.m, "m_eq": p.m_eq, "z": p.z,
+                       "precision": precision, "recompute_every": 50,
+                       "kernel": "resident" if st["kernel"] == 1 else "general",
+                       "exact_rows_per_chain_step": st["exact_rows"] / max(1, st["chain_steps"]),
+                       "flags": flags})
+
+
+def bench_cube10(args):
+    from paper_2104_07097_amd import instances as inst
+    return bench_simple(args, inst.cube10(16), "fp64",
+                        "hypercube [-1,1]^10 as [I;-I]x<=1, z=16 walks from the origin, FP64", 10000)
+
+
+def bench_simplex_cut(args):
+    from paper_2104_07097_amd import instances as inst
+    return bench_simple(args, inst.simplex_cut(), "bf16x3",
+                        "simplex n=500 + 4 Gaussian equalities + 5000 Gaussian halfspaces, "
+                        "z=4096 from the centre, BF16x3 screening, factored FP64 projection", 200)
+
+
+def bench_batched(args):
+    import torch
+    from paper_2104_07097_amd import instances as inst
+    from paper_2104_07097_amd import mhar
+    probs = inst.batched()
+    made = [_make(p, "fp32") for p in probs]
+    batch = mhar.Batch([ch for _, ch in made])
+    steps = args.steps if args.steps != 5000 else 100
+    batch.step(min(args.warmup, 20))
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    batch.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    z = sum(p.z for p in probs)
+    flags = 0
+    for _, ch in made:
+        flags |= ch.sync()
+    return _base_line(z * steps / sec, steps, min(args.warmup, 20), sec, "fp32",
+                      {"workload": "256 Gaussian-halfspace polytopes, n log-uniform in [20,400], "
+                                   "m=ceil(4 n^1.5), 256 walks each, one persistent launch per call",
+                       "problems": len(probs), "z_total": z,
+                       "sum_mn": int(sum(p.m * p.n for p in probs)), "flags": flags})
+
+
+def bench_rotbox(args):
+    """Learned rank-r + diagonal covariance vs isotropic directions (same seed,
+    same steps): min-marginal ESS/s over a recorded window, plus the max marginal
+    KS distance of the final states to exact samples (equal accuracy check)."""
+    import numpy as np
+    import torch
+    from paper_2104_07097_amd import instances as inst
+    from paper_2104_07097_amd.stats import ks_two_sample, min_marginal_ess
+    p, Q, sides = inst.rotbox()
+    steps = args.steps if args.steps != 5000 else 1000
+    rec_chains = 64
+    rng = np.random.default_rng(77)
+    Yr = rng.uniform(-0.5, 0.5, size=(p.z, p.n)) * sides[None, :]
+    exact = Yr @ Q.T
+    exact = exact[np.all(exact @ p.A.T <= p.b, axis=1)]
+    out = {}
+    for mode in ("plain", "learned"):
+        prob, ch = _make(p, "fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "learned":
+            ch.precond_create(args.rank)
+            ch.precond_train(args.burnin, 0.05)
+            ch.precond_freeze()
+        else:
+            ch.step(args.burnin)
+        torch.cuda.synchronize()
+        burn = time.perf_counter() - t0
+        start, _ = ch.state()
+        sec = _timed_steps(ch, steps)
+        Xend, _ = ch.state()
+        # replay the measured window (same seed, same start) recording 64 walks
+        ch.set_state(start, args.burnin)
+        rec = ch.record(steps, 1, rec_chains).cpu().numpy()
+        Xrep, _ = ch.state()
+        ess, _ = min_marginal_ess(rec)
+        ess *= p.z / rec_chains
+        Xe = Xend.cpu().numpy()
+        ks = max(ks_two_sample(Xe[:, j], exact[:, j]) for j in range(0, p.n, 10))
+        out[mode] = {"chain_steps_per_sec": p.z * steps / sec, "ms_per_step": sec * 1e3 / steps,
+                     "min_marginal_ess": ess, "min_marginal_ess_per_sec": ess / sec,
+                     "burnin_s": burn, "max_marginal_ks_vs_exact": ks,
+                     "replay_bitwise_identical": bool(torch.equal(Xrep, Xend)),
+                     "flags": ch.sync()}
+        ch.close()
+        prob.close()
+    line = _base_line(out["learned"]["chain_steps_per_sec"], steps, args.burnin,
+                      steps / out["learned"]["chain_steps_per_sec"] * p.z, "fp32",
+                      {"workload": "rotated box n=1000 (sides log-uniform in [1e-3,1]) + 8000 "
+                                   "unit-norm halfspaces at distance 1, z=8192 from the centre",
+                       "rank": args.rank, "burnin": args.burnin, "window_steps": steps})
+    line["learned_vs_plain"] = out
+    line["ess_gain"] = out["learned"]["min_marginal_ess_per_sec"] / max(
+        out["plain"]["min_marginal_ess_per_sec"], 1e-300)
+    return line
+
+
+OTHER_WORKLOADS = {"cube10": bench_cube10, "simplex_cut": bench_simplex_cut,
+                   "batched": bench_batched, "rotbox": bench_rotbox}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +264,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
+    ap.add_argument("--workload", default="randpoly",
+                    choices=["randpoly", "cube10", "simplex_cut", "batched", "rotbox"],
+                    help="randpoly (default) is the single-GPU configuration of the headline "
+                         "metric; the others are the remaining configurations")
+    ap.add_argument("--rank", type=int, default=64, help="rotbox: rank of the learned covariance")
+    ap.add_argument("--burnin", type=int, default=500, help="rotbox: burn-in (training) steps")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -129,6 +285,10 @@ def main():
     if not torch.cuda.is_available():
         log("bench.py needs a HIP device")
         sys.exit(1)
+    if args.workload != "randpoly":
+        line = OTHER_WORKLOADS[args.workload](args)
+        print(json.dumps(line), flush=True)
+        return
     launch_steps = max(1, min(args.launch_steps, args.steps))
     steps = (args.steps // launch_steps) * launch_steps
     p = inst.randpoly()  # n=100, m=2000, z=1024
@@ -144,6 +304,14 @@ def main():
             f"{p.z * steps / r['gpu_time'] / 1e6:.2f} M chain-steps/s, flags={r['flags']}, "
             f"feasible={feasible}, exact rows/chain-step="
             f"{r['stats']['exact_rows'] / max(1, r['stats']['chain_steps']):.2f}")
+    if args.calibrate_copy_mib > 0:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
     best = max(precs, key=lambda k: p.z * steps / results[k]["gpu_time"])
     r = results[best]
     value = p.z * steps / r["gpu_time"]
@@ -170,7 +338,8 @@ def main():
                    "steps_per_launch": launch_steps},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[best],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[best], "traffic": None,
-                     "kernel": f"mhar_steps_kernel<{best}>",
+                     "kernel": ("resident_kernel" if r["stats"]["kernel"] == 1 else "mhar_steps_kernel")
+                               + f"<{best}>, {r['stats']['split']} workgroups per 16-walk tile",
                      "avg_launch_ms": avg_launch * 1e3,
                      "flops_per_launch": flops_per_launch},
         "wall_s": sum(results[k]["wall"] for k in precs),

@@ -97,6 +97,7 @@ typedef struct {
 
 typedef struct mhar_problem* mhar_problem_t;
 typedef struct mhar_chains* mhar_chains_t;
+typedef struct mhar_batch* mhar_batch_t;
 
 /* Diagnostics of one chains handle, accumulated since creation. */
 typedef struct {
@@ -104,6 +105,8 @@ typedef struct {
     uint64_t chain_steps;       /* walks x steps */
     uint64_t exact_rows;        /* rows evaluated exactly in FP64 (candidates of the screening) */
     uint64_t recomputes;        /* exact slack recomputes */
+    int32_t kernel;             /* 0: general kernel (slack in HBM), 1: register-resident kernel */
+    int32_t split;              /* workgroups per 16-walk tile (resident kernel), else 1 */
 } mhar_stats_t;
 
 /* library version as major*10000 + minor*100 + patch */
@@ -190,6 +193,81 @@ mhar_status_t mhar_sync(mhar_chains_t chains, void* stream, int32_t* any_flags);
 mhar_status_t mhar_get_stats(mhar_chains_t chains, void* stream, mhar_stats_t* stats);
 
 mhar_status_t mhar_chains_destroy(mhar_chains_t chains);
+
+/* ---------------------------------------------------------------------- */
+/* Learned direction covariance (burn-in only; not in the paper)          */
+/* ---------------------------------------------------------------------- */
+/* Directions become d = P (U eps + exp(l) o h), eps ~ N(0, I_rank) from the
+ * LOWRANK stream, h ~ N(0, I_n): Gaussian with covariance
+ * Sigma = U U^T + diag(exp(2 l)), symmetric and independent of the state,
+ * so the uniform target is kept.  Training fits Sigma to the walk states by
+ * Adam on the Gaussian NLL  1/2 log det Sigma + 1/2 tr(Sigma^{-1} S)  (S: the
+ * (1/z) covariance of the states about their mean) -- the isotropic
+ * pre-processing the paper's cost analysis assumes (S3.1).  U is n x rank
+ * row-major FP64, l (log_sigma) has n entries.  Steps taken while a
+ * covariance is attached run on the general kernel. */
+
+/* Device workspace bytes for a covariance of rank 1..64 on these chains. */
+mhar_status_t mhar_precond_workspace_size(mhar_chains_t chains, int32_t rank, size_t* bytes);
+
+/* Attach a covariance: U_ij = 0.01 N(0,1) from the stream (seed, tag 4,
+ * chain = i, step 0), l = 0.  workspace: dev, 256-byte aligned. */
+mhar_status_t mhar_precond_create(mhar_chains_t chains, int32_t rank, void* workspace,
+                                  size_t ws_bytes, void* stream);
+
+/* Set U (dev n x rank) and log_sigma (dev n); clears the Adam moments and
+ * sets the trained coordinates V = diag(exp(-log_sigma)) U. */
+mhar_status_t mhar_precond_set(mhar_chains_t chains, const double* U, const double* log_sigma,
+                               void* stream);
+
+/* Copy U (dev n x rank) and log_sigma (dev n); either may be NULL. */
+mhar_status_t mhar_precond_get(mhar_chains_t chains, double* U, double* log_sigma, void* stream);
+
+/* NLL of the current states and its gradient: nll dev (1 double), grad_U
+ * dev (n x rank), grad_log_sigma dev (n); any may be NULL. */
+mhar_status_t mhar_precond_loss(mhar_chains_t chains, double* nll, double* grad_U,
+                                double* grad_log_sigma, void* stream);
+
+/* `steps` burn-in steps: each is one MHAR step with the current Sigma,
+ * then one Adam update (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
+ * from the gradient at the new states.  Adam works in the scale-free
+ * coordinates (V, log_sigma) with U = diag(exp(log_sigma)) V: their
+ * gradients are diag(exp(log_sigma)) grad_U and grad_log_sigma plus the row
+ * sums of grad_U o U, so every axis, long or short, gets an O(1) step.
+ * U is rebuilt from V after each update.  MHAR_E_STATE once frozen. */
+mhar_status_t mhar_precond_train(mhar_chains_t chains, int64_t steps, double lr, void* stream);
+
+/* Freeze the covariance: later steps use it unchanged, training is refused. */
+mhar_status_t mhar_precond_freeze(mhar_chains_t chains);
+
+/* Detach the covariance: back to isotropic directions. */
+mhar_status_t mhar_precond_destroy(mhar_chains_t chains);
+
+/* ---------------------------------------------------------------------- */
+/* Batches: many problems of uneven n and m in one persistent launch      */
+/* ---------------------------------------------------------------------- */
+/* A batch groups `count` existing chains handles (each on its own problem,
+ * all of one precision).  mhar_batch_step advances all of them by the same
+ * number of steps in one persistent launch: workgroups take (problem,
+ * 16-walk tile) units from a device queue ordered by decreasing cost
+ * (m x n), the longest-processing-time-first rule, so uneven problems
+ * balance across the GPU.  Trajectories are identical to stepping each
+ * handle alone.  The handles stay owned by the caller, must outlive the
+ * batch, and should not be stepped on other streams while it exists. */
+
+/* Device workspace bytes for a batch of these handles (count >= 1). */
+mhar_status_t mhar_batch_workspace_size(int32_t count, const mhar_chains_t* chains, size_t* bytes);
+
+/* Create the batch (host array of `count` handles; workspace dev, 256-byte
+ * aligned).  Allocates one small pinned host buffer for the unit
+ * descriptors. */
+mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void* workspace,
+                                size_t ws_bytes, mhar_batch_t* out);
+
+/* Enqueue `steps` steps of every handle in the batch. */
+mhar_status_t mhar_batch_step(mhar_batch_t batch, int64_t steps, void* stream);
+
+mhar_status_t mhar_batch_destroy(mhar_batch_t batch);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,28 @@ struct mhar_chains {
     unsigned long long* gL;
     unsigned* gbar;
     int* gerr;
+    // learned direction covariance
+    int pc_rank;        // 0: isotropic directions
+    int pc_frozen;
+    int64_t pc_t;       // Adam step counter
+    int split_saved;    // kernel choice before the covariance was attached
+    int force_recompute;
+    PrecondBufs pc;
+};
+
+struct mhar_batch {
+    int count;
+    int prec;
+    std::vector<mhar_chains*> chains;
+    std::vector<int> saved_split;
+    StepArgs* descs_dev;
+    int2* units_dev;
+    unsigned* next_dev;
+    StepArgs* descs_host;   // pinned
+    hipEvent_t copied;
+    bool copy_pending;
+    int nunits, max_lda, grid;
+    double work_per_step;
 };
 
 namespace {
@@ -228,6 +250,9 @@ StepArgs make_args(const mhar_chains* c)
     a.eps_g = p->eps_g;
     a.u_s = p->u_s;
     a.split = c->split > 0 ? c->split : 1;
+    a.r = c->pc_rank;
+    a.U = c->pc_rank ? c->pc.U : nullptr;
+    a.esig = c->pc_rank ? c->pc.esig : nullptr;
     a.gU = c->gU;
     a.gL = c->gL;
     a.gbar = c->gbar;
@@ -265,6 +290,10 @@ mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, doub
     const mhar_problem* p = c->p;
     int64_t chunk = p->steps_per_launch > 0 ? p->steps_per_launch : auto_chunk(p);
     int64_t done = 0;
+    if (c->force_recompute) {
+        recompute_first = 1;
+        c->force_recompute = 0;
+    }
     if (recompute_first) {
         StepArgs a = make_args(c);
         a.steps = 0;
@@ -559,6 +588,271 @@ mhar_status_t mhar_get_stats(mhar_chains_t c, void* stream, mhar_stats_t* stats)
     stats->chain_steps = c->step * (uint64_t)c->z;
     stats->exact_rows = cnt[0];
     stats->recomputes = c->recomputes;
+    stats->kernel = c->split > 0 ? 1 : 0;
+    stats->split = c->split > 0 ? c->split : 1;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_workspace_size(mhar_chains_t c, int32_t rank, size_t* bytes)
+{
+    if (!c || !bytes) return fail(MHAR_E_INVALID_ARG, "chains and bytes must be non-NULL");
+    if (rank < 1 || rank > kMaxMeq) return fail(MHAR_E_SHAPE, "rank must be in [1, 64]");
+    *bytes = precond_bytes(c->p->n, rank, c->z, c->p->lda);
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_create(mhar_chains_t c, int32_t rank, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (c->pc_rank) return fail(MHAR_E_STATE, "a covariance is already attached");
+    if (rank < 1 || rank > kMaxMeq) return fail(MHAR_E_SHAPE, "rank must be in [1, 64]");
+    if (!ws || !aligned256(ws)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < precond_bytes(c->p->n, rank, c->z, c->p->lda))
+        return fail(MHAR_E_WORKSPACE, "precond workspace too small");
+    c->pc = PrecondBufs{};
+    c->pc.n = c->p->n;
+    c->pc.r = rank;
+    c->pc.z = c->z;
+    c->pc.lda = c->p->lda;
+    precond_carve(&c->pc, ws);
+    MHAR_HIP(launch_precond_init(c->pc, c->seed, (hipStream_t)stream), "covariance init");
+    c->pc_rank = rank;
+    c->pc_frozen = 0;
+    c->pc_t = 0;
+    c->split_saved = c->split;
+    c->split = 0;
+    c->force_recompute = 1;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_set(mhar_chains_t c, const double* U, const double* ls, void* stream)
+{
+    if (!c || !U || !ls) return fail(MHAR_E_INVALID_ARG, "chains, U and log_sigma must be non-NULL");
+    if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nr = (size_t)c->pc.n * c->pc.r;
+    MHAR_HIP(hipMemcpyAsync(c->pc.U, U, nr * 8, hipMemcpyDeviceToDevice, s), "covariance copy");
+    MHAR_HIP(hipMemcpyAsync(c->pc.logsig, ls, (size_t)c->pc.n * 8, hipMemcpyDeviceToDevice, s), "covariance copy");
+    MHAR_HIP(launch_fill_i32((int*)c->pc.m1V, (int64_t)nr * 2, 0, s), "moment reset");
+    MHAR_HIP(launch_fill_i32((int*)c->pc.m2V, (int64_t)nr * 2, 0, s), "moment reset");
+    MHAR_HIP(launch_fill_i32((int*)c->pc.m1l, (int64_t)c->pc.n * 2, 0, s), "moment reset");
+    MHAR_HIP(launch_fill_i32((int*)c->pc.m2l, (int64_t)c->pc.n * 2, 0, s), "moment reset");
+    MHAR_HIP(launch_precond_set_scales(c->pc, s), "covariance scale");
+    c->pc_t = 0;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_get(mhar_chains_t c, double* U, double* ls, void* stream)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
+    hipStream_t s = (hipStream_t)stream;
+    if (U) MHAR_HIP(hipMemcpyAsync(U, c->pc.U, (size_t)c->pc.n * c->pc.r * 8, hipMemcpyDeviceToDevice, s), "covariance copy");
+    if (ls) MHAR_HIP(hipMemcpyAsync(ls, c->pc.logsig, (size_t)c->pc.n * 8, hipMemcpyDeviceToDevice, s), "covariance copy");
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_loss(mhar_chains_t c, double* nll, double* gU, double* gls, void* stream)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
+    hipStream_t s = (hipStream_t)stream;
+    MHAR_HIP(launch_precond_grad(c->pc, c->X, s), "covariance gradient");
+    if (nll) MHAR_HIP(hipMemcpyAsync(nll, c->pc.nll, 8, hipMemcpyDeviceToDevice, s), "loss copy");
+    if (gU) MHAR_HIP(hipMemcpyAsync(gU, c->pc.gU, (size_t)c->pc.n * c->pc.r * 8, hipMemcpyDeviceToDevice, s), "gradient copy");
+    if (gls) MHAR_HIP(hipMemcpyAsync(gls, c->pc.gl, (size_t)c->pc.n * 8, hipMemcpyDeviceToDevice, s), "gradient copy");
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_train(mhar_chains_t c, int64_t steps, double lr, void* stream)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
+    if (c->pc_frozen) return fail(MHAR_E_STATE, "the covariance is frozen");
+    if (steps < 0 || !(lr > 0.0)) return fail(MHAR_E_INVALID_ARG, "need steps >= 0 and lr > 0");
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t k = 0; k < steps; ++k) {
+        mhar_status_t st = run_steps(c, 1, 0, nullptr, 0, 0, s);
+        if (st) return st;
+        MHAR_HIP(launch_precond_grad(c->pc, c->X, s), "covariance gradient");
+        c->pc_t += 1;
+        MHAR_HIP(launch_precond_adam(c->pc, c->pc_t, lr, 0.9, 0.999, 1e-8, s), "covariance update");
+    }
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_freeze(mhar_chains_t c)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
+    c->pc_frozen = 1;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_destroy(mhar_chains_t c)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (!c->pc_rank) return MHAR_OK;
+    c->pc_rank = 0;
+    c->pc_frozen = 0;
+    c->split = c->split_saved;
+    c->force_recompute = 1;
+    return MHAR_OK;
+}
+
+static size_t carve_batch(int count, int nunits, void* ws, mhar_batch* b)
+{
+    Carver c(ws);
+    StepArgs* d = c.take<StepArgs>(count);
+    int2* u = c.take<int2>(nunits);
+    unsigned* nx = c.take<unsigned>(64);
+    if (b) {
+        b->descs_dev = d;
+        b->units_dev = u;
+        b->next_dev = nx;
+    }
+    return c.used;
+}
+
+static mhar_status_t batch_units(int32_t count, const mhar_chains_t* chains, int* nunits, int* prec)
+{
+    if (count < 1 || !chains) return fail(MHAR_E_INVALID_ARG, "need count >= 1 and a chains array");
+    int total = 0;
+    for (int i = 0; i < count; ++i) {
+        if (!chains[i]) return fail(MHAR_E_INVALID_ARG, "NULL chains handle in the batch");
+        if (i > 0 && chains[i]->p->prec != chains[0]->p->prec)
+            return fail(MHAR_E_INVALID_ARG, "all problems of a batch must share one precision");
+        for (int j = 0; j < i; ++j)
+            if (chains[j] == chains[i]) return fail(MHAR_E_INVALID_ARG, "a chains handle appears twice");
+        total += chains[i]->z_pad / kChainTile;
+    }
+    *nunits = total;
+    *prec = chains[0]->p->prec;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_batch_workspace_size(int32_t count, const mhar_chains_t* chains, size_t* bytes)
+{
+    if (!bytes) return fail(MHAR_E_INVALID_ARG, "bytes is NULL");
+    int nunits = 0, prec = 0;
+    mhar_status_t st = batch_units(count, chains, &nunits, &prec);
+    if (st) return st;
+    *bytes = carve_batch(count, nunits, nullptr, nullptr);
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void* ws, size_t ws_bytes,
+                                mhar_batch_t* out)
+{
+    if (!out) return fail(MHAR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int nunits = 0, prec = 0;
+    mhar_status_t st = batch_units(count, chains, &nunits, &prec);
+    if (st) return st;
+    if (!ws || !aligned256(ws)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < carve_batch(count, nunits, nullptr, nullptr)) return fail(MHAR_E_WORKSPACE, "batch workspace too small");
+    mhar_batch* b = new mhar_batch{};
+    b->count = count;
+    b->prec = prec;
+    b->nunits = nunits;
+    carve_batch(count, nunits, ws, b);
+    b->max_lda = 0;
+    b->work_per_step = 0.0;
+    // units in decreasing order of cost (longest processing time first)
+    std::vector<std::pair<double, int2>> order;
+    for (int i = 0; i < count; ++i) {
+        mhar_chains* c = chains[i];
+        b->chains.push_back(c);
+        b->saved_split.push_back(c->split);
+        b->max_lda = std::max(b->max_lda, c->p->lda);
+        const double cost = (double)c->p->m_pad * c->p->lda;
+        for (int t = 0; t < c->z_pad / kChainTile; ++t) order.push_back({cost, int2{i, t}});
+        b->work_per_step += cost * c->z_pad;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) { return x.first > y.first; });
+    std::vector<int2> units(nunits);
+    for (int u = 0; u < nunits; ++u) units[u] = order[u].second;
+    auto cleanup = [&](mhar_status_t code) {
+        if (b->descs_host) hipHostFree(b->descs_host);
+        delete b;
+        return code;
+    };
+    hipError_t e = hipHostMalloc((void**)&b->descs_host, sizeof(StepArgs) * count, hipHostMallocDefault);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "pinned descriptor buffer"));
+    e = hipMemcpy(b->units_dev, units.data(), sizeof(int2) * nunits, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "batch setup"));
+    int dev = 0, cus = 1;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "device query"));
+    b->grid = std::min(nunits, cus * batch_blocks_per_cu(prec, b->max_lda));
+    // the batched launch runs the general kernel: resident handles switch over
+    for (mhar_chains* c : b->chains) {
+        if (c->split > 0) {
+            c->split = 0;
+            c->force_recompute = 1;
+        }
+    }
+    *out = b;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_batch_step(mhar_batch_t b, int64_t steps, void* stream_)
+{
+    if (!b) return fail(MHAR_E_INVALID_ARG, "batch is NULL");
+    if (steps < 0) return fail(MHAR_E_INVALID_ARG, "steps must be >= 0");
+    hipStream_t stream = (hipStream_t)stream_;
+    // bound one launch to ~2^39 row-walk-K products
+    int64_t chunk = (int64_t)((double)(int64_t(1) << 39) / std::max(b->work_per_step, 1.0));
+    chunk = std::min<int64_t>(std::max<int64_t>(chunk, 1), 1000);
+    int64_t done = 0;
+    while (done < steps) {
+        const int64_t k = std::min(chunk, steps - done);
+        if (b->copy_pending) MHAR_HIP(hipEventSynchronize(b->copied), "descriptor buffer reuse");
+        for (int i = 0; i < b->count; ++i) {
+            mhar_chains* c = b->chains[i];
+            int rf = 0;
+            if (c->force_recompute) {
+                rf = 1;
+                c->force_recompute = 0;
+                c->pending = 0;
+                c->T = 2;
+                c->since = 0;
+            }
+            StepArgs a = make_args(c);
+            a.steps = (int)k;
+            a.recompute_first = rf;
+            b->descs_host[i] = a;
+        }
+        MHAR_HIP(hipMemcpyAsync(b->descs_dev, b->descs_host, sizeof(StepArgs) * b->count,
+                                hipMemcpyHostToDevice, stream), "descriptor copy");
+        MHAR_HIP(hipEventRecord(b->copied, stream), "descriptor copy event");
+        b->copy_pending = true;
+        MHAR_HIP(launch_fill_i32((int*)b->next_dev, 1, 0, stream), "queue reset");
+        MHAR_HIP(launch_batch(b->prec, b->descs_dev, b->units_dev, b->nunits, b->next_dev, b->max_lda,
+                              b->grid, stream), "batched launch");
+        for (mhar_chains* c : b->chains) advance_schedule(c, k);
+        done += k;
+    }
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_batch_destroy(mhar_batch_t b)
+{
+    if (!b) return MHAR_OK;
+    if (b->copy_pending) hipEventSynchronize(b->copied);
+    for (int i = 0; i < b->count; ++i) {
+        mhar_chains* c = b->chains[i];
+        if (b->saved_split[i] > 0 && c->pc_rank == 0) {
+            c->split = b->saved_split[i];
+            c->force_recompute = 1;
+        }
+    }
+    hipEventDestroy(b->copied);
+    hipHostFree(b->descs_host);
+    delete b;
     return MHAR_OK;
 }
 

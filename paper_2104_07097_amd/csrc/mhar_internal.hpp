@@ -45,6 +45,10 @@ struct StepArgs {
     const float* absb;      // m_pad, |b_i| rounded up
     const double* Aeq;      // m_eq x lda
     const double* WT;       // m_eq x lda: rows of (A_eq A_eq^T)^{-1} A_eq
+    // learned direction covariance U U^T + diag(esig^2) (r = 0: isotropic)
+    int r;
+    const double* U;        // n x r
+    const double* esig;     // n, exp(log_sigma)
     // chains
     int z, z_pad;
     double* X;              // z_pad x lda
@@ -82,6 +86,10 @@ struct StepArgs {
 };
 
 size_t step_lds_bytes(int prec, int lda);
+// one persistent launch over (problem, walk tile) units of many problems
+hipError_t launch_batch(int prec, const StepArgs* descs, const int2* units, int nunits,
+                        unsigned* next, int max_lda, int grid, hipStream_t stream);
+int batch_blocks_per_cu(int prec, int max_lda);
 // register-resident kernel for small problems (FP32 / BF16X3, lda <= 256,
 // m_pad <= 16 x 512): number of workgroups per walk tile, 0 = not usable
 int resident_split(int prec, int lda, int m_pad, int z_pad);
@@ -110,5 +118,24 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long l
                            hipStream_t stream);
 hipError_t launch_export_flags(const int* flags, int z, int32_t* out, int clear_internal,
                                hipStream_t stream);
+
+// ---- learned preconditioner (direction covariance U U^T + diag(exp(2 l))) ----
+struct PrecondBufs {
+    int n, r, z, lda;
+    double *U, *logsig, *esig;          // covariance factor, log scales, exp(log scales)
+    double *V;                          // trained coordinates V = diag(exp(-l)) U (n x r)
+    double *m1V, *m2V, *m1l, *m2l;      // Adam moments of V and l
+    double *mean, *Sd, *W, *B, *H;      // n, n, n x r, z x r, n x r
+    double *GB, *C, *Cinv, *K;          // r x r each
+    double *gU, *gl, *rowterm, *nll;    // n x r, n, n, 2 (NLL, log det C)
+    int* status;
+};
+size_t precond_bytes(int n, int r, int z, int lda);
+void precond_carve(PrecondBufs* p, void* ws);
+hipError_t launch_precond_init(const PrecondBufs& p, uint64_t seed, hipStream_t stream);
+hipError_t launch_precond_set_scales(const PrecondBufs& p, hipStream_t stream);
+hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_t stream);
+hipError_t launch_precond_adam(const PrecondBufs& p, int64_t t, double lr, double b1, double b2,
+                               double eps, hipStream_t stream);
 
 }  // namespace mhar

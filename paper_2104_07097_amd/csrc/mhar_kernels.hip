@@ -92,6 +92,35 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, unsigned char* 
         drow[2 * p] = ev;
         if (2 * p + 1 < n) drow[2 * p + 1] = od;
     }
+    if (a.r > 0) {
+        // learned preconditioner: h <- U eps + exp(l) o h, eps ~ N(0, I_r)
+        // from the LOWRANK stream (sequential sum over the rank, no contraction)
+        __syncthreads();
+        double* eps = cs->y;
+        const int rpairs = (a.r + 1) >> 1;
+        for (int item = tid; item < kChainTile * rpairs; item += kThreads) {
+            int cl = item / rpairs, p = item - cl * rpairs;
+            int chain = c0 + cl;
+            if (chain >= a.z) continue;
+            Block4 w = stream_block(a.seed, kTagLowRank, a.chain_offset + (uint32_t)chain, step,
+                                    (uint32_t)p);
+            double ev, od;
+            gauss_pair(w, ev, od);
+            eps[cl * kMaxMeq + 2 * p] = ev;
+            if (2 * p + 1 < a.r) eps[cl * kMaxMeq + 2 * p + 1] = od;
+        }
+        __syncthreads();
+        for (int item = tid; item < kChainTile * n; item += kThreads) {
+            int cl = item / n, j = item - cl * n;
+            int chain = c0 + cl;
+            if (chain >= a.z) continue;
+            const double* ur = a.U + (size_t)j * a.r;
+            double v = 0.0;
+            for (int q = 0; q < a.r; ++q) v = __dadd_rn(v, __dmul_rn(ur[q], eps[cl * kMaxMeq + q]));
+            double* dp = a.D + (size_t)chain * lda + j;
+            *dp = __dadd_rn(v, __dmul_rn(a.esig[j], *dp));
+        }
+    }
     if (a.m_eq > 0) {
         __syncthreads();
         // y = A_eq h for every walk; one wave per (walk, equality row)
@@ -196,22 +225,36 @@ __device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int 
             const float* Dt = (const float*)big;
             const int ld = f32_ld(lda);
             f32x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-            for (int k0 = 0; k0 < lda; k0 += 32) {
-                const float4* bp = (const float4*)(Dt + c * ld + k0 + 8 * g);
-                float4 b0 = bp[0], b1 = bp[1];
+            // A chunks are prefetched one chunk ahead (register double buffer)
+            float4 cur[8], nxt[8];
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    const float4* ap = (const float4*)(a.A32 + (size_t)(row0 + 16 * rb + c) * lda + k0 + 8 * g);
-                    float4 a0 = ap[0], a1 = ap[1];
-                    acc[rb] = mma_f32(a0.x, b0.x, acc[rb]);
-                    acc[rb] = mma_f32(a0.y, b0.y, acc[rb]);
-                    acc[rb] = mma_f32(a0.z, b0.z, acc[rb]);
-                    acc[rb] = mma_f32(a0.w, b0.w, acc[rb]);
-                    acc[rb] = mma_f32(a1.x, b1.x, acc[rb]);
-                    acc[rb] = mma_f32(a1.y, b1.y, acc[rb]);
-                    acc[rb] = mma_f32(a1.z, b1.z, acc[rb]);
-                    acc[rb] = mma_f32(a1.w, b1.w, acc[rb]);
+            for (int rb = 0; rb < 4; ++rb) {
+                const float4* ap = (const float4*)(a.A32 + (size_t)(row0 + 16 * rb + c) * lda + 8 * g);
+                cur[2 * rb] = ap[0];
+                cur[2 * rb + 1] = ap[1];
+            }
+            for (int k0 = 0; k0 < lda; k0 += 32) {
+                if (k0 + 32 < lda) {
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const float4* ap = (const float4*)(a.A32 + (size_t)(row0 + 16 * rb + c) * lda + k0 + 32 + 8 * g);
+                        nxt[2 * rb] = ap[0];
+                        nxt[2 * rb + 1] = ap[1];
+                    }
                 }
+                const float4* bp = (const float4*)(Dt + c * ld + k0 + 8 * g);
+                const float4 b0 = bp[0], b1 = bp[1];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float bv = e < 4 ? (&b0.x)[e] : (&b1.x)[e - 4];
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const float av = e < 4 ? (&cur[2 * rb].x)[e] : (&cur[2 * rb + 1].x)[e - 4];
+                        acc[rb] = mma_f32(av, bv, acc[rb]);
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
             }
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
@@ -222,18 +265,33 @@ __device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int 
             const int ld = bf_ld(lda);
             const __bf16* Dl = Dh + kChainTile * ld;
             f32x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
-            for (int k0 = 0; k0 < lda; k0 += 32) {
-                bf16x8 bh = *(const bf16x8*)(Dh + c * ld + k0 + 8 * g);
-                bf16x8 bl = *(const bf16x8*)(Dl + c * ld + k0 + 8 * g);
+            // A chunks are prefetched one chunk ahead (register double buffer)
+            bf16x8 cur[8], nxt[8];
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    size_t off = (size_t)(row0 + 16 * rb + c) * lda + k0 + 8 * g;
-                    bf16x8 ah = *(const bf16x8*)(a.Ahi + off);
-                    bf16x8 al = *(const bf16x8*)(a.Alo + off);
-                    acc[rb] = mma_bf16(al, bh, acc[rb]);
-                    acc[rb] = mma_bf16(ah, bl, acc[rb]);
-                    acc[rb] = mma_bf16(ah, bh, acc[rb]);
+            for (int rb = 0; rb < 4; ++rb) {
+                const size_t off = (size_t)(row0 + 16 * rb + c) * lda + 8 * g;
+                cur[2 * rb] = *(const bf16x8*)(a.Ahi + off);
+                cur[2 * rb + 1] = *(const bf16x8*)(a.Alo + off);
+            }
+            for (int k0 = 0; k0 < lda; k0 += 32) {
+                if (k0 + 32 < lda) {
+#pragma unroll
+                    for (int rb = 0; rb < 4; ++rb) {
+                        const size_t off = (size_t)(row0 + 16 * rb + c) * lda + k0 + 32 + 8 * g;
+                        nxt[2 * rb] = *(const bf16x8*)(a.Ahi + off);
+                        nxt[2 * rb + 1] = *(const bf16x8*)(a.Alo + off);
+                    }
                 }
+                const bf16x8 bh = *(const bf16x8*)(Dh + c * ld + k0 + 8 * g);
+                const bf16x8 bl = *(const bf16x8*)(Dl + c * ld + k0 + 8 * g);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) acc[rb] = mma_bf16(cur[2 * rb + 1], bh, acc[rb]);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) acc[rb] = mma_bf16(cur[2 * rb], bl, acc[rb]);
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) acc[rb] = mma_bf16(cur[2 * rb], bh, acc[rb]);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) cur[q] = nxt[q];
             }
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
@@ -503,14 +561,14 @@ __device__ void recompute_slack(const StepArgs& a, ChainLds* cs, unsigned char* 
     __syncthreads();
 }
 
+// All `a.steps` steps of walk tile `tile` of one problem (the slack, the last
+// screening product and the lower bounds stay in HBM between steps).
 template <int P>
-__global__ __launch_bounds__(kThreads) void mhar_steps_kernel(StepArgs a)
+__device__ void run_tile(const StepArgs& a, unsigned char* smem, int tile)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     unsigned char* big = smem;
     ChainLds* cs = (ChainLds*)(smem + big_bytes(a.lda));
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x;
     const int c0 = tile * kChainTile;
 
     if (tid < kChainTile) {
@@ -558,6 +616,35 @@ __global__ __launch_bounds__(kThreads) void mhar_steps_kernel(StepArgs a)
         if (cs->flags[tid] && chain < a.z) atomicOr(&a.flags[chain], cs->flags[tid]);
     }
     if (tid == 0 && cs->exact) atomicAdd(&a.counters[0], cs->exact);
+    __syncthreads();
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void mhar_steps_kernel(StepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    run_tile<P>(a, smem, blockIdx.x);
+}
+
+// Many problems in one persistent launch: workgroups take (problem, walk
+// tile) units from a queue ordered by decreasing cost (longest processing
+// time first) through a device counter, and leave when the queue is empty.
+template <int P>
+__global__ __launch_bounds__(kThreads) void mhar_batch_kernel(const StepArgs* __restrict__ descs,
+                                                              const int2* __restrict__ units,
+                                                              int nunits, unsigned* next)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int unit_lds;
+    while (true) {
+        if (threadIdx.x == 0) unit_lds = (int)atomicAdd(next, 1u);
+        __syncthreads();
+        const int u = unit_lds;
+        __syncthreads();
+        if (u >= nunits) break;
+        const int2 w = units[u];
+        run_tile<P>(descs[w.x], smem, w.y);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -751,16 +838,52 @@ template <int P>
 static hipError_t launch_steps_t(const StepArgs& a, hipStream_t stream)
 {
     const size_t lds = step_lds_bytes(P, a.lda);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)mhar_steps_kernel<P>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    hipError_t e = hipFuncSetAttribute((const void*)mhar_steps_kernel<P>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mhar_steps_kernel<P>, dim3(a.z_pad / kChainTile), dim3(kThreads), lds,
                        stream, a);
     return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_batch_t(const StepArgs* descs, const int2* units, int nunits,
+                                 unsigned* next, int max_lda, int grid, hipStream_t stream)
+{
+    const size_t lds = step_lds_bytes(P, max_lda);
+    // the kernel also has a few bytes of static LDS: request only what is used
+    hipError_t e = hipFuncSetAttribute((const void*)mhar_batch_kernel<P>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mhar_batch_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, descs, units,
+                       nunits, next);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(int prec, const StepArgs* descs, const int2* units, int nunits,
+                        unsigned* next, int max_lda, int grid, hipStream_t stream)
+{
+    switch (prec) {
+    case kFP64: return launch_batch_t<kFP64>(descs, units, nunits, next, max_lda, grid, stream);
+    case kFP32: return launch_batch_t<kFP32>(descs, units, nunits, next, max_lda, grid, stream);
+    case kBF16X3: return launch_batch_t<kBF16X3>(descs, units, nunits, next, max_lda, grid, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int batch_blocks_per_cu(int prec, int max_lda)
+{
+    int nb = 0;
+    const size_t lds = step_lds_bytes(prec, max_lda);
+    const void* fn = prec == kFP64 ? (const void*)mhar_batch_kernel<kFP64>
+                   : prec == kFP32 ? (const void*)mhar_batch_kernel<kFP32>
+                                   : (const void*)mhar_batch_kernel<kBF16X3>;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();   // do not leave a stale error for the next launch
+        return 1;
+    }
+    return nb < 1 ? 1 : nb;
 }
 
 hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream)

@@ -1,0 +1,390 @@
+// mhar_precond.hip -- learned direction covariance for MHAR (FP64).
+//
+// The directions of the walks are drawn as d = P (U eps + exp(l) o h) with
+// eps ~ N(0, I_r), h ~ N(0, I_n): Gaussian with covariance
+// Sigma = U U^T + diag(exp(2 l)), symmetric and independent of the state,
+// so every hit-and-run step keeps the uniform law on the polytope.  During
+// burn-in (U, l) are fitted to the walk states by Adam on the Gaussian
+// negative log-likelihood
+//     NLL = 1/2 log det Sigma + 1/2 tr(Sigma^{-1} S),
+// S the (1/z) covariance of the z states about their mean, then frozen: a
+// fit of Sigma to the covariance of the target brings the body towards the
+// near-isotropic position the paper's cost analysis assumes (S3.1).
+//
+// With D = diag(exp(2 l)), W = D^{-1} U, C = I + U^T W (r x r), Y the
+// centred states (z x n), B = Y W (z x r), H = Y^T B / z, G = B^T B / z and
+// K = I + C^{-1} G (Woodbury and the determinant lemma):
+//     NLL  = sum_i (l_i + S_ii exp(-2 l_i)/2) + log det C / 2 - tr(C^{-1} G) / 2
+//     dU   = (W K - D^{-1} H) C^{-1}
+//     dl_i = exp(2 l_i) [ (Sigma^{-1})_ii - (Sigma^{-1} S Sigma^{-1})_ii ],
+//     (Sigma^{-1})_ii = exp(-2 l_i) - sum_a V_ia W_ia,  V = W C^{-1},
+//     (Sigma^{-1} S Sigma^{-1})_ii = exp(-4 l_i) S_ii - 2 exp(-2 l_i) sum_a V_ia H_ia
+//                                    + sum_ab V_ia V_ib G_ab.
+// Only n x r, z x r and r x r quantities are formed.
+#include <math.h>
+
+#include "mhar_device.hpp"
+#include "mhar_internal.hpp"
+
+namespace mhar {
+
+namespace {
+
+constexpr uint32_t kTagTrain = 4;
+
+__global__ void precond_init_kernel(int n, int r, uint64_t seed, double* U, double* V,
+                                    double* logsig, double* esig, double* m1V, double* m2V,
+                                    double* m1l, double* m2l)
+{
+    const int64_t total = (int64_t)n * r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / r), q = (int)(e - (int64_t)j * r);
+        Block4 w = stream_block(seed, kTagTrain, (uint32_t)j, 0, (uint32_t)(q >> 1));
+        double ev, od;
+        gauss_pair(w, ev, od);
+        U[e] = 0.01 * ((q & 1) ? od : ev);
+        V[e] = U[e];   // log scales start at 0
+        m1V[e] = 0.0;
+        m2V[e] = 0.0;
+    }
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        logsig[j] = 0.0;
+        esig[j] = 1.0;
+        m1l[j] = 0.0;
+        m2l[j] = 0.0;
+    }
+}
+
+// scales of a caller-given (U, l): exp(l) and the trained coordinates V = U / exp(l)
+__global__ void scales_kernel(int n, int r, const double* U, const double* logsig, double* esig,
+                              double* V)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+        const double e = exp(logsig[j]);
+        esig[j] = e;
+        for (int q = 0; q < r; ++q) V[(int64_t)j * r + q] = U[(int64_t)j * r + q] / e;
+    }
+}
+
+// column means and (1/z) variances of the states
+__global__ void mean_sd_kernel(int n, int z, int lda, const double* __restrict__ X, double* mean,
+                               double* Sd)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int k = 0; k < z; ++k) s += X[(size_t)k * lda + i];
+    const double mu = s / z;
+    double v = 0.0;
+    for (int k = 0; k < z; ++k) {
+        const double y = X[(size_t)k * lda + i] - mu;
+        v = fma(y, y, v);
+    }
+    mean[i] = mu;
+    Sd[i] = v / z;
+}
+
+__global__ void w_kernel(int n, int r, const double* U, const double* logsig, double* W)
+{
+    const int64_t total = (int64_t)n * r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / r);
+        W[e] = U[e] * exp(-2.0 * logsig[j]);
+    }
+}
+
+// B[k][q] = sum_i (X[k][i] - mean_i) W[i][q]: one block per state, one lane per rank column
+__global__ void b_kernel(int n, int r, int lda, const double* __restrict__ X,
+                         const double* __restrict__ mean, const double* __restrict__ W, double* B)
+{
+    const int k = blockIdx.x, q = threadIdx.x;
+    if (q >= r) return;
+    const double* xr = X + (size_t)k * lda;
+    double v = 0.0;
+    for (int i = 0; i < n; ++i) v = fma(xr[i] - mean[i], W[(size_t)i * r + q], v);
+    B[(size_t)k * r + q] = v;
+}
+
+// H[i][q] = (1/z) sum_k (X[k][i] - mean_i) B[k][q]: one block per coordinate
+__global__ void h_kernel(int n, int r, int z, int lda, const double* __restrict__ X,
+                         const double* __restrict__ mean, const double* __restrict__ B, double* H)
+{
+    const int i = blockIdx.x, q = threadIdx.x;
+    if (q >= r) return;
+    const double mu = mean[i];
+    double v = 0.0;
+    for (int k = 0; k < z; ++k) v = fma(X[(size_t)k * lda + i] - mu, B[(size_t)k * r + q], v);
+    H[(size_t)i * r + q] = v / z;
+}
+
+// G = B^T B / z and C = I + U^T W, one thread per (p, q)
+__global__ void gc_kernel(int n, int r, int z, const double* __restrict__ B,
+                          const double* __restrict__ U, const double* __restrict__ W, double* G,
+                          double* C)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r * r) return;
+    const int p = e / r, q = e - p * r;
+    double g = 0.0;
+    for (int k = 0; k < z; ++k) g = fma(B[(size_t)k * r + p], B[(size_t)k * r + q], g);
+    G[e] = g / z;
+    double c = (p == q) ? 1.0 : 0.0;
+    for (int i = 0; i < n; ++i) c = fma(U[(size_t)i * r + p], W[(size_t)i * r + q], c);
+    C[e] = c;
+}
+
+// Cholesky of C (r <= 64), log det C, C^{-1}, K = I + C^{-1} G; one workgroup
+__global__ void chol_kernel(int r, const double* C, const double* G, double* Cinv, double* K,
+                            double* logdet, int* status)
+{
+    __shared__ double L[kMaxMeq * kMaxMeq];
+    __shared__ int bad;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < r * r; e += nt) L[e] = C[e];
+    __syncthreads();
+    if (tid == 0) {
+        bad = 0;
+        double ld = 0.0;
+        for (int j = 0; j < r && !bad; ++j) {
+            double piv = L[j * r + j];
+            for (int k = 0; k < j; ++k) piv -= L[j * r + k] * L[j * r + k];
+            if (!(piv > 0.0)) {
+                bad = 1;
+                break;
+            }
+            const double ljj = sqrt(piv);
+            L[j * r + j] = ljj;
+            ld += 2.0 * log(ljj);
+            for (int i = j + 1; i < r; ++i) {
+                double v = L[i * r + j];
+                for (int k = 0; k < j; ++k) v -= L[i * r + k] * L[j * r + k];
+                L[i * r + j] = v / ljj;
+            }
+        }
+        *logdet = ld;
+        *status = bad;
+    }
+    __syncthreads();
+    if (bad) return;
+    // column q of C^{-1}: solve L L^T y = e_q
+    for (int q = tid; q < r; q += nt) {
+        double y[kMaxMeq];
+        for (int i = 0; i < r; ++i) {
+            double v = (i == q) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= L[i * r + k] * y[k];
+            y[i] = v / L[i * r + i];
+        }
+        for (int i = r - 1; i >= 0; --i) {
+            double v = y[i];
+            for (int k = i + 1; k < r; ++k) v -= L[k * r + i] * y[k];
+            y[i] = v / L[i * r + i];
+        }
+        for (int i = 0; i < r; ++i) Cinv[i * r + q] = y[i];
+    }
+    __syncthreads();
+    for (int e = tid; e < r * r; e += nt) {
+        const int p = e / r, q = e - p * r;
+        double v = (p == q) ? 1.0 : 0.0;
+        for (int k = 0; k < r; ++k) v = fma(Cinv[p * r + k], G[k * r + q], v);
+        K[e] = v;
+    }
+}
+
+// per coordinate i: dU row, dl_i and the row's NLL term; one block of 64 lanes per row
+__global__ void grad_kernel(int n, int r, const double* __restrict__ W, const double* __restrict__ H,
+                            const double* __restrict__ K, const double* __restrict__ Cinv,
+                            const double* __restrict__ G, const double* __restrict__ logsig,
+                            const double* __restrict__ Sd, double* gU, double* gl, double* rowterm)
+{
+    __shared__ double R[kMaxMeq], V[kMaxMeq], Wr[kMaxMeq], Hr[kMaxMeq];
+    const int i = blockIdx.x, q = threadIdx.x;
+    const double dinv = exp(-2.0 * logsig[i]);
+    if (q < r) {
+        Wr[q] = W[(size_t)i * r + q];
+        Hr[q] = H[(size_t)i * r + q];
+    }
+    __syncthreads();
+    if (q < r) {
+        double v = 0.0, w = 0.0;
+        for (int c = 0; c < r; ++c) {
+            v = fma(Wr[c], K[c * r + q], v);
+            w = fma(Wr[c], Cinv[c * r + q], w);
+        }
+        R[q] = v - dinv * Hr[q];
+        V[q] = w;
+    }
+    __syncthreads();
+    if (q < r) {
+        double v = 0.0;
+        for (int b = 0; b < r; ++b) v = fma(R[b], Cinv[b * r + q], v);
+        gU[(size_t)i * r + q] = v;
+    }
+    if (q == 0) {
+        double vw = 0.0, vh = 0.0, vgv = 0.0;
+        for (int a = 0; a < r; ++a) {
+            vw = fma(V[a], Wr[a], vw);
+            vh = fma(V[a], Hr[a], vh);
+            double t = 0.0;
+            for (int b = 0; b < r; ++b) t = fma(G[a * r + b], V[b], t);
+            vgv = fma(V[a], t, vgv);
+        }
+        const double sinv = dinv - vw;
+        const double sss = dinv * dinv * Sd[i] - 2.0 * dinv * vh + vgv;
+        gl[i] = (sinv - sss) / dinv;
+        rowterm[i] = logsig[i] + 0.5 * Sd[i] * dinv;
+    }
+}
+
+// NLL = sum_i rowterm_i + log det C / 2 - tr(C^{-1} G) / 2 (fixed summation order)
+__global__ void nll_kernel(int n, int r, const double* rowterm, const double* Cinv,
+                           const double* G, const double* logdet, double* nll)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += rowterm[i];
+    double tr = 0.0;
+    for (int p = 0; p < r; ++p)
+        for (int q = 0; q < r; ++q) tr = fma(Cinv[p * r + q], G[q * r + p], tr);
+    *nll = s + 0.5 * (*logdet) - 0.5 * tr;
+}
+
+// One Adam (Kingma & Ba) update in the scale-free coordinates (V, l), U = diag(exp(l)) V.
+// With gU, gl the NLL gradient in (U, l), the chain rule gives dV = exp(l) o gU (row scale)
+// and dl = gl + sum_q gU o U (each row).  Gradients in (V, l) are O(1) whatever the axis
+// lengths, which keeps Adam's per-entry step from swamping the weak pull on long axes.
+// One thread per coordinate row; after the update U = exp(l_new) o V_new.
+__global__ void adam_kernel(int n, int r, int64_t t, double lr, double b1, double b2, double eps,
+                            double* U, double* V, const double* gU, double* m1V, double* m2V,
+                            double* logsig, const double* gl, double* m1l, double* m2l,
+                            double* esig)
+{
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int64_t row = (int64_t)i * r;
+        const double e = esig[i];
+        double g = gl[i];
+        for (int q = 0; q < r; ++q) g = __dadd_rn(g, __dmul_rn(gU[row + q], U[row + q]));
+        for (int q = 0; q < r; ++q) {
+            const int64_t k = row + q;
+            const double gv = __dmul_rn(gU[k], e);
+            m1V[k] = b1 * m1V[k] + (1.0 - b1) * gv;
+            m2V[k] = b2 * m2V[k] + (1.0 - b2) * gv * gv;
+            V[k] -= lr * (m1V[k] / c1) / (sqrt(m2V[k] / c2) + eps);
+        }
+        m1l[i] = b1 * m1l[i] + (1.0 - b1) * g;
+        m2l[i] = b2 * m2l[i] + (1.0 - b2) * g * g;
+        logsig[i] -= lr * (m1l[i] / c1) / (sqrt(m2l[i] / c2) + eps);
+        const double en = exp(logsig[i]);
+        esig[i] = en;
+        for (int q = 0; q < r; ++q) U[row + q] = __dmul_rn(en, V[row + q]);
+    }
+}
+
+inline int blocks_for(int64_t total, int threads)
+{
+    int64_t b = (total + threads - 1) / threads;
+    return (int)(b < 1 ? 1 : (b > 65535 ? 65535 : b));
+}
+
+}  // namespace
+
+size_t precond_bytes(int n, int r, int z, int lda)
+{
+    (void)lda;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t nr = (size_t)n * r, rr = (size_t)r * r;
+    size_t b = 0;
+    b += 5 * al(nr * 8);              // U, m1V, m2V, W, H
+    b += 2 * al(nr * 8);              // gU, V
+    b += 8 * al((size_t)n * 8);       // logsig, esig, m1l, m2l, mean, Sd, gl, rowterm
+    b += al((size_t)z * r * 8);       // B
+    b += 4 * al(rr * 8);              // G, C, Cinv, K
+    b += al(64);                      // nll, logdet
+    b += al(64);                      // status
+    return b;
+}
+
+void precond_carve(PrecondBufs* p, void* ws)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    char* b = (char*)ws;
+    size_t o = 0;
+    const size_t nr = (size_t)p->n * p->r, rr = (size_t)p->r * p->r;
+    auto take = [&](size_t bytes) {
+        char* q = b + o;
+        o += al(bytes);
+        return q;
+    };
+    p->U = (double*)take(nr * 8);
+    p->m1V = (double*)take(nr * 8);
+    p->m2V = (double*)take(nr * 8);
+    p->W = (double*)take(nr * 8);
+    p->H = (double*)take(nr * 8);
+    p->gU = (double*)take(nr * 8);
+    p->V = (double*)take(nr * 8);
+    p->logsig = (double*)take((size_t)p->n * 8);
+    p->esig = (double*)take((size_t)p->n * 8);
+    p->m1l = (double*)take((size_t)p->n * 8);
+    p->m2l = (double*)take((size_t)p->n * 8);
+    p->mean = (double*)take((size_t)p->n * 8);
+    p->Sd = (double*)take((size_t)p->n * 8);
+    p->gl = (double*)take((size_t)p->n * 8);
+    p->rowterm = (double*)take((size_t)p->n * 8);
+    p->B = (double*)take((size_t)p->z * p->r * 8);
+    p->GB = (double*)take(rr * 8);
+    p->C = (double*)take(rr * 8);
+    p->Cinv = (double*)take(rr * 8);
+    p->K = (double*)take(rr * 8);
+    p->nll = (double*)take(64);
+    p->status = (int*)take(64);
+}
+
+hipError_t launch_precond_init(const PrecondBufs& p, uint64_t seed, hipStream_t stream)
+{
+    hipLaunchKernelGGL(precond_init_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0,
+                       stream, p.n, p.r, seed, p.U, p.V, p.logsig, p.esig, p.m1V, p.m2V, p.m1l, p.m2l);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_set_scales(const PrecondBufs& p, hipStream_t stream)
+{
+    hipLaunchKernelGGL(scales_kernel, dim3(blocks_for(p.n, 64)), dim3(64), 0, stream, p.n, p.r, p.U,
+                       p.logsig, p.esig, p.V);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_t stream)
+{
+    double* rowterm = p.rowterm;
+    hipLaunchKernelGGL(mean_sd_kernel, dim3(blocks_for(p.n, 64)), dim3(64), 0, stream, p.n, p.z,
+                       p.lda, X, p.mean, p.Sd);
+    hipLaunchKernelGGL(w_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0, stream,
+                       p.n, p.r, p.U, p.logsig, p.W);
+    hipLaunchKernelGGL(b_kernel, dim3(p.z), dim3(64), 0, stream, p.n, p.r, p.lda, X, p.mean, p.W,
+                       p.B);
+    hipLaunchKernelGGL(h_kernel, dim3(p.n), dim3(64), 0, stream, p.n, p.r, p.z, p.lda, X, p.mean,
+                       p.B, p.H);
+    hipLaunchKernelGGL(gc_kernel, dim3(blocks_for(p.r * p.r, 64)), dim3(64), 0, stream, p.n, p.r,
+                       p.z, p.B, p.U, p.W, p.GB, p.C);
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, stream, p.r, p.C, p.GB, p.Cinv, p.K,
+                       p.nll + 1, p.status);
+    hipLaunchKernelGGL(grad_kernel, dim3(p.n), dim3(64), 0, stream, p.n, p.r, p.W, p.H, p.K, p.Cinv,
+                       p.GB, p.logsig, p.Sd, p.gU, p.gl, rowterm);
+    hipLaunchKernelGGL(nll_kernel, dim3(1), dim3(64), 0, stream, p.n, p.r, rowterm, p.Cinv, p.GB,
+                       p.nll + 1, p.nll);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_adam(const PrecondBufs& p, int64_t t, double lr, double b1, double b2,
+                               double eps, hipStream_t stream)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(p.n, 64)), dim3(64), 0, stream, p.n, p.r, t,
+                       lr, b1, b2, eps, p.U, p.V, p.gU, p.m1V, p.m2V, p.logsig, p.gl, p.m1l, p.m2l,
+                       p.esig);
+    return hipGetLastError();
+}
+
+}  // namespace mhar

@@ -7,18 +7,22 @@
 // leaves the chip between steps:
 //   * the slack tile (rows of this workgroup x 16 walks) lives in registers
 //     and is updated eagerly (s <- s - theta g) as soon as theta is known;
-//   * the states X and directions D of the 16 walks live in LDS as FP64;
-//   * the screening product G stays in the accumulators of the step;
+//   * the states X and directions D of the 16 walks live in LDS as FP64,
+//     D double-buffered: the directions of step t+1 (independent of the
+//     state) are generated while the workgroup waits at the group barrier
+//     of step t;
+//   * the screening product G stays in the accumulators of the step; row
+//     norms and |b| of the workgroup's rows are cached in LDS;
 //   * candidate rows for the exact evaluation are staged into LDS with
 //     wide loads, then each lane runs one sequential FP64 dot product;
 //   * A is streamed with a register double buffer over a fully unrolled
-//     (row block, K chunk) loop;
+//     K loop;
 //   * the rows of a walk tile are split over `split` workgroups of 512
-//     rows each (one per CU); per step they combine the certified bounds
-//     and the exact chord ends of their walks through device-scope atomics
-//     at two group barriers.  The grid is launched cooperatively, so all
-//     workgroups of a group are resident; every wait is bounded in time and
-//     raises an error flag instead of hanging.
+//     rows each (one per CU); each screens its rows with its own certified
+//     bounds, and the group combines the exact chord ends of its walks
+//     through device-scope atomics at one barrier per step.  The grid is
+//     launched cooperatively, so all workgroups of a group are resident;
+//     every wait is bounded in time and raises an error flag.
 #include <math.h>
 
 #include "mhar_device.hpp"
@@ -29,12 +33,12 @@ namespace mhar {
 namespace {
 
 constexpr int kCandBatch = 8;  // most candidate rows staged per wave per batch
-__host__ __device__ constexpr int cand_batch(int lda) { return lda <= 128 ? 8 : 4; }
+constexpr int kRowsPerWg = kWaves * kRowGroup;
 
 struct ResLds {
     double theta[kChainTile];
     double E[kChainTile];
-    double dnorm[kChainTile];
+    double dnorm[2][kChainTile];
     double y[kChainTile * kMaxMeq];
     unsigned long long lmax_bits[kChainTile];   // exact lambda_max >= 0 as ordered bits
     unsigned long long nlmin_bits[kChainTile];  // exact -lambda_min >= 0 as ordered bits
@@ -44,51 +48,61 @@ struct ResLds {
     int cand_row[kWaves][kCandBatch];
     int cand_chain[kWaves][kCandBatch];
     unsigned long long mask[kWaves][16];   // candidate ballots of each wave's 16 output slots
+    float rownorm[kRowsPerWg];
+    float absb[kRowsPerWg];
     unsigned long long exact;
     int ok;
 };
 
-__host__ __device__ inline int res_xld(int lda) { return lda + 2; }
-__host__ __device__ inline int res_fld(int lda) { return lda + 4; }
-__host__ __device__ inline int res_bld(int lda) { return lda + 8; }
-
 struct ResLayout {
     size_t x_off, d_off, op_off, cb_off, st_off, total;
+    int cb_rows;  // candidate rows staged per wave
 };
 
+__host__ __device__ constexpr size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// LDS layout for a padded row length lda; the candidate buffer takes what
+// is left of the 160 KB (at most kCandBatch rows per wave).
 __host__ __device__ inline ResLayout res_layout(int prec, int lda)
 {
     ResLayout L;
-    size_t o = 0;
-    auto al = [](size_t v) { return (v + 15) & ~(size_t)15; };
-    L.x_off = o;
-    o = al(o + (size_t)kChainTile * res_xld(lda) * 8);
-    L.d_off = o;
-    o = al(o + (size_t)kChainTile * res_xld(lda) * 8);
-    L.op_off = o;
-    if (prec == kFP32) o = al(o + (size_t)kChainTile * res_fld(lda) * 4);
-    else o = al(o + (size_t)2 * kChainTile * res_bld(lda) * 2);
-    L.cb_off = o;
-    o = al(o + (size_t)kWaves * cand_batch(lda) * lda * 8);
-    L.st_off = o;
-    o = al(o + sizeof(ResLds));
-    L.total = o;
+    const size_t tile64 = al16((size_t)kChainTile * (lda + 2) * 8);
+    L.x_off = 0;
+    L.d_off = tile64;                      // two direction buffers
+    L.op_off = L.d_off + 2 * tile64;
+    const size_t op = prec == kFP32 ? al16((size_t)kChainTile * (lda + 4) * 4)
+                                    : al16((size_t)2 * kChainTile * (lda + 8) * 2);
+    L.cb_off = L.op_off + op;
+    const size_t st = al16(sizeof(ResLds));
+    const size_t budget = 163840;
+    const size_t used = L.cb_off + st;
+    const size_t per_row = (size_t)kWaves * lda * 8;
+    int rows = used < budget ? (int)((budget - used) / per_row) : 0;
+    if (rows > kCandBatch) rows = kCandBatch;
+    L.cb_rows = rows;
+    L.st_off = L.cb_off + al16((size_t)rows * per_row);
+    L.total = L.st_off + st;
     return L;
 }
 
-// Group barrier of the `split` workgroups that share a walk tile.  All
-// exchange traffic uses relaxed device-scope atomics, which are performed at
-// the device coherence point; a thread only arrives after the atomics it
-// issued have returned (their results are consumed), so no device-scope
-// fence is needed (such fences write back and invalidate the XCD's L2).
-// The wait is bounded by ~1 s of wall clock; returns false if it timed out
-// or another group failed.
-__device__ bool group_barrier(unsigned* cnt, unsigned target, int* err, int* ok_lds)
+// Group barrier of the `split` workgroups that share a walk tile, in two
+// halves so that independent work can run between them.  All exchange
+// traffic uses relaxed device-scope atomics, which are performed at the
+// device coherence point; a thread only arrives after the atomics it issued
+// have returned (their results are consumed), so no device-scope fence is
+// needed (such fences write back and invalidate the XCD's L2).
+__device__ void group_arrive(unsigned* cnt)
 {
     __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (bounded by ~1 s of wall clock) until `target` arrivals; returns
+// false if the wait timed out or another group failed.
+__device__ bool group_wait(unsigned* cnt, unsigned target, int* err, int* ok_lds)
+{
     if (threadIdx.x == 0) {
         int ok = 1;
-        __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t t0 = wall_clock64();
         while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
@@ -115,11 +129,13 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
     constexpr int lda = NK * 32;
     const ResLayout LY = res_layout(P, lda);
     double* Xt = (double*)(smem + LY.x_off);
-    double* Dt = (double*)(smem + LY.d_off);
+    double* Dbuf = (double*)(smem + LY.d_off);
     unsigned char* op = smem + LY.op_off;
     double* Cb = (double*)(smem + LY.cb_off);
     ResLds* cs = (ResLds*)(smem + LY.st_off);
+    const int CB = LY.cb_rows;
     constexpr int xld = lda + 2;
+    constexpr int dstride = (int)(al16((size_t)kChainTile * xld * 8) / 8);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
@@ -137,7 +153,8 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
     }
     const int c0 = tile * kChainTile;
     const int n = a.n, m = a.m, m_pad = a.m_pad;
-    const int row0 = slice * kWaves * kRowGroup + wave * kRowGroup;  // this wave's 64 rows
+    const int rbase = slice * kRowsPerWg;
+    const int row0 = rbase + wave * kRowGroup;  // this wave's 64 rows
     const bool rows_live = row0 < m_pad;
     const bool active_c = (c0 + c) < a.z;
     unsigned long long* gL = a.gL + (size_t)tile * 3 * 2 * kChainTile;
@@ -145,12 +162,18 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
     unsigned nbar = 0;
     const double u64 = 0x1.0p-53;
 
-    // ---- load the tile state ----
+    // ---- load the tile state and the row constants ----
     for (int item = tid; item < kChainTile * xld; item += kThreads) {
         const int cl = item / xld, j = item - cl * xld;
         const int chain = c0 + cl;
         Xt[item] = (chain < a.z && j < n) ? a.X[(size_t)chain * a.lda + j] : 0.0;
-        Dt[item] = 0.0;
+        Dbuf[item] = 0.0;
+        Dbuf[dstride + item] = 0.0;
+    }
+    for (int i = tid; i < kRowsPerWg; i += kThreads) {
+        const int row = rbase + i;
+        cs->rownorm[i] = row < m_pad ? a.rownorm[row] : 0.0f;
+        cs->absb[i] = row < m_pad ? a.absb[row] : 0.0f;
     }
     if (tid < kChainTile) {
         cs->theta[tid] = a.theta[c0 + tid];
@@ -160,9 +183,75 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
     if (tid == 0) cs->exact = 0;
     __syncthreads();
 
+    // directions of global step `step` into buffer `buf`, plus their norms
+    // and the matrix-core operand tile
+    auto make_directions = [&](uint64_t step, int buf) __attribute__((always_inline)) {
+        double* Dt = Dbuf + buf * dstride;
+        const int npairs = (n + 1) >> 1;
+        for (int item = tid; item < kChainTile * npairs; item += kThreads) {
+            const int cl = item / npairs, p = item - cl * npairs;
+            const int chain = c0 + cl;
+            if (chain >= a.z) continue;
+            Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step, (uint32_t)p);
+            double ev, od;
+            gauss_pair(w, ev, od);
+            Dt[cl * xld + 2 * p] = ev;
+            if (2 * p + 1 < n) Dt[cl * xld + 2 * p + 1] = od;
+        }
+        __syncthreads();
+        if (a.m_eq > 0) {
+            for (int pr = wave; pr < kChainTile * a.m_eq; pr += kWaves) {
+                const int cl = pr / a.m_eq, p = pr - cl * a.m_eq;
+                double v = 0.0;
+                if (c0 + cl < a.z) {
+                    const double* er = a.Aeq + (size_t)p * a.lda;
+                    for (int j = lane; j < n; j += 64) v = fma(er[j], Dt[cl * xld + j], v);
+                }
+                v = wave_sum(v);
+                if (lane == 0) cs->y[cl * kMaxMeq + p] = v;
+            }
+            __syncthreads();
+            for (int item = tid; item < kChainTile * n; item += kThreads) {
+                const int cl = item / n, j = item - cl * n;
+                if (c0 + cl >= a.z) continue;
+                double v = Dt[cl * xld + j];
+                for (int p = 0; p < a.m_eq; ++p) v = fma(-a.WT[(size_t)p * a.lda + j], cs->y[cl * kMaxMeq + p], v);
+                Dt[cl * xld + j] = v;
+            }
+            __syncthreads();
+        }
+        for (int cl = wave; cl < kChainTile; cl += kWaves) {
+            double v = 0.0;
+            for (int j = lane; j < n; j += 64) v = fma(Dt[cl * xld + j], Dt[cl * xld + j], v);
+            v = wave_sum(v);
+            if (lane == 0) cs->dnorm[buf][cl] = sqrt(v);
+        }
+        if (P == kFP32) {
+            float* Ot = (float*)op;
+            constexpr int fld = lda + 4;
+            for (int item = tid; item < kChainTile * lda; item += kThreads) {
+                const int cl = item / lda, j = item - cl * lda;
+                Ot[cl * fld + j] = (float)Dt[cl * xld + j];
+            }
+        } else {
+            __bf16* Oh = (__bf16*)op;
+            constexpr int bld = lda + 8;
+            __bf16* Ol = Oh + kChainTile * bld;
+            for (int item = tid; item < kChainTile * lda; item += kThreads) {
+                const int cl = item / lda, j = item - cl * lda;
+                __bf16 hi, lo;
+                split_bf16((float)Dt[cl * xld + j], hi, lo);
+                Oh[cl * bld + j] = hi;
+                Ol[cl * bld + j] = lo;
+            }
+        }
+        __syncthreads();
+    };
+
     float S[4][4];   // slack of rows row0 + 16 rb + 4 g + r, walk c
     int T = 2, since = a.since0;
     bool recompute_now = true;   // the slack never crosses a launch boundary
+    if (a.steps > 0) make_directions(a.step0, 0);
     for (int s = 0;; ++s) {
         if (recompute_now) {
             // exact FP64 slack b - A x of this wave's rows (FP64 matrix cores)
@@ -224,73 +313,14 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
         }
         if (s >= a.steps) break;
         const uint64_t step = a.step0 + (uint64_t)s;
-
-        // ---------------- A: directions ----------------
-        const int npairs = (n + 1) >> 1;
-        for (int item = tid; item < kChainTile * npairs; item += kThreads) {
-            const int cl = item / npairs, p = item - cl * npairs;
-            const int chain = c0 + cl;
-            if (chain >= a.z) continue;
-            Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step, (uint32_t)p);
-            double ev, od;
-            gauss_pair(w, ev, od);
-            Dt[cl * xld + 2 * p] = ev;
-            if (2 * p + 1 < n) Dt[cl * xld + 2 * p + 1] = od;
-        }
+        const int buf = s & 1;
+        const double* Dt = Dbuf + buf * dstride;
         if (tid < kChainTile) {
             cs->up[tid] = __float_as_uint(kInf);
             cs->um[tid] = __float_as_uint(kInf);
             cs->lmax_bits[tid] = __double_as_longlong(kInfD);
             cs->nlmin_bits[tid] = __double_as_longlong(kInfD);
         }
-        __syncthreads();
-        if (a.m_eq > 0) {
-            for (int pr = wave; pr < kChainTile * a.m_eq; pr += kWaves) {
-                const int cl = pr / a.m_eq, p = pr - cl * a.m_eq;
-                double v = 0.0;
-                if (c0 + cl < a.z) {
-                    const double* er = a.Aeq + (size_t)p * a.lda;
-                    for (int j = lane; j < n; j += 64) v = fma(er[j], Dt[cl * xld + j], v);
-                }
-                v = wave_sum(v);
-                if (lane == 0) cs->y[cl * kMaxMeq + p] = v;
-            }
-            __syncthreads();
-            for (int item = tid; item < kChainTile * n; item += kThreads) {
-                const int cl = item / n, j = item - cl * n;
-                if (c0 + cl >= a.z) continue;
-                double v = Dt[cl * xld + j];
-                for (int p = 0; p < a.m_eq; ++p) v = fma(-a.WT[(size_t)p * a.lda + j], cs->y[cl * kMaxMeq + p], v);
-                Dt[cl * xld + j] = v;
-            }
-            __syncthreads();
-        }
-        for (int cl = wave; cl < kChainTile; cl += kWaves) {
-            double v = 0.0;
-            for (int j = lane; j < n; j += 64) v = fma(Dt[cl * xld + j], Dt[cl * xld + j], v);
-            v = wave_sum(v);
-            if (lane == 0) cs->dnorm[cl] = sqrt(v);
-        }
-        if (P == kFP32) {
-            float* Ot = (float*)op;
-            constexpr int fld = lda + 4;
-            for (int item = tid; item < kChainTile * lda; item += kThreads) {
-                const int cl = item / lda, j = item - cl * lda;
-                Ot[cl * fld + j] = (float)Dt[cl * xld + j];
-            }
-        } else {
-            __bf16* Oh = (__bf16*)op;
-            constexpr int bld = lda + 8;
-            __bf16* Ol = Oh + kChainTile * bld;
-            for (int item = tid; item < kChainTile * lda; item += kThreads) {
-                const int cl = item / lda, j = item - cl * lda;
-                __bf16 hi, lo;
-                split_bf16((float)Dt[cl * xld + j], hi, lo);
-                Oh[cl * bld + j] = hi;
-                Ol[cl * bld + j] = lo;
-            }
-        }
-        __syncthreads();
 
         // ---------------- B: screening product (this wave's 64 rows) ----------------
         f32x4 acc[4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
@@ -298,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             if (P == kFP32) {
                 const float* Ot = (const float*)op;
                 constexpr int fld = lda + 4;
-                float4 buf[2][8];
+                float4 bufa[2][8];
                 auto load = [&](float4* dst, int kc) __attribute__((always_inline)) {
 #pragma unroll
                     for (int rb = 0; rb < 4; ++rb) {
@@ -307,13 +337,13 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                         dst[2 * rb + 1] = ap[1];
                     }
                 };
-                load(buf[0], 0);
+                load(bufa[0], 0);
 #pragma unroll
                 for (int kc = 0; kc < NK; ++kc) {
-                    if (kc + 1 < NK) load(buf[(kc + 1) & 1], kc + 1);
+                    if (kc + 1 < NK) load(bufa[(kc + 1) & 1], kc + 1);
                     const float4* bp = (const float4*)(Ot + c * fld + kc * 32 + 8 * g);
                     const float4 b0 = bp[0], b1 = bp[1];
-                    const float4* cur = buf[kc & 1];
+                    const float4* cur = bufa[kc & 1];
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const float bv = e < 4 ? (&b0.x)[e] : (&b1.x)[e - 4];
@@ -328,7 +358,7 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                 const __bf16* Oh = (const __bf16*)op;
                 constexpr int bld = lda + 8;
                 const __bf16* Ol = Oh + kChainTile * bld;
-                bf16x8 buf[2][8];
+                bf16x8 bufa[2][8];
                 auto load = [&](bf16x8* dst, int kc) __attribute__((always_inline)) {
 #pragma unroll
                     for (int rb = 0; rb < 4; ++rb) {
@@ -337,13 +367,13 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                         dst[2 * rb + 1] = *(const bf16x8*)(a.Alo + off);
                     }
                 };
-                load(buf[0], 0);
+                load(bufa[0], 0);
 #pragma unroll
                 for (int kc = 0; kc < NK; ++kc) {
-                    if (kc + 1 < NK) load(buf[(kc + 1) & 1], kc + 1);
+                    if (kc + 1 < NK) load(bufa[(kc + 1) & 1], kc + 1);
                     const bf16x8 bh = *(const bf16x8*)(Oh + c * bld + kc * 32 + 8 * g);
                     const bf16x8 bl = *(const bf16x8*)(Ol + c * bld + kc * 32 + 8 * g);
-                    const bf16x8* cur = buf[kc & 1];
+                    const bf16x8* cur = bufa[kc & 1];
 #pragma unroll
                     for (int rb = 0; rb < 4; ++rb) acc[rb] = mma_bf16(cur[2 * rb + 1], bh, acc[rb]);
 #pragma unroll
@@ -358,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
         // Every workgroup screens its rows with its own upper bounds of the
         // chord ends; they can only exceed the bounds over all rows, so the
         // candidate set is a superset of the one the global bound would give.
-        const float ed = active_c ? (float)(cs->dnorm[c] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+        const float ed = active_c ? (float)(cs->dnorm[buf][c] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
         const float Ek = (float)cs->E[c] * kHighGrow;
         const float bscale = a.u_s * (float)T * kHighGrow;
         float lo_p[4][4], lo_m[4][4];
@@ -368,13 +398,13 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int row = row0 + 16 * rb + 4 * g + r;
+                    const int li = wave * kRowGroup + 16 * rb + 4 * g + r;   // row within the workgroup
                     float hp = kInf, hm = kInf;
                     lo_p[rb][r] = kInf;
                     lo_m[rb][r] = kInf;
-                    if (rows_live && row < m) {
-                        const float na = a.rownorm[row];
-                        const float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                    if (rows_live && rbase + li < m) {
+                        const float na = cs->rownorm[li];
+                        const float dl = fmaf(na, Ek, fmaf(bscale, cs->absb[li], 1e-30f));
                         ratio_bounds(S[rb][r], acc[rb][r], dl, na * ed, lo_p[rb][r], hp, lo_m[rb][r], hm);
                     }
                     up = fminf(up, hp);
@@ -384,6 +414,7 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             up = fminf(up, __shfl_xor(up, 32, 64));
             um = fminf(um, __shfl_xor(um, 16, 64));
             um = fminf(um, __shfl_xor(um, 32, 64));
+            __syncthreads();   // the resets above are done
             if (g == 0) {
                 atomicMin(&cs->up[c], __float_as_uint(up));
                 atomicMin(&cs->um[c], __float_as_uint(um));
@@ -407,7 +438,6 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
 
         // ---------------- C: exact chords of the candidate rows ----------------
         {
-            constexpr int CB = cand_batch(lda);
             double* cb = Cb + (size_t)wave * CB * lda;
             int slot = 0;
             unsigned long long mk = cs->mask[wave][0];
@@ -447,18 +477,19 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                     const double bi = a.b64[rr];
                     double sx = bi, gx = 0.0;
                     int j = 0;
-                    for (; j + 4 <= n; j += 4) {
-                        const double a0 = av[j], a1 = av[j + 1], a2 = av[j + 2], a3 = av[j + 3];
-                        const double x0 = xv[j], x1 = xv[j + 1], x2 = xv[j + 2], x3 = xv[j + 3];
-                        const double d0 = dv[j], d1 = dv[j + 1], d2 = dv[j + 2], d3 = dv[j + 3];
-                        sx = __dsub_rn(sx, __dmul_rn(a0, x0));
-                        gx = __dadd_rn(gx, __dmul_rn(a0, d0));
-                        sx = __dsub_rn(sx, __dmul_rn(a1, x1));
-                        gx = __dadd_rn(gx, __dmul_rn(a1, d1));
-                        sx = __dsub_rn(sx, __dmul_rn(a2, x2));
-                        gx = __dadd_rn(gx, __dmul_rn(a2, d2));
-                        sx = __dsub_rn(sx, __dmul_rn(a3, x3));
-                        gx = __dadd_rn(gx, __dmul_rn(a3, d3));
+                    for (; j + 8 <= n; j += 8) {
+                        double av8[8], xv8[8], dv8[8];
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            av8[e] = av[j + e];
+                            xv8[e] = xv[j + e];
+                            dv8[e] = dv[j + e];
+                        }
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            sx = __dsub_rn(sx, __dmul_rn(av8[e], xv8[e]));
+                            gx = __dadd_rn(gx, __dmul_rn(av8[e], dv8[e]));
+                        }
                     }
                     for (; j < n; ++j) {
                         sx = __dsub_rn(sx, __dmul_rn(av[j], xv[j]));
@@ -479,25 +510,31 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             if (lane == 0 && nex) atomicAdd(&cs->exact, nex);
         }
         __syncthreads();
+
+        // ---- combine the exact chord ends of the group; meanwhile the
+        //      directions of the next step are generated ----
+        const int xslot = (int)(step % 3);
         if (split > 1) {
-            // combine the exact chord ends of the group's workgroups
-            const int slot = (int)(step % 3);
             if (tid < kChainTile) {
-                // results consumed: the atomics have been performed before arrival
+                // results consumed: the atomics are performed before arrival
                 const unsigned long long o0 = __hip_atomic_fetch_min(
-                    &gL[(slot * 2 + 0) * kChainTile + tid], cs->lmax_bits[tid], __ATOMIC_RELAXED,
+                    &gL[(xslot * 2 + 0) * kChainTile + tid], cs->lmax_bits[tid], __ATOMIC_RELAXED,
                     __HIP_MEMORY_SCOPE_AGENT);
                 const unsigned long long o1 = __hip_atomic_fetch_min(
-                    &gL[(slot * 2 + 1) * kChainTile + tid], cs->nlmin_bits[tid], __ATOMIC_RELAXED,
+                    &gL[(xslot * 2 + 1) * kChainTile + tid], cs->nlmin_bits[tid], __ATOMIC_RELAXED,
                     __HIP_MEMORY_SCOPE_AGENT);
-                if ((o0 & o1) == 1ull) cs->ok = 2;
+                if (o0 == ~0ull || o1 == ~0ull) cs->ok = 3;   // never true: forces the wait
             }
             nbar += 1;
-            if (!group_barrier(gbar, nbar * (unsigned)split, a.gerr, &cs->ok)) break;
+            group_arrive(gbar);
+        }
+        if (s + 1 < a.steps) make_directions(step + 1, buf ^ 1);
+        if (split > 1) {
+            if (!group_wait(gbar, nbar * (unsigned)split, a.gerr, &cs->ok)) break;
             if (tid < kChainTile) {
-                cs->lmax_bits[tid] = __hip_atomic_load(&gL[(slot * 2 + 0) * kChainTile + tid],
+                cs->lmax_bits[tid] = __hip_atomic_load(&gL[(xslot * 2 + 0) * kChainTile + tid],
                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                cs->nlmin_bits[tid] = __hip_atomic_load(&gL[(slot * 2 + 1) * kChainTile + tid],
+                cs->nlmin_bits[tid] = __hip_atomic_load(&gL[(xslot * 2 + 1) * kChainTile + tid],
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             // every workgroup has read the slot of the previous step
@@ -506,43 +543,48 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                     &gL[(int)((step + 2) % 3) * 2 * kChainTile + tid],
                     (unsigned long long)__double_as_longlong(kInfD), __ATOMIC_RELAXED,
                     __HIP_MEMORY_SCOPE_AGENT);
-                if (o == 1ull) cs->ok = 2;
+                if (o == ~0ull) cs->ok = 3;   // never true: forces the wait
             }
+            __syncthreads();
         }
 
         // ---------------- D: theta, eager slack update, state update ----------------
-        if (tid < kChainTile) {
-            const int chain = c0 + tid;
-            double th = 0.0;
-            int fl = 0;
+        // every wave computes theta of all 16 walks (lanes 0-15), so the
+        // slack update needs no further barrier
+        double th_l = 0.0;
+        int fl_l = 0;
+        if (lane < kChainTile) {
+            const int chain = c0 + lane;
             if (chain < a.z) {
-                const double lmax = __longlong_as_double((long long)cs->lmax_bits[tid]);
-                const double lmin = -__longlong_as_double((long long)cs->nlmin_bits[tid]);
+                const double lmax = __longlong_as_double((long long)cs->lmax_bits[lane]);
+                const double lmin = -__longlong_as_double((long long)cs->nlmin_bits[lane]);
                 if (lmax == kInfD || lmin == -kInfD) {
-                    fl |= kUnbounded;
+                    fl_l = kUnbounded;
                 } else if (!(lmax > lmin)) {
-                    fl |= kDegenerate;
+                    fl_l = kDegenerate;
                 } else {
                     Block4 w = stream_block(a.seed, kTagTheta, a.chain_offset + (uint32_t)chain, step, 0);
                     const double u = open_unit(w.w0, w.w1);
-                    th = __dadd_rn(lmin, __dmul_rn(u, __dsub_rn(lmax, lmin)));
+                    th_l = __dadd_rn(lmin, __dmul_rn(u, __dsub_rn(lmax, lmin)));
                 }
             }
-            cs->theta[tid] = th;
-            if (fl) cs->flags[tid] |= fl;
         }
-        __syncthreads();
+        const double th_c = __shfl(th_l, c, 64);
         {
-            const float th32 = (float)cs->theta[c];
+            const float th32 = (float)th_c;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) S[rb][r] = fmaf(-th32, acc[rb][r], S[rb][r]);
         }
+        if (wave == 0 && lane < kChainTile) {
+            cs->theta[lane] = th_l;
+            if (fl_l) cs->flags[lane] |= fl_l;
+        }
         for (int cl = wave; cl < kChainTile; cl += kWaves) {
             const int chain = c0 + cl;
             if (chain >= a.z) continue;
-            const double th = cs->theta[cl];
+            const double th = __shfl(th_l, cl, 64);
             double xo = 0.0, xn2 = 0.0;
             bool finite = isfinite(th);
             const bool rec = slice == 0 && a.rec_stride > 0 && chain < a.rec_chains &&
@@ -563,7 +605,7 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             xn2 = wave_sum(xn2);
             finite = __all(finite);
             if (lane == 0) {
-                const double dn = cs->dnorm[cl], at = fabs(th);
+                const double dn = cs->dnorm[buf][cl], at = fabs(th);
                 const double us = (double)a.u_s;
                 double E = cs->E[cl];
                 E += at * dn * ((double)a.eps_g + 2.0 * us);
@@ -603,13 +645,9 @@ template <int P, int NK>
 hipError_t launch_res(const StepArgs& a, hipStream_t stream)
 {
     const size_t lds = res_layout(P, NK * 32).total;
-    static bool attr_set = false;
     const void* fn = (const void*)resident_kernel<P, NK>;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     const dim3 grid((a.z_pad / kChainTile) * a.split), block(kThreads);
     if (a.split > 1) {
         StepArgs copy = a;
@@ -625,9 +663,11 @@ int res_blocks_per_cu()
 {
     int nb = 0;
     const size_t lds = res_layout(P, NK * 32).total;
-    hipFuncSetAttribute((const void*)resident_kernel<P, NK>, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)resident_kernel<P, NK>, kThreads, lds) != hipSuccess)
+    if (hipFuncSetAttribute((const void*)resident_kernel<P, NK>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)resident_kernel<P, NK>, kThreads, lds) != hipSuccess) {
+        (void)hipGetLastError();   // do not leave a stale error for the next launch
         return 0;
+    }
     return nb;
 }
 
@@ -668,7 +708,7 @@ int res_occupancy(int lda)
 int resident_split(int prec, int lda, int m_pad, int z_pad)
 {
     if (prec != kFP32 && prec != kBF16X3) return 0;
-    if (lda > 256 || res_layout(prec, lda).total > 163840) return 0;
+    if (lda > 256 || res_layout(prec, lda).cb_rows < 1) return 0;
     const int rows = kWaves * kRowGroup;
     const int split = (m_pad + rows - 1) / rows;
     if (split > 16) return 0;

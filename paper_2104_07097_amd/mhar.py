@@ -48,7 +48,8 @@ class Options(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_uint64), ("chain_steps", ctypes.c_uint64),
-                ("exact_rows", ctypes.c_uint64), ("recomputes", ctypes.c_uint64)]
+                ("exact_rows", ctypes.c_uint64), ("recomputes", ctypes.c_uint64),
+                ("kernel", ctypes.c_int32), ("split", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -79,6 +80,19 @@ SIGNATURES = {
     "mhar_sync": (_st, [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]),
     "mhar_get_stats": (_st, [_vp, _vp, ctypes.POINTER(Stats)]),
     "mhar_chains_destroy": (_st, [_vp]),
+    "mhar_precond_workspace_size": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "mhar_precond_create": (_st, [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
+    "mhar_precond_set": (_st, [_vp, _vp, _vp, _vp]),
+    "mhar_precond_get": (_st, [_vp, _vp, _vp, _vp]),
+    "mhar_precond_loss": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "mhar_precond_train": (_st, [_vp, _i64, ctypes.c_double, _vp]),
+    "mhar_precond_freeze": (_st, [_vp]),
+    "mhar_precond_destroy": (_st, [_vp]),
+    "mhar_batch_workspace_size": (_st, [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]),
+    "mhar_batch_create": (_st, [ctypes.c_int32, ctypes.POINTER(_vp), _vp, ctypes.c_size_t,
+                                ctypes.POINTER(_vp)]),
+    "mhar_batch_step": (_st, [_vp, _i64, _vp]),
+    "mhar_batch_destroy": (_st, [_vp]),
 }
 
 _lib = None
@@ -251,9 +265,84 @@ class Chains:
         _check(load().mhar_get_stats(self.handle, self.stream, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
+    # ---- learned direction covariance ----
+    def precond_create(self, rank: int):
+        lib = load()
+        sz = ctypes.c_size_t()
+        _check(lib.mhar_precond_workspace_size(self.handle, int(rank), ctypes.byref(sz)))
+        self._pc_ws, ptr, nbytes = _workspace(self.torch, sz.value, self.problem.device)
+        _check(lib.mhar_precond_create(self.handle, int(rank), ptr, nbytes, self.stream))
+        self.rank = int(rank)
+
+    def precond_set(self, U, log_sigma):
+        t = self.torch
+        U = U.to(device=self.problem.device, dtype=t.float64).contiguous()
+        ls = log_sigma.to(device=self.problem.device, dtype=t.float64).contiguous()
+        _check(load().mhar_precond_set(self.handle, U.data_ptr(), ls.data_ptr(), self.stream))
+        t.cuda.current_stream(self.problem.device).synchronize()
+
+    def precond_get(self):
+        t = self.torch
+        U = t.empty((self.problem.n, self.rank), dtype=t.float64, device=self.problem.device)
+        ls = t.empty(self.problem.n, dtype=t.float64, device=self.problem.device)
+        _check(load().mhar_precond_get(self.handle, U.data_ptr(), ls.data_ptr(), self.stream))
+        return U, ls
+
+    def precond_loss(self):
+        t = self.torch
+        nll = t.empty(1, dtype=t.float64, device=self.problem.device)
+        gU = t.empty((self.problem.n, self.rank), dtype=t.float64, device=self.problem.device)
+        gl = t.empty(self.problem.n, dtype=t.float64, device=self.problem.device)
+        _check(load().mhar_precond_loss(self.handle, nll.data_ptr(), gU.data_ptr(), gl.data_ptr(),
+                                        self.stream))
+        return nll, gU, gl
+
+    def precond_train(self, steps: int, lr: float):
+        _check(load().mhar_precond_train(self.handle, int(steps), float(lr), self.stream))
+
+    def precond_freeze(self):
+        _check(load().mhar_precond_freeze(self.handle))
+
+    def precond_destroy(self):
+        _check(load().mhar_precond_destroy(self.handle))
+
     def close(self):
         if getattr(self, "handle", None):
             _check(load().mhar_chains_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several Chains (each on its own Problem, one precision) stepped together in
+    one persistent launch (mhar_batch_create / mhar_batch_step)."""
+
+    def __init__(self, chains_list):
+        torch = chains_list[0].torch
+        self.torch = torch
+        self.chains = list(chains_list)
+        lib = load()
+        arr = (ctypes.c_void_p * len(self.chains))(*[c.handle.value for c in self.chains])
+        sz = ctypes.c_size_t()
+        _check(lib.mhar_batch_workspace_size(len(self.chains), arr, ctypes.byref(sz)))
+        dev = self.chains[0].problem.device
+        self._ws, ptr, nbytes = _workspace(torch, sz.value, dev)
+        h = ctypes.c_void_p()
+        _check(lib.mhar_batch_create(len(self.chains), arr, ptr, nbytes, ctypes.byref(h)))
+        self.handle = h
+        self.device = dev
+
+    def step(self, steps: int):
+        _check(load().mhar_batch_step(self.handle, int(steps), _stream(self.torch, self.device)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().mhar_batch_destroy(self.handle))
             self.handle = None
 
     def __del__(self):
