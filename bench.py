@@ -41,6 +41,10 @@ TRAFFIC = {
 }
 
 
+KERNEL_PATHS = {1: "general", 2: "resident", 3: "tiled"}
+KERNEL_NAMES = {1: "mhar_steps_kernel", 2: "resident_kernel", 3: "tiled_screen_kernel"}
+
+
 def sources_sha256():
     import glob
     import hashlib
@@ -179,7 +183,7 @@ def bench_simple(args, p, precision, workload, default_steps):
     return _base_line(p.z * steps / sec, steps, args.warmup, sec, precision,
                       {"workload": workload, "n": p.n, "m": p.m, "m_eq": p.m_eq, "z": p.z,
                        "precision": precision, "recompute_every": 50,
-                       "kernel": "resident" if st["kernel"] == 1 else "general",
+                       "kernel": KERNEL_PATHS.get(st["kernel"], "?"),
                        "exact_rows_per_chain_step": st["exact_rows"] / max(1, st["chain_steps"]),
                        "flags": flags})
 
@@ -372,7 +376,7 @@ def main():
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[best],
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[best],
                      "traffic": measured_traffic(best, launch_steps),
-                     "kernel": ("resident_kernel" if r["stats"]["kernel"] == 1 else "mhar_steps_kernel")
+                     "kernel": KERNEL_NAMES.get(r["stats"]["kernel"], "?")
                                + f"<{best}>, {r['stats']['split']} workgroups per 16-walk tile",
                      "avg_launch_ms": avg_launch * 1e3,
                      "flops_per_launch": flops_per_launch},

@@ -88,11 +88,23 @@ enum {
     MHAR_CHAIN_INFEASIBLE = 8   /* exact FP64 slack below -1e-12 max(1,|b_i|) */
 };
 
+/* Kernel path of the step.  Every path gives the same trajectories (the
+ * chord is evaluated exactly in FP64); they differ in speed only. */
+typedef enum {
+    MHAR_PATH_AUTO = 0,      /* chosen from the shape (default) */
+    MHAR_PATH_GENERAL = 1,   /* one workgroup per 16 walks over all rows, slack in HBM */
+    MHAR_PATH_RESIDENT = 2,  /* slack in registers, rows split over co-resident workgroups;
+                                FP32/BF16X3, n <= 256, m <= 8192 (else MHAR_E_UNSUPPORTED) */
+    MHAR_PATH_TILED = 3      /* per step a screening GEMM over 256-row x 128-walk tiles and a
+                                chords kernel; FP32/BF16X3 (else MHAR_E_UNSUPPORTED) */
+} mhar_path_t;
+
 typedef struct {
     int32_t precision;        /* mhar_precision_t, default MHAR_FP32 */
     int32_t recompute_every;  /* R >= 1: exact FP64 recompute of the slack b - A X every R steps (default 50) */
     int32_t steps_per_launch; /* 0 = automatic; bounds the steps one kernel launch runs */
-    int32_t reserved[5];      /* must be 0 */
+    int32_t path;             /* mhar_path_t, default MHAR_PATH_AUTO */
+    int32_t reserved[4];      /* must be 0 */
 } mhar_options_t;
 
 typedef struct mhar_problem* mhar_problem_t;
@@ -105,7 +117,7 @@ typedef struct {
     uint64_t chain_steps;       /* walks x steps */
     uint64_t exact_rows;        /* rows evaluated exactly in FP64 (candidates of the screening) */
     uint64_t recomputes;        /* exact slack recomputes */
-    int32_t kernel;             /* 0: general kernel (slack in HBM), 1: register-resident kernel */
+    int32_t kernel;             /* mhar_path_t of the last step: MHAR_PATH_GENERAL, _RESIDENT or _TILED */
     int32_t split;              /* workgroups per 16-walk tile (resident kernel), else 1 */
 } mhar_stats_t;
 

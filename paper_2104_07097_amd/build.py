@@ -17,6 +17,9 @@ HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17", "-Wall",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit contraction: a*b+c rounds twice unless written as fma(), so the
+    # exact chord follows the sequential FP64 order of the line-set formula
+    "-ffp-contract=off",
 ]
 
 

@@ -15,7 +15,7 @@
 using namespace mhar;
 
 struct mhar_problem {
-    int n, m, m_pad, lda, m_eq, prec, R, steps_per_launch;
+    int n, m, m_pad, lda, m_eq, prec, R, steps_per_launch, path;
     float eps_g, u_s;
     double *A64, *b64, *Aeq, *beq, *WT;
     float *A32, *rownorm, *absb;
@@ -28,6 +28,7 @@ struct mhar_chains {
     mhar_problem* p;
     int z, z_pad;
     int split;  // > 0: register-resident kernel with this many workgroups per walk tile
+    int tiled;  // 1: tiled path (screening GEMM + chords kernel per step)
     uint64_t seed;
     uint32_t chain_offset;
     uint64_t step;
@@ -36,6 +37,9 @@ struct mhar_chains {
     double *X, *D, *theta, *E;
     void *S, *G;
     float* L;
+    float* Ug;
+    void* Dop;
+    double* dn;
     int* flags;
     unsigned long long* counters;
     float* gU;
@@ -117,7 +121,11 @@ mhar_status_t check_options(const mhar_options_t* opt, mhar_options_t* out)
         return fail(MHAR_E_INVALID_ARG, "options.recompute_every must be <= 100000");
     if (opt->steps_per_launch < 0)
         return fail(MHAR_E_INVALID_ARG, "options.steps_per_launch must be >= 0");
-    for (int i = 0; i < 5; ++i)
+    if (opt->path < MHAR_PATH_AUTO || opt->path > MHAR_PATH_TILED)
+        return fail(MHAR_E_INVALID_ARG, "options.path must be a mhar_path_t value");
+    if (opt->path == MHAR_PATH_TILED && opt->precision == MHAR_FP64)
+        return fail(MHAR_E_UNSUPPORTED, "the tiled path screens in FP32 or BF16X3 only");
+    for (int i = 0; i < 4; ++i)
         if (opt->reserved[i] != 0) return fail(MHAR_E_INVALID_ARG, "options.reserved must be 0");
     *out = *opt;
     return MHAR_OK;
@@ -171,6 +179,9 @@ size_t carve_chains(const mhar_problem* p, int z_pad, void* ws, mhar_chains* ch)
     q->S = c.take<char>((size_t)z_pad * p->m_pad * st);
     q->G = c.take<char>((size_t)z_pad * p->m_pad * st);
     q->L = c.take<float>((size_t)(z_pad / kChainTile) * (p->m_pad / kRowGroup) * 2 * kChainTile);
+    q->Ug = c.take<float>((size_t)(z_pad / kChainTile) * (p->m_pad / kRowGroup) * 2 * kChainTile);
+    q->Dop = p->prec == MHAR_FP64 ? nullptr : (void*)c.take<float>(rows);
+    q->dn = c.take<double>(z_pad);
     q->theta = c.take<double>(z_pad);
     q->E = c.take<double>(z_pad);
     q->flags = c.take<int>(z_pad);
@@ -236,6 +247,9 @@ StepArgs make_args(const mhar_chains* c)
     a.S = c->S;
     a.G = c->G;
     a.L = c->L;
+    a.Ug = c->Ug;
+    a.Dop = c->Dop;
+    a.dn = c->dn;
     a.theta = c->theta;
     a.E = c->E;
     a.flags = c->flags;
@@ -260,6 +274,16 @@ StepArgs make_args(const mhar_chains* c)
     return a;
 }
 
+// Automatic choice between the general and the tiled path (reduced
+// precision only): the general kernel streams all of A once per 16 walks, the
+// tiled path once per 128 walks and one row tile of D per 256 rows, which wins
+// once A no longer sits in one XCD's L2.
+int use_tiled(const mhar_problem* p, int z_pad)
+{
+    if (p->prec == MHAR_FP64) return 0;
+    return (int64_t)p->m_pad * p->lda >= (int64_t(1) << 18) && z_pad >= 64;
+}
+
 int64_t auto_chunk(const mhar_problem* p)
 {
     int64_t work = (int64_t)p->m_pad * p->lda;
@@ -269,6 +293,7 @@ int64_t auto_chunk(const mhar_problem* p)
 
 hipError_t launch_any(const mhar_chains* c, const StepArgs& a, hipStream_t stream)
 {
+    if (c->tiled) return launch_tiled(c->p->prec, a, stream);
     if (c->split <= 0) return launch_steps(c->p->prec, a, stream);
     if (c->split > 1) {
         // fresh exchange slots and arrival counters for this launch
@@ -401,6 +426,7 @@ mhar_status_t mhar_problem_create(int64_t n, int64_t m, const double* A, const d
     p->prec = o.precision;
     p->R = o.recompute_every;
     p->steps_per_launch = o.steps_per_launch;
+    p->path = o.path;
     p->eps_g = eps_for(o.precision, d.n);
     p->u_s = o.precision == MHAR_FP64 ? std::ldexp(1.0f, -53) : std::ldexp(1.0f, -24);
     carve_problem(d, o.precision, workspace, p);
@@ -483,11 +509,22 @@ mhar_status_t mhar_chains_create(mhar_problem_t p, int64_t z, const double* X0, 
     c->seed = seed;
     c->chain_offset = (uint32_t)chain_offset;
     carve_chains(p, z_pad, workspace, c);
-    c->split = resident_split(p->prec, p->lda, p->m_pad, z_pad);
     auto cleanup = [&](mhar_status_t code) {
         delete c;
         return code;
     };
+    const int rs = resident_split(p->prec, p->lda, p->m_pad, z_pad);
+    c->split = 0;
+    c->tiled = 0;
+    if (p->path == MHAR_PATH_RESIDENT) {
+        if (rs <= 0) return cleanup(fail(MHAR_E_UNSUPPORTED, "the resident path does not fit this shape"));
+        c->split = rs;
+    } else if (p->path == MHAR_PATH_TILED) {
+        c->tiled = 1;
+    } else if (p->path == MHAR_PATH_AUTO) {
+        if (rs > 0) c->split = rs;
+        else c->tiled = use_tiled(p, z_pad);
+    }
     hipError_t e = launch_fill_i32((int*)c->theta, (int64_t)z_pad * 2, 0, stream);
     if (e == hipSuccess) e = launch_fill_i32((int*)c->E, (int64_t)z_pad * 2, 0, stream);
     if (e == hipSuccess) e = launch_fill_i32(c->flags, z_pad, 0, stream);
@@ -588,7 +625,7 @@ mhar_status_t mhar_get_stats(mhar_chains_t c, void* stream, mhar_stats_t* stats)
     stats->chain_steps = c->step * (uint64_t)c->z;
     stats->exact_rows = cnt[0];
     stats->recomputes = c->recomputes;
-    stats->kernel = c->split > 0 ? 1 : 0;
+    stats->kernel = c->tiled ? MHAR_PATH_TILED : c->split > 0 ? MHAR_PATH_RESIDENT : MHAR_PATH_GENERAL;
     stats->split = c->split > 0 ? c->split : 1;
     return MHAR_OK;
 }

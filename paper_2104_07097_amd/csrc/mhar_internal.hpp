@@ -56,6 +56,9 @@ struct StepArgs {
     void* S;                // slack, tile-fragment order, FP64 (FP64 mode) or FP32
     void* G;                // last screening product, same order and type
     float* L;               // per tile: (m_pad/64) x 2 x 16 lower bounds of the chord ratios
+    float* Ug;              // tiled path, same layout: upper bounds of the chord ends per group
+    void* Dop;              // tiled path: direction operand, z_pad x lda (FP32, or bf16 hi then lo)
+    double* dn;             // tiled path: z_pad direction norms
     double* theta;          // z_pad, last theta
     double* E;              // z_pad, slack drift coefficient
     int* flags;             // z_pad
@@ -95,6 +98,9 @@ int batch_blocks_per_cu(int prec, int max_lda);
 int resident_split(int prec, int lda, int m_pad, int z_pad);
 hipError_t launch_resident(int prec, const StepArgs& a, hipStream_t stream);
 hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream);
+// tiled path for large problems (FP32 / BF16X3): per step a screening GEMM and
+// a chords + directions kernel, and an FP64 recompute GEMM every R steps
+hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream);
 
 // one-time setup
 hipError_t launch_convert_problem(int prec, int n, int m, int m_pad, int lda, const double* A,

@@ -26,6 +26,8 @@ namespace mhar {
 
 namespace {
 
+constexpr int kCandCap = 512;   // candidate (row, walk) pairs listed per tile and step
+
 struct ChainLds {
     double theta[kChainTile];
     double E[kChainTile];
@@ -35,7 +37,57 @@ struct ChainLds {
     unsigned um[kChainTile];
     int flags[kChainTile];
     unsigned long long exact;
+    // exact chords: candidate list, and per walk the chord ends as the bits of
+    // lambda_max and of -lambda_min (both >= 0, so integer min is float min)
+    unsigned long long lmax_bits[kChainTile];
+    unsigned long long nlmin_bits[kChainTile];
+    int cfl[kChainTile];
+    int ncand;
+    int2 cand[kCandCap];
 };
+
+// s_i = b_i - a_i x and g_i = a_i d in FP64 in the order of a sequential sum
+// (separate roundings, the device code is built without contraction); the
+// loads of a block of 16 are issued before its dependent chain.
+__device__ __forceinline__ void exact_row(const double* __restrict__ ar,
+                                          const double* __restrict__ xr,
+                                          const double* __restrict__ dr, double bi, int n,
+                                          double& s_out, double& g_out)
+{
+    constexpr int B = 16;
+    double s = bi, g = 0.0;
+    int j = 0;
+    for (; j + B <= n; j += B) {
+        double av[B], xv[B], dv[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            av[u] = ar[j + u];
+            xv[u] = xr[j + u];
+            dv[u] = dr[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            s = __dsub_rn(s, __dmul_rn(av[u], xv[u]));
+            g = __dadd_rn(g, __dmul_rn(av[u], dv[u]));
+        }
+    }
+    for (; j < n; ++j) {
+        s = __dsub_rn(s, __dmul_rn(ar[j], xr[j]));
+        g = __dadd_rn(g, __dmul_rn(ar[j], dr[j]));
+    }
+    s_out = s;
+    g_out = g;
+}
+
+// Chord-end contribution of one exactly evaluated row (S4.4, Lemma 4.2).
+__device__ __forceinline__ void chord_row(ChainLds* cs, int cl, double s, double gg, double bi)
+{
+    if (s < -1e-12 * fmax(1.0, fabs(bi))) atomicOr(&cs->cfl[cl], kInfeasible);
+    if (s < 0.0) s = 0.0;
+    if (gg > 0.0) atomicMin(&cs->lmax_bits[cl], (unsigned long long)__double_as_longlong(s / gg));
+    else if (gg < 0.0)
+        atomicMin(&cs->nlmin_bits[cl], (unsigned long long)__double_as_longlong(-(s / gg)));
+}
 
 __host__ __device__ inline int x_ld(int lda) { return lda + 2; }     // FP64 LDS row stride
 __host__ __device__ inline int f32_ld(int lda) { return lda + 4; }   // FP32 LDS row stride
@@ -73,9 +125,7 @@ __device__ __forceinline__ size_t frag_index(int tile, int Q, int row, int c)
 // ---------------------------------------------------------------------------
 // Phase A: directions of the 16 walks of this tile at `step`.
 // ---------------------------------------------------------------------------
-template <int P>
-__device__ void make_directions(const StepArgs& a, ChainLds* cs, unsigned char* big, int c0,
-                                uint64_t step)
+__device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_t step)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = a.n, lda = a.lda;
@@ -110,15 +160,38 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, unsigned char* 
             if (2 * p + 1 < a.r) eps[cl * kMaxMeq + 2 * p + 1] = od;
         }
         __syncthreads();
-        for (int item = tid; item < kChainTile * n; item += kThreads) {
-            int cl = item / n, j = item - cl * n;
-            int chain = c0 + cl;
-            if (chain >= a.z) continue;
+        // one coordinate per thread: its row of U is loaded once, in blocks of
+        // 8, and applied to the 16 walks, each walk's sum in rank order
+        for (int j = tid; j < n; j += kThreads) {
             const double* ur = a.U + (size_t)j * a.r;
-            double v = 0.0;
-            for (int q = 0; q < a.r; ++q) v = __dadd_rn(v, __dmul_rn(ur[q], eps[cl * kMaxMeq + q]));
-            double* dp = a.D + (size_t)chain * lda + j;
-            *dp = __dadd_rn(v, __dmul_rn(a.esig[j], *dp));
+            double v[kChainTile];
+#pragma unroll
+            for (int cl = 0; cl < kChainTile; ++cl) v[cl] = 0.0;
+            int q = 0;
+            for (; q + 8 <= a.r; q += 8) {
+                double u8[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) u8[e] = ur[q + e];
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int cl = 0; cl < kChainTile; ++cl)
+                        v[cl] = __dadd_rn(v[cl], __dmul_rn(u8[e], eps[cl * kMaxMeq + q + e]));
+            }
+            for (; q < a.r; ++q) {
+                const double uq = ur[q];
+#pragma unroll
+                for (int cl = 0; cl < kChainTile; ++cl)
+                    v[cl] = __dadd_rn(v[cl], __dmul_rn(uq, eps[cl * kMaxMeq + q]));
+            }
+            const double es = a.esig[j];
+#pragma unroll
+            for (int cl = 0; cl < kChainTile; ++cl) {
+                if (c0 + cl < a.z) {
+                    double* dp = a.D + (size_t)(c0 + cl) * lda + j;
+                    *dp = __dadd_rn(v[cl], __dmul_rn(es, *dp));
+                }
+            }
         }
     }
     if (a.m_eq > 0) {
@@ -160,7 +233,14 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, unsigned char* 
         v = wave_sum(v);
         if (lane == 0) cs->dnorm[cl] = sqrt(v);
     }
-    // operand tile in LDS
+}
+
+// The directions of the tile as the matrix-core operand in LDS.
+template <int P>
+__device__ void stage_operand(const StepArgs& a, unsigned char* big, int c0)
+{
+    const int tid = threadIdx.x;
+    const int n = a.n, lda = a.lda;
     if (P == kFP64) {
         double* Dt = (double*)big;
         const int ld = x_ld(lda);
@@ -389,21 +469,26 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
     const float* Lt = a.L + (size_t)tile * ngroups * 2 * kChainTile;
     const float bscale = a.u_s * (float)T * kHighGrow;
     const double u64 = 0x1.0p-53;
+    const unsigned long long kInfBits = 0x7FF0000000000000ull;
 
+    if (tid < kChainTile) {
+        cs->lmax_bits[tid] = kInfBits;
+        cs->nlmin_bits[tid] = kInfBits;
+        cs->cfl[tid] = 0;
+    }
+    if (tid == 0) cs->ncand = 0;
+    __syncthreads();
+
+    // 1. candidate rows of every walk: rows whose lower bound does not exceed
+    //    the certified chord-end bound U.  They are listed in LDS; past the
+    //    list's capacity they are evaluated on the spot.
     for (int cl = wave; cl < kChainTile; cl += kWaves) {
         const int chain = c0 + cl;
-        if (chain >= a.z) {
-            if (lane == 0) cs->theta[cl] = 0.0;
-            continue;
-        }
+        if (chain >= a.z) continue;
         const float up = __uint_as_float(cs->up[cl]);
         const float um = __uint_as_float(cs->um[cl]);
         const float ed = (float)(cs->dnorm[cl] * (double)a.eps_g) * kHighGrow + 1e-30f;
         const float Ek = (float)cs->E[cl] * kHighGrow;
-        const double* xr = a.X + (size_t)chain * lda;
-        const double* dr = a.D + (size_t)chain * lda;
-        double lmax = kInfD, lmin = -kInfD;
-        int fl = 0;
         unsigned long long nex = 0;
         for (int qb = 0; qb < ngroups; qb += 64) {
             const int q = qb + lane;
@@ -430,25 +515,47 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
                 const bool cand = (row < a.m) && ((lo_p <= up) || (lo_m <= um));
                 nex += __popcll(__ballot(cand));
                 if (cand) {
-                    // the line-set formula of S4.4, in the operation order of a
-                    // sequential FP64 evaluation
-                    const double* ar = a.A64 + (size_t)row * lda;
-                    const double bi = a.b64[row];
-                    double s = bi;
-                    for (int j = 0; j < n; ++j) s = __dsub_rn(s, __dmul_rn(ar[j], xr[j]));
-                    double gg = 0.0;
-                    for (int j = 0; j < n; ++j) gg = __dadd_rn(gg, __dmul_rn(ar[j], dr[j]));
-                    if (s < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
-                    if (s < 0.0) s = 0.0;
-                    if (gg > 0.0) lmax = fmin(lmax, s / gg);
-                    else if (gg < 0.0) lmin = fmax(lmin, s / gg);
+                    const int slot = atomicAdd(&cs->ncand, 1);
+                    if (slot < kCandCap) {
+                        cs->cand[slot] = make_int2(row, cl);
+                    } else {
+                        double s, gg;
+                        const double bi = a.b64[row];
+                        exact_row(a.A64 + (size_t)row * lda, a.X + (size_t)chain * lda,
+                                  a.D + (size_t)chain * lda, bi, n, s, gg);
+                        chord_row(cs, cl, s, gg, bi);
+                    }
                 }
             }
         }
-        lmax = wave_min(lmax);
-        lmin = wave_max(lmin);
-        for (int o = 32; o > 0; o >>= 1) fl |= __shfl_xor(fl, o, 64);
+        if (lane == 0 && nex) atomicAdd(&cs->exact, nex);
+    }
+    __syncthreads();
 
+    // 2. exact FP64 evaluation of the listed rows, all in parallel
+    const int nc = min(cs->ncand, kCandCap);
+    for (int t = tid; t < nc; t += kThreads) {
+        const int2 rc = cs->cand[t];
+        const int chain = c0 + rc.y;
+        double s, gg;
+        const double bi = a.b64[rc.x];
+        exact_row(a.A64 + (size_t)rc.x * lda, a.X + (size_t)chain * lda, a.D + (size_t)chain * lda,
+                  bi, n, s, gg);
+        chord_row(cs, rc.y, s, gg, bi);
+    }
+    __syncthreads();
+
+    // 3. theta (S4.5), the update and the drift bound of every walk
+    for (int cl = wave; cl < kChainTile; cl += kWaves) {
+        const int chain = c0 + cl;
+        if (chain >= a.z) {
+            if (lane == 0) cs->theta[cl] = 0.0;
+            continue;
+        }
+        const double* dr = a.D + (size_t)chain * lda;
+        const double lmax = __longlong_as_double((long long)cs->lmax_bits[cl]);
+        const double lmin = -__longlong_as_double((long long)cs->nlmin_bits[cl]);
+        int fl = cs->cfl[cl];
         double th = 0.0;
         if (lmax == kInfD || lmin == -kInfD) {
             fl |= kUnbounded;
@@ -490,7 +597,6 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
             cs->E[cl] = E;
             cs->theta[cl] = th;
             cs->flags[cl] |= fl;
-            cs->exact += nex;
         }
     }
 }
@@ -593,7 +699,8 @@ __device__ void run_tile(const StepArgs& a, unsigned char* smem, int tile)
             cs->up[tid] = __float_as_uint(kInf);
             cs->um[tid] = __float_as_uint(kInf);
         }
-        make_directions<P>(a, cs, big, c0, step);
+        make_directions(a, cs, c0, step);
+        stage_operand<P>(a, big, c0);
         screen<P>(a, cs, big, tile, c0, pending, T);
         __syncthreads();
         exact_chords<P>(a, cs, tile, c0, step, s, T);
@@ -644,6 +751,475 @@ __global__ __launch_bounds__(kThreads) void mhar_batch_kernel(const StepArgs* __
         if (u >= nunits) break;
         const int2 w = units[u];
         run_tile<P>(descs[w.x], smem, w.y);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled path for large problems (FP32 / BF16X3 screening).
+//
+// With one workgroup per 16 walks, every workgroup streams all of A each
+// step, which bounds large problems by the A stream.  The tiled path splits a
+// step into three kernels instead:
+//   tiled_screen : G = A D as a GEMM over (256-row x 128-walk) tiles with A and
+//                  the direction operand staged through LDS (double buffered),
+//                  fused with the deferred slack update and the ratio bounds;
+//                  per (64-row group, walk) it writes the least lower bound
+//                  and the least upper bound of each chord end;
+//   tiled_chords : per 16-walk tile, the chord-end bound as the minimum over
+//                  the groups, the exact FP64 chord of the candidate rows,
+//                  theta and the update (Phase D), then the next step's
+//                  directions (Phase A) written to HBM as FP64 rows and as
+//                  the matrix-core operand;
+//   tiled_recompute: every R steps the exact slack b - A X as an FP64 GEMM.
+// The arithmetic that decides a trajectory (directions, exact chords, theta,
+// update) is the same code as the single-kernel path, so trajectories agree.
+// ---------------------------------------------------------------------------
+constexpr int kTR = 256;   // rows per screening tile
+constexpr int kTW = 128;   // walks per screening tile
+constexpr int kTK = 32;    // K per LDS stage
+
+template <int P> struct TileFmt;
+template <> struct TileFmt<kBF16X3> {
+    static constexpr int planes = 2;       // hi, lo
+    static constexpr int per16 = 8;        // elements per 16-byte chunk
+    static constexpr int row_bytes = 80;   // 32 bf16 + 16 bytes of padding
+};
+template <> struct TileFmt<kFP32> {
+    static constexpr int planes = 1;
+    static constexpr int per16 = 4;
+    static constexpr int row_bytes = 144;  // 32 floats + 16 bytes of padding
+};
+
+template <int P>
+__host__ __device__ constexpr int screen_stage_bytes()
+{
+    return TileFmt<P>::planes * (kTR + kTW) * TileFmt<P>::row_bytes;
+}
+
+// Tile t of the launch for workgroup `bid`: workgroups are dealt round-robin to
+// the 8 XCDs, so XCD x gets the contiguous tile range [x*per, (x+1)*per) and
+// its concurrently resident workgroups share row blocks of A in its L2.
+__device__ __forceinline__ int xcd_tile(int bid, int total)
+{
+    const int per = (total + 7) >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int pending, int T)
+{
+    typedef TileFmt<P> F;
+    constexpr int kChunkRow = kTK / F::per16;              // 16-byte chunks per row and plane
+    constexpr int kAChunks = F::planes * kTR * kChunkRow;  // 2048 in both formats
+    constexpr int kChunks = F::planes * (kTR + kTW) * kChunkRow;
+    constexpr int kPer = kChunks / kThreads;               // 6
+    static_assert(kChunks % kThreads == 0, "chunk split");
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int nrb = (a.m_pad + kTR - 1) / kTR, ncb = (a.z_pad + kTW - 1) / kTW;
+    const int t = xcd_tile(blockIdx.x, nrb * ncb);
+    if (t >= nrb * ncb) return;
+    const int rb = t / ncb, cb = t - rb * ncb;
+    const int R0 = rb * kTR, C0 = cb * kTW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int wr = wave & 3, wc = wave >> 2;
+    const int lda = a.lda;
+
+    // this thread's 16-byte chunks of a stage: global element offset (without
+    // the K offset), LDS byte offset, and whether the source row exists
+    const unsigned char* src[kPer];
+    int dst[kPer];
+    bool ok[kPer];
+    const size_t zl = (size_t)a.z_pad * lda;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int u = tid + i * kThreads;
+        if (u < kAChunks) {
+            const int plane = u / (kTR * kChunkRow), rem = u - plane * kTR * kChunkRow;
+            const int row = rem / kChunkRow, part = rem - row * kChunkRow;
+            ok[i] = R0 + row < a.m_pad;
+            const size_t off = (size_t)(ok[i] ? R0 + row : 0) * lda + part * F::per16;
+            if (P == kBF16X3)
+                src[i] = (const unsigned char*)((plane ? a.Alo : a.Ahi) + off);
+            else
+                src[i] = (const unsigned char*)(a.A32 + off);
+            dst[i] = (plane * kTR + row) * F::row_bytes + part * 16;
+        } else {
+            const int v = u - kAChunks;
+            const int plane = v / (kTW * kChunkRow), rem = v - plane * kTW * kChunkRow;
+            const int row = rem / kChunkRow, part = rem - row * kChunkRow;
+            ok[i] = C0 + row < a.z_pad;
+            const size_t off = (size_t)(ok[i] ? C0 + row : 0) * lda + part * F::per16;
+            if (P == kBF16X3)
+                src[i] = (const unsigned char*)((const __bf16*)a.Dop + plane * zl + off);
+            else
+                src[i] = (const unsigned char*)((const float*)a.Dop + off);
+            dst[i] = (F::planes * kTR + plane * kTW + row) * F::row_bytes + part * 16;
+        }
+    }
+    const int esz = 16 / F::per16;   // bytes per element
+    uint4 buf[kPer];
+    auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            buf[i] = ok[i] ? *(const uint4*)(src[i] + (size_t)k0 * esz) : make_uint4(0, 0, 0, 0);
+    };
+    auto deposit = [&](int stage) __attribute__((always_inline)) {
+        unsigned char* base = smem + stage * screen_stage_bytes<P>();
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) *(uint4*)(base + dst[i]) = buf[i];
+    };
+
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+
+    const bool wave_rows = R0 + wr * 64 < a.m_pad;
+    const int nk = lda / kTK;
+    fetch(0);
+    deposit(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) fetch((kt + 1) * kTK);
+        const unsigned char* base = smem + (kt & 1) * screen_stage_bytes<P>();
+        if (wave_rows) {
+            if (P == kBF16X3) {
+                const unsigned char* Ab = base;
+                const unsigned char* Db = base + 2 * kTR * F::row_bytes;
+                bf16x8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const int row = wr * 64 + rt * 16 + c;
+                    ah[rt] = *(const bf16x8*)(Ab + row * F::row_bytes + 16 * g);
+                    al[rt] = *(const bf16x8*)(Ab + (kTR + row) * F::row_bytes + 16 * g);
+                }
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int w = wc * 64 + ct * 16 + c;
+                    bh[ct] = *(const bf16x8*)(Db + w * F::row_bytes + 16 * g);
+                    bl[ct] = *(const bf16x8*)(Db + (kTW + w) * F::row_bytes + 16 * g);
+                }
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < 4; ++ct) {
+                        acc[rt][ct] = mma_bf16(al[rt], bh[ct], acc[rt][ct]);
+                        acc[rt][ct] = mma_bf16(ah[rt], bl[ct], acc[rt][ct]);
+                        acc[rt][ct] = mma_bf16(ah[rt], bh[ct], acc[rt][ct]);
+                    }
+            } else {
+                const unsigned char* Ab = base;
+                const unsigned char* Db = base + kTR * F::row_bytes;
+                float4 av[4][2], bv[4][2];
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const int row = wr * 64 + rt * 16 + c;
+                    av[rt][0] = *(const float4*)(Ab + row * F::row_bytes + 32 * g);
+                    av[rt][1] = *(const float4*)(Ab + row * F::row_bytes + 32 * g + 16);
+                }
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct) {
+                    const int w = wc * 64 + ct * 16 + c;
+                    bv[ct][0] = *(const float4*)(Db + w * F::row_bytes + 32 * g);
+                    bv[ct][1] = *(const float4*)(Db + w * F::row_bytes + 32 * g + 16);
+                }
+                // MFMA e takes K index 8g + e from lane group g, for A and D alike
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                        for (int ct = 0; ct < 4; ++ct)
+                            acc[rt][ct] = mma_f32((&av[rt][e >> 2].x)[e & 3],
+                                                  (&bv[ct][e >> 2].x)[e & 3], acc[rt][ct]);
+            }
+        }
+        if (kt + 1 < nk) deposit((kt + 1) & 1);
+        __syncthreads();
+    }
+    if (!wave_rows) return;
+
+    // fused epilogue: deferred slack update, new product, interval bounds
+    float* S = (float*)a.S;
+    float* Gb = (float*)a.G;
+    const int Q = a.m_pad >> 4, ngroups = a.m_pad / kRowGroup;
+    const int grp = (R0 + wr * 64) / kRowGroup;
+    const float bscale = a.u_s * (float)T * kHighGrow;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int cbase = C0 + wc * 64 + ct * 16;
+        if (cbase >= a.z_pad) break;
+        const int tile = cbase / kChainTile, chain = cbase + c;
+        const bool active = chain < a.z;
+        const float ed = active ? (float)(a.dn[chain] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+        const float Ek = (float)a.E[chain] * kHighGrow;
+        const float th = (float)a.theta[chain];
+        float up = kInf, um = kInf, lp = kInf, lm = kInf;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            const int q = ((R0 + wr * 64) >> 4) + rt;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
+                const int row = 16 * q + out_row<false>(g, r);
+                const float gv = acc[rt][ct][r];
+                float sv = S[idx];
+                if (pending) {
+                    sv = fmaf(-th, Gb[idx], sv);
+                    S[idx] = sv;
+                }
+                Gb[idx] = gv;
+                const float na = a.rownorm[row];
+                const float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                const float e = na * ed;
+                float lo_p, hi_p, lo_m, hi_m;
+                ratio_bounds(sv, gv, dl, e, lo_p, hi_p, lo_m, hi_m);
+                up = fminf(up, hi_p);
+                um = fminf(um, hi_m);
+                lp = fminf(lp, lo_p);
+                lm = fminf(lm, lo_m);
+            }
+        }
+#pragma unroll
+        for (int o = 16; o <= 32; o <<= 1) {
+            up = fminf(up, __shfl_xor(up, o, 64));
+            um = fminf(um, __shfl_xor(um, o, 64));
+            lp = fminf(lp, __shfl_xor(lp, o, 64));
+            lm = fminf(lm, __shfl_xor(lm, o, 64));
+        }
+        if (g == 0) {
+            const size_t base = ((size_t)tile * ngroups + grp) * 2 * kChainTile + c;
+            a.L[base] = lp;
+            a.L[base + kChainTile] = lm;
+            a.Ug[base] = up;
+            a.Ug[base + kChainTile] = um;
+        }
+    }
+}
+
+// Chords of step `step` for one 16-walk tile (do_chords), then the directions
+// of step `dir_step` (gen_dirs) as FP64 rows, norms and the screening operand.
+template <int P>
+__global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint64_t step,
+                                                                int s_rel, int T, int do_chords,
+                                                                int gen_dirs, uint64_t dir_step)
+{
+    __shared__ ChainLds cs_lds;
+    ChainLds* cs = &cs_lds;
+    const int tid = threadIdx.x;
+    const int tile = blockIdx.x, c0 = tile * kChainTile;
+    const int lda = a.lda, n = a.n;
+    if (do_chords) {
+        const int ngroups = a.m_pad / kRowGroup;
+        if (tid < kChainTile) {
+            const int chain = c0 + tid;
+            cs->theta[tid] = a.theta[chain];
+            cs->E[tid] = a.E[chain];
+            cs->dnorm[tid] = a.dn[chain];
+            cs->flags[tid] = 0;
+            cs->up[tid] = __float_as_uint(kInf);
+            cs->um[tid] = __float_as_uint(kInf);
+        }
+        if (tid == 0) cs->exact = 0;
+        __syncthreads();
+        {
+            // chord-end bounds: minimum of the per-group upper bounds
+            const int c = tid & 15;
+            const float* Ut = a.Ug + (size_t)tile * ngroups * 2 * kChainTile;
+            float up = kInf, um = kInf;
+            for (int q = tid >> 4; q < ngroups; q += kThreads / kChainTile) {
+                up = fminf(up, Ut[(q * 2 + 0) * kChainTile + c]);
+                um = fminf(um, Ut[(q * 2 + 1) * kChainTile + c]);
+            }
+            up = fminf(up, __shfl_xor(up, 16, 64));
+            up = fminf(up, __shfl_xor(up, 32, 64));
+            um = fminf(um, __shfl_xor(um, 16, 64));
+            um = fminf(um, __shfl_xor(um, 32, 64));
+            if ((tid & 63) < kChainTile) {
+                atomicMin(&cs->up[c], __float_as_uint(up));
+                atomicMin(&cs->um[c], __float_as_uint(um));
+            }
+        }
+        __syncthreads();
+        exact_chords<P>(a, cs, tile, c0, step, s_rel, T);
+        __syncthreads();
+        if (tid < kChainTile) {
+            const int chain = c0 + tid;
+            a.theta[chain] = cs->theta[tid];
+            a.E[chain] = cs->E[tid];
+            if (cs->flags[tid] && chain < a.z) atomicOr(&a.flags[chain], cs->flags[tid]);
+        }
+        if (tid == 0 && cs->exact) atomicAdd(&a.counters[0], cs->exact);
+        __syncthreads();
+    }
+    if (!gen_dirs) return;
+    make_directions(a, cs, c0, dir_step);
+    __syncthreads();
+    if (tid < kChainTile) a.dn[c0 + tid] = cs->dnorm[tid];
+    if (P == kBF16X3) {
+        __bf16* Dh = (__bf16*)a.Dop;
+        __bf16* Dl = Dh + (size_t)a.z_pad * lda;
+        for (int item = tid; item < kChainTile * lda; item += kThreads) {
+            const int cl = item / lda, j = item - cl * lda, chain = c0 + cl;
+            const size_t o = (size_t)chain * lda + j;
+            const float v = (chain < a.z && j < n) ? (float)a.D[o] : 0.0f;
+            __bf16 hi, lo;
+            split_bf16(v, hi, lo);
+            Dh[o] = hi;
+            Dl[o] = lo;
+        }
+    } else {
+        float* Df = (float*)a.Dop;
+        for (int item = tid; item < kChainTile * lda; item += kThreads) {
+            const int cl = item / lda, j = item - cl * lda, chain = c0 + cl;
+            const size_t o = (size_t)chain * lda + j;
+            Df[o] = (chain < a.z && j < n) ? (float)a.D[o] : 0.0f;
+        }
+    }
+}
+
+// Exact FP64 slack s = b - A X over (256-row x 64-walk) tiles on the FP64
+// matrix cores, stored in the screening layout; workgroups of the first row
+// block also reset the drift coefficient of their walks.
+constexpr int kRR = 256, kRW = 64, kRK = 16;
+constexpr int kRRowBytes = kRK * 8 + 16;
+constexpr int kRStage = (kRR + kRW) * kRRowBytes;
+
+__global__ __launch_bounds__(kThreads) void tiled_recompute_kernel(StepArgs a)
+{
+    constexpr int kChunkRow = kRK * 8 / 16;                 // 8
+    constexpr int kAChunks = kRR * kChunkRow;               // 2048
+    constexpr int kPer = (kRR + kRW) * kChunkRow / kThreads;  // 5
+    static_assert((kRR + kRW) * kChunkRow % kThreads == 0, "chunk split");
+    extern __shared__ __align__(16) unsigned char smem[];
+
+    const int nrb = (a.m_pad + kRR - 1) / kRR, ncb = (a.z_pad + kRW - 1) / kRW;
+    const int t = xcd_tile(blockIdx.x, nrb * ncb);
+    if (t >= nrb * ncb) return;
+    const int rb = t / ncb, cb = t - rb * ncb;
+    const int R0 = rb * kRR, C0 = cb * kRW;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int wr = wave & 3, wc = wave >> 2;   // 64 rows x 32 walks per wave
+    const int lda = a.lda, n = a.n;
+
+    if (rb == 0) {
+        // drift coefficient after an exact recompute (one wave per walk)
+        for (int w = wave; w < kRW; w += kWaves) {
+            const int chain = C0 + w;
+            if (chain >= a.z_pad) break;
+            double v = 0.0;
+            for (int j = lane; j < n; j += 64) {
+                const double x = a.X[(size_t)chain * lda + j];
+                v = fma(x, x, v);
+            }
+            v = wave_sum(v);
+            if (lane == 0)
+                a.E[chain] = ((double)a.u_s * (1.0 + 0x1.0p-20) + (2.0 * n + 4.0) * 0x1.0p-53) * sqrt(v);
+        }
+    }
+
+    const double* src[kPer];
+    int dst[kPer];
+    bool ok[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+        const int u = tid + i * kThreads;
+        if (u < kAChunks) {
+            const int row = u / kChunkRow, part = u - row * kChunkRow;
+            ok[i] = R0 + row < a.m_pad;
+            src[i] = a.A64 + (size_t)(ok[i] ? R0 + row : 0) * lda + part * 2;
+            dst[i] = row * kRRowBytes + part * 16;
+        } else {
+            const int v = u - kAChunks;
+            const int row = v / kChunkRow, part = v - row * kChunkRow;
+            ok[i] = C0 + row < a.z_pad;
+            src[i] = a.X + (size_t)(ok[i] ? C0 + row : 0) * lda + part * 2;
+            dst[i] = (kRR + row) * kRRowBytes + part * 16;
+        }
+    }
+    uint4 buf[kPer];
+    auto fetch = [&](int k0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < kPer; ++i)
+            buf[i] = ok[i] ? *(const uint4*)(src[i] + k0) : make_uint4(0, 0, 0, 0);
+    };
+    auto deposit = [&](int stage) __attribute__((always_inline)) {
+        unsigned char* base = smem + stage * kRStage;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) *(uint4*)(base + dst[i]) = buf[i];
+    };
+
+    f64x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
+    const bool wave_rows = R0 + wr * 64 < a.m_pad;
+    const int nk = lda / kRK;
+    fetch(0);
+    deposit(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) fetch((kt + 1) * kRK);
+        const unsigned char* base = smem + (kt & 1) * kRStage;
+        if (wave_rows) {
+            double2 av[4][2], bv[2][2];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const unsigned char* p = base + (wr * 64 + rt * 16 + c) * kRRowBytes + 32 * g;
+                av[rt][0] = *(const double2*)p;
+                av[rt][1] = *(const double2*)(p + 16);
+            }
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+                const unsigned char* p = base + (kRR + wc * 32 + ct * 16 + c) * kRRowBytes + 32 * g;
+                bv[ct][0] = *(const double2*)p;
+                bv[ct][1] = *(const double2*)(p + 16);
+            }
+            // MFMA i takes K index 4g + i from lane group g, for A and X alike
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+                    for (int ct = 0; ct < 2; ++ct)
+                        acc[rt][ct] = mma_f64((&av[rt][i >> 1].x)[i & 1],
+                                              (&bv[ct][i >> 1].x)[i & 1], acc[rt][ct]);
+        }
+        if (kt + 1 < nk) deposit((kt + 1) & 1);
+        __syncthreads();
+    }
+    if (!wave_rows) return;
+    float* S = (float*)a.S;
+    const int Q = a.m_pad >> 4;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+        const int cbase = C0 + wc * 32 + ct * 16;
+        if (cbase >= a.z_pad) break;
+        const int tile = cbase / kChainTile, chain = cbase + c;
+        const bool active = chain < a.z;
+        int fl = 0;
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = R0 + wr * 64 + rt * 16 + out_row<true>(g, r);
+                const double bi = a.b64[row];
+                const double s = bi - acc[rt][ct][r];
+                if (active && row < a.m) {
+                    if (!(s > 0.0)) fl |= kNotInterior;
+                    if (s < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
+                }
+                S[frag_index<false>(tile, Q, row, c)] = (float)s;
+            }
+        }
+        fl |= __shfl_xor(fl, 16, 64);
+        fl |= __shfl_xor(fl, 32, 64);
+        if (g == 0 && fl) atomicOr(&a.flags[chain], fl);
     }
 }
 
@@ -828,6 +1404,9 @@ inline int grid_for(int64_t total, int threads)
 
 }  // namespace
 
+static_assert((size_t)kChainTile * (kMaxN + 2) * sizeof(double) + sizeof(ChainLds) <= 163840,
+              "the general kernel's LDS must fit one CU at the largest n");
+
 size_t step_lds_bytes(int prec, int lda)
 {
     (void)prec;
@@ -884,6 +1463,60 @@ int batch_blocks_per_cu(int prec, int max_lda)
         return 1;
     }
     return nb < 1 ? 1 : nb;
+}
+
+template <int P>
+static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream)
+{
+    const size_t lds_s = 2 * (size_t)screen_stage_bytes<P>();
+    const size_t lds_r = 2 * (size_t)kRStage;
+    hipError_t e = hipFuncSetAttribute((const void*)tiled_screen_kernel<P>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)tiled_recompute_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
+    if (e != hipSuccess) return e;
+    const int ts = ((a.m_pad + kTR - 1) / kTR) * ((a.z_pad + kTW - 1) / kTW);
+    const int tr = ((a.m_pad + kRR - 1) / kRR) * ((a.z_pad + kRW - 1) / kRW);
+    const dim3 grid_s((ts + 7) / 8 * 8), grid_r((tr + 7) / 8 * 8), grid_c(a.z_pad / kChainTile);
+    int pending = a.pending0, T = a.T0, since = a.since0;
+    if (a.recompute_first) {
+        hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kThreads), lds_r, stream, a);
+        pending = 0;
+        T = 2;
+        since = 0;
+    }
+    if (a.steps > 0)
+        hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a,
+                           (uint64_t)0, 0, T, 0, 1, a.step0);
+    for (int s = 0; s < a.steps; ++s) {
+        const uint64_t step = a.step0 + (uint64_t)s;
+        hipLaunchKernelGGL(tiled_screen_kernel<P>, grid_s, dim3(kThreads), lds_s, stream, a,
+                           pending, T);
+        hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a, step, s,
+                           T, 1, (int)(s + 1 < a.steps), step + 1);
+        pending = 1;
+        T += 1;
+        since += 1;
+        if (since >= a.R) {
+            hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kThreads), lds_r, stream, a);
+            pending = 0;
+            T = 2;
+            since = 0;
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream)
+{
+    switch (prec) {
+    case kFP32: return launch_tiled_t<kFP32>(a, stream);
+    case kBF16X3: return launch_tiled_t<kBF16X3>(a, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream)

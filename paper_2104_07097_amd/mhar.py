@@ -43,7 +43,8 @@ class MharError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("recompute_every", ctypes.c_int32),
-                ("steps_per_launch", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("steps_per_launch", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Stats(ctypes.Structure):
@@ -140,12 +141,16 @@ def _make_module_functions():
 globals().update(_make_module_functions())
 
 
-def options(precision="fp32", recompute_every=50, steps_per_launch=0) -> Options:
+PATHS = {"auto": 0, "general": 1, "resident": 2, "tiled": 3}
+
+
+def options(precision="fp32", recompute_every=50, steps_per_launch=0, path="auto") -> Options:
     o = Options()
     _check(load().mhar_options_default(ctypes.byref(o)))
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     o.recompute_every = int(recompute_every)
     o.steps_per_launch = int(steps_per_launch)
+    o.path = PATHS[path] if isinstance(path, str) else int(path)
     return o
 
 
@@ -163,7 +168,7 @@ class Problem:
     """{x : A x <= b, A_eq x = b_eq} set up on the device (mhar_problem_create)."""
 
     def __init__(self, A, b, A_eq=None, b_eq=None, precision="fp32", recompute_every=50,
-                 steps_per_launch=0):
+                 steps_per_launch=0, path="auto"):
         import torch
         self.torch = torch
         lib = load()
@@ -177,7 +182,7 @@ class Problem:
             b_eq = b_eq.to(device=self.device, dtype=torch.float64).contiguous()
             m_eq = A_eq.shape[0]
         self.n, self.m, self.m_eq = n, m, m_eq
-        self.opt = options(precision, recompute_every, steps_per_launch)
+        self.opt = options(precision, recompute_every, steps_per_launch, path)
         sz = ctypes.c_size_t()
         _check(lib.mhar_problem_workspace_size(n, m, m_eq, ctypes.byref(self.opt), ctypes.byref(sz)))
         self._ws, ptr, nbytes = _workspace(torch, sz.value, self.device)

@@ -16,13 +16,13 @@ def announce(*parts):
     print("[gpu-case]", *parts, flush=True)
 
 
-def make(p, precision, recompute_every=50, seed=0, chain_offset=0, X0=None):
+def make(p, precision, recompute_every=50, seed=0, chain_offset=0, X0=None, path="auto"):
     import torch
     from paper_2104_07097_amd import mhar
     dev = device()
     t = lambda a: None if a is None else torch.tensor(a, device=dev, dtype=torch.float64)
     prob = mhar.Problem(t(p.A), t(p.b), t(p.A_eq), t(p.b_eq), precision=precision,
-                        recompute_every=recompute_every)
+                        recompute_every=recompute_every, path=path)
     ch = mhar.Chains(prob, t(p.X0 if X0 is None else X0), seed=seed, chain_offset=chain_offset)
     return prob, ch
 

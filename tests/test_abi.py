@@ -72,3 +72,13 @@ def test_create_rejects_null_and_misaligned():
                                    ctypes.byref(h)) == mhar.E_WORKSPACE
     assert lib.mhar_step(None, 1, None) == mhar.E_INVALID_ARG
     assert lib.mhar_chains_destroy(None) == mhar.OK
+
+
+@pytest.mark.parametrize("prec,path,code", [("fp32", 4, mhar.E_INVALID_ARG), ("fp32", -1, mhar.E_INVALID_ARG),
+                                            ("fp64", "tiled", mhar.E_UNSUPPORTED),
+                                            ("bf16x3", "tiled", mhar.OK), ("fp64", "general", mhar.OK)])
+def test_path_option_checked(prec, path, code):
+    lib = mhar.load()
+    o = mhar.options(prec, path=path)
+    sz = ctypes.c_size_t()
+    assert lib.mhar_problem_workspace_size(50, 100, 0, ctypes.byref(o), ctypes.byref(sz)) == code
