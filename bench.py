@@ -247,7 +247,7 @@ def bench_rotbox(args):
     exact = exact[np.all(exact @ p.A.T <= p.b, axis=1)]
     out = {}
     for mode in ("plain", "learned"):
-        prob, ch = _make(p, "fp32")
+        prob, ch = _make(p, "bf16x3")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if mode == "learned":
@@ -277,7 +277,7 @@ def bench_rotbox(args):
         ch.close()
         prob.close()
     line = _base_line(out["learned"]["chain_steps_per_sec"], steps, args.burnin,
-                      steps / out["learned"]["chain_steps_per_sec"] * p.z, "fp32",
+                      steps / out["learned"]["chain_steps_per_sec"] * p.z, "bf16x3",
                       {"workload": "rotated box n=1000 (sides log-uniform in [1e-3,1]) + 8000 "
                                    "unit-norm halfspaces at distance 1, z=8192 from the centre",
                        "rank": args.rank, "burnin": args.burnin, "window_steps": steps})

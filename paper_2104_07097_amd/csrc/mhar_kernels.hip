@@ -89,6 +89,73 @@ __device__ __forceinline__ void chord_row(ChainLds* cs, int cl, double s, double
         atomicMin(&cs->nlmin_bits[cl], (unsigned long long)__double_as_longlong(-(s / gg)));
 }
 
+// Exact evaluation of listed candidates through LDS: batches of `nb_max`
+// candidates, one per thread; for each chunk of C coordinates the workgroup
+// stages the candidates' rows of A and the x and d rows of the 16 walks with
+// coalesced 16-byte loads, then every thread continues its sequential sums
+// from LDS.  Same arithmetic, in the same order, as exact_row.
+__device__ void exact_rows_staged(const StepArgs& a, ChainLds* cs, int c0, int nc, double* stage,
+                                  int nb_max, int C)
+{
+    const int tid = threadIdx.x;
+    const int n = a.n, lda = a.lda;
+    const int ld = C + 2;                     // LDS row stride (doubles), keeps 16-byte alignment
+    for (int b0 = 0; b0 < nc; b0 += nb_max) {
+        const int nb = min(nb_max, nc - b0);
+        const int rows = nb + 2 * kChainTile;
+        int2 rc = make_int2(0, 0);
+        double s = 0.0, gg = 0.0;
+        if (tid < nb) {
+            rc = cs->cand[b0 + tid];
+            s = a.b64[rc.x];
+        }
+        for (int j0 = 0; j0 < n; j0 += C) {
+            const int cw = min(C, lda - j0);      // staged width: whole padded row, even
+            const int halves = cw >> 1;
+            __syncthreads();                      // the previous chunk is consumed
+            for (int e = tid; e < rows * halves; e += kThreads) {
+                const int r = e / halves, h = e - r * halves;
+                const double* src;
+                if (r < nb) {
+                    src = a.A64 + (size_t)cs->cand[b0 + r].x * lda;
+                } else {
+                    const int w = r - nb, cl = w & (kChainTile - 1);
+                    const int chain = min(c0 + cl, a.z_pad - 1);
+                    src = (w < kChainTile ? a.X : a.D) + (size_t)chain * lda;
+                }
+                *(double2*)(stage + r * ld + 2 * h) = *(const double2*)(src + j0 + 2 * h);
+            }
+            __syncthreads();
+            if (tid < nb) {
+                const double* av = stage + tid * ld;
+                const double* xv = stage + (nb + rc.y) * ld;
+                const double* dv = stage + (nb + kChainTile + rc.y) * ld;
+                const int len = min(C, n - j0);
+                int j = 0;
+                for (; j + 8 <= len; j += 8) {
+                    double a8[8], x8[8], d8[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        a8[u] = av[j + u];
+                        x8[u] = xv[j + u];
+                        d8[u] = dv[j + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        s = __dsub_rn(s, __dmul_rn(a8[u], x8[u]));
+                        gg = __dadd_rn(gg, __dmul_rn(a8[u], d8[u]));
+                    }
+                }
+                for (; j < len; ++j) {
+                    s = __dsub_rn(s, __dmul_rn(av[j], xv[j]));
+                    gg = __dadd_rn(gg, __dmul_rn(av[j], dv[j]));
+                }
+            }
+        }
+        if (tid < nb) chord_row(cs, rc.y, s, gg, a.b64[rc.x]);
+    }
+}
+
 __host__ __device__ inline int x_ld(int lda) { return lda + 2; }     // FP64 LDS row stride
 __host__ __device__ inline int f32_ld(int lda) { return lda + 4; }   // FP32 LDS row stride
 __host__ __device__ inline int bf_ld(int lda) { return lda + 8; }    // bf16 LDS row stride
@@ -455,9 +522,11 @@ __device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int 
 // ---------------------------------------------------------------------------
 // Phase D: exact chords of the candidate rows, theta, state update.
 // ---------------------------------------------------------------------------
+// `stage` (stage_bytes of LDS free during this phase, may be null) carries the
+// candidates' rows through LDS when it holds at least 16 coordinates of them.
 template <int P>
 __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, uint64_t step,
-                             int64_t s_rel, int T)
+                             int64_t s_rel, int T, double* stage, size_t stage_bytes)
 {
     typedef typename Op<P>::state_t st_t;
     constexpr bool F64 = Op<P>::f64;
@@ -534,14 +603,21 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
 
     // 2. exact FP64 evaluation of the listed rows, all in parallel
     const int nc = min(cs->ncand, kCandCap);
-    for (int t = tid; t < nc; t += kThreads) {
-        const int2 rc = cs->cand[t];
-        const int chain = c0 + rc.y;
-        double s, gg;
-        const double bi = a.b64[rc.x];
-        exact_row(a.A64 + (size_t)rc.x * lda, a.X + (size_t)chain * lda, a.D + (size_t)chain * lda,
-                  bi, n, s, gg);
-        chord_row(cs, rc.y, s, gg, bi);
+    const int nb_max = 96;
+    int C = stage ? (int)(stage_bytes / (sizeof(double) * (nb_max + 2 * kChainTile))) - 2 : 0;
+    C = min(C, 128) & ~15;
+    if (C >= 16) {
+        exact_rows_staged(a, cs, c0, nc, stage, nb_max, C);
+    } else {
+        for (int t = tid; t < nc; t += kThreads) {
+            const int2 rc = cs->cand[t];
+            const int chain = c0 + rc.y;
+            double s, gg;
+            const double bi = a.b64[rc.x];
+            exact_row(a.A64 + (size_t)rc.x * lda, a.X + (size_t)chain * lda,
+                      a.D + (size_t)chain * lda, bi, n, s, gg);
+            chord_row(cs, rc.y, s, gg, bi);
+        }
     }
     __syncthreads();
 
@@ -703,7 +779,7 @@ __device__ void run_tile(const StepArgs& a, unsigned char* smem, int tile)
         stage_operand<P>(a, big, c0);
         screen<P>(a, cs, big, tile, c0, pending, T);
         __syncthreads();
-        exact_chords<P>(a, cs, tile, c0, step, s, T);
+        exact_chords<P>(a, cs, tile, c0, step, s, T, (double*)big, big_bytes(a.lda));
         __syncthreads();
         pending = 1;
         T += 1;
@@ -774,6 +850,9 @@ __global__ __launch_bounds__(kThreads) void mhar_batch_kernel(const StepArgs* __
 // The arithmetic that decides a trajectory (directions, exact chords, theta,
 // update) is the same code as the single-kernel path, so trajectories agree.
 // ---------------------------------------------------------------------------
+// LDS the chords kernel lends to the exact evaluation: 96 candidates and the
+// x and d rows of 16 walks, 64 coordinates at a time
+constexpr int kChordStageBytes = (96 + 2 * kChainTile) * (64 + 2) * 8;
 constexpr int kTR = 256;   // rows per screening tile
 constexpr int kTW = 128;   // walks per screening tile
 constexpr int kTK = 32;    // K per LDS stage
@@ -859,16 +938,23 @@ __global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int 
         }
     }
     const int esz = 16 / F::per16;   // bytes per element
-    uint4 buf[kPer];
-    auto fetch = [&](int k0) __attribute__((always_inline)) {
+    const int nk = lda / kTK;
+    // K-steps are fetched kDepth ahead into a ring of register buffers (K-step
+    // k in slot k % kDepth) and deposited into the LDS stage the next K-step
+    // reads from, so about kDepth K-steps of compute cover the load latency.
+    constexpr int kDepth = 3;
+    uint4 ring[kDepth][kPer];
+    auto fetch = [&](uint4* dst, int k) __attribute__((always_inline)) {
+        const bool live = k < nk;
 #pragma unroll
         for (int i = 0; i < kPer; ++i)
-            buf[i] = ok[i] ? *(const uint4*)(src[i] + (size_t)k0 * esz) : make_uint4(0, 0, 0, 0);
+            dst[i] = (live && ok[i]) ? *(const uint4*)(src[i] + (size_t)k * kTK * esz)
+                                     : make_uint4(0, 0, 0, 0);
     };
-    auto deposit = [&](int stage) __attribute__((always_inline)) {
+    auto deposit = [&](const uint4* from, int stage) __attribute__((always_inline)) {
         unsigned char* base = smem + stage * screen_stage_bytes<P>();
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) *(uint4*)(base + dst[i]) = buf[i];
+        for (int i = 0; i < kPer; ++i) *(uint4*)(base + dst[i]) = from[i];
     };
 
     f32x4 acc[4][4];
@@ -878,67 +964,77 @@ __global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int 
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
     const bool wave_rows = R0 + wr * 64 < a.m_pad;
-    const int nk = lda / kTK;
-    fetch(0);
-    deposit(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) fetch((kt + 1) * kTK);
-        const unsigned char* base = smem + (kt & 1) * screen_stage_bytes<P>();
-        if (wave_rows) {
-            if (P == kBF16X3) {
-                const unsigned char* Ab = base;
-                const unsigned char* Db = base + 2 * kTR * F::row_bytes;
-                bf16x8 ah[4], al[4], bh[4], bl[4];
+    auto compute = [&](int stage) __attribute__((always_inline)) {
+        const unsigned char* base = smem + stage * screen_stage_bytes<P>();
+        if (!wave_rows) return;
+        if (P == kBF16X3) {
+            const unsigned char* Ab = base;
+            const unsigned char* Db = base + 2 * kTR * F::row_bytes;
+            bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
-                for (int rt = 0; rt < 4; ++rt) {
-                    const int row = wr * 64 + rt * 16 + c;
-                    ah[rt] = *(const bf16x8*)(Ab + row * F::row_bytes + 16 * g);
-                    al[rt] = *(const bf16x8*)(Ab + (kTR + row) * F::row_bytes + 16 * g);
-                }
+            for (int rt = 0; rt < 4; ++rt) {
+                const int row = wr * 64 + rt * 16 + c;
+                ah[rt] = *(const bf16x8*)(Ab + row * F::row_bytes + 16 * g);
+                al[rt] = *(const bf16x8*)(Ab + (kTR + row) * F::row_bytes + 16 * g);
+            }
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const int w = wc * 64 + ct * 16 + c;
+                bh[ct] = *(const bf16x8*)(Db + w * F::row_bytes + 16 * g);
+                bl[ct] = *(const bf16x8*)(Db + (kTW + w) * F::row_bytes + 16 * g);
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < 4; ++ct) {
-                    const int w = wc * 64 + ct * 16 + c;
-                    bh[ct] = *(const bf16x8*)(Db + w * F::row_bytes + 16 * g);
-                    bl[ct] = *(const bf16x8*)(Db + (kTW + w) * F::row_bytes + 16 * g);
+                    acc[rt][ct] = mma_bf16(al[rt], bh[ct], acc[rt][ct]);
+                    acc[rt][ct] = mma_bf16(ah[rt], bl[ct], acc[rt][ct]);
+                    acc[rt][ct] = mma_bf16(ah[rt], bh[ct], acc[rt][ct]);
                 }
+        } else {
+            const unsigned char* Ab = base;
+            const unsigned char* Db = base + kTR * F::row_bytes;
+            float4 av[4][2], bv[4][2];
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const int row = wr * 64 + rt * 16 + c;
+                av[rt][0] = *(const float4*)(Ab + row * F::row_bytes + 32 * g);
+                av[rt][1] = *(const float4*)(Ab + row * F::row_bytes + 32 * g + 16);
+            }
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) {
+                const int w = wc * 64 + ct * 16 + c;
+                bv[ct][0] = *(const float4*)(Db + w * F::row_bytes + 32 * g);
+                bv[ct][1] = *(const float4*)(Db + w * F::row_bytes + 32 * g + 16);
+            }
+            // MFMA e takes K index 8g + e from lane group g, for A and D alike
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                    for (int ct = 0; ct < 4; ++ct) {
-                        acc[rt][ct] = mma_bf16(al[rt], bh[ct], acc[rt][ct]);
-                        acc[rt][ct] = mma_bf16(ah[rt], bl[ct], acc[rt][ct]);
-                        acc[rt][ct] = mma_bf16(ah[rt], bh[ct], acc[rt][ct]);
-                    }
-            } else {
-                const unsigned char* Ab = base;
-                const unsigned char* Db = base + kTR * F::row_bytes;
-                float4 av[4][2], bv[4][2];
+                    for (int ct = 0; ct < 4; ++ct)
+                        acc[rt][ct] = mma_f32((&av[rt][e >> 2].x)[e & 3],
+                                              (&bv[ct][e >> 2].x)[e & 3], acc[rt][ct]);
+        }
+    };
+
 #pragma unroll
-                for (int rt = 0; rt < 4; ++rt) {
-                    const int row = wr * 64 + rt * 16 + c;
-                    av[rt][0] = *(const float4*)(Ab + row * F::row_bytes + 32 * g);
-                    av[rt][1] = *(const float4*)(Ab + row * F::row_bytes + 32 * g + 16);
-                }
+    for (int u = 0; u < kDepth; ++u) fetch(ring[u], u);
+    deposit(ring[0], 0);
+    __syncthreads();
+    fetch(ring[0], kDepth);
+    for (int k0 = 0; k0 < nk; k0 += kDepth) {
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct) {
-                    const int w = wc * 64 + ct * 16 + c;
-                    bv[ct][0] = *(const float4*)(Db + w * F::row_bytes + 32 * g);
-                    bv[ct][1] = *(const float4*)(Db + w * F::row_bytes + 32 * g + 16);
-                }
-                // MFMA e takes K index 8g + e from lane group g, for A and D alike
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-#pragma unroll
-                    for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-                        for (int ct = 0; ct < 4; ++ct)
-                            acc[rt][ct] = mma_f32((&av[rt][e >> 2].x)[e & 3],
-                                                  (&bv[ct][e >> 2].x)[e & 3], acc[rt][ct]);
+        for (int u = 0; u < kDepth; ++u) {
+            const int k = k0 + u;   // K-step computed here; slot (u + 1) % kDepth holds k + 1
+            if (k < nk) {
+                compute(k & 1);
+                if (k + 1 < nk) deposit(ring[(u + 1) % kDepth], (k + 1) & 1);
+                __syncthreads();
+                fetch(ring[(u + 1) % kDepth], k + 1 + kDepth);
             }
         }
-        if (kt + 1 < nk) deposit((kt + 1) & 1);
-        __syncthreads();
     }
     if (!wave_rows) return;
 
@@ -948,54 +1044,76 @@ __global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int 
     const int Q = a.m_pad >> 4, ngroups = a.m_pad / kRowGroup;
     const int grp = (R0 + wr * 64) / kRowGroup;
     const float bscale = a.u_s * (float)T * kHighGrow;
+    // two halves of two walk tiles each: all slack and product loads of a half
+    // are issued before its arithmetic, so their latency is paid once
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int cbase = C0 + wc * 64 + ct * 16;
-        if (cbase >= a.z_pad) break;
-        const int tile = cbase / kChainTile, chain = cbase + c;
-        const bool active = chain < a.z;
-        const float ed = active ? (float)(a.dn[chain] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
-        const float Ek = (float)a.E[chain] * kHighGrow;
-        const float th = (float)a.theta[chain];
-        float up = kInf, um = kInf, lp = kInf, lm = kInf;
+    for (int half = 0; half < 2; ++half) {
+        float sv[2][4][4], gp[2][4][4];
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            const int q = ((R0 + wr * 64) >> 4) + rt;
+        for (int h = 0; h < 2; ++h) {
+            const int cbase = C0 + wc * 64 + (2 * half + h) * 16;
+            const int tile = min(cbase, a.z_pad - kChainTile) / kChainTile;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
-                const int row = 16 * q + out_row<false>(g, r);
-                const float gv = acc[rt][ct][r];
-                float sv = S[idx];
-                if (pending) {
-                    sv = fmaf(-th, Gb[idx], sv);
-                    S[idx] = sv;
+            for (int rt = 0; rt < 4; ++rt) {
+                const int q = ((R0 + wr * 64) >> 4) + rt;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
+                    sv[h][rt][r] = S[idx];
+                    gp[h][rt][r] = pending ? Gb[idx] : 0.0f;
                 }
-                Gb[idx] = gv;
-                const float na = a.rownorm[row];
-                const float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
-                const float e = na * ed;
-                float lo_p, hi_p, lo_m, hi_m;
-                ratio_bounds(sv, gv, dl, e, lo_p, hi_p, lo_m, hi_m);
-                up = fminf(up, hi_p);
-                um = fminf(um, hi_m);
-                lp = fminf(lp, lo_p);
-                lm = fminf(lm, lo_m);
             }
         }
 #pragma unroll
-        for (int o = 16; o <= 32; o <<= 1) {
-            up = fminf(up, __shfl_xor(up, o, 64));
-            um = fminf(um, __shfl_xor(um, o, 64));
-            lp = fminf(lp, __shfl_xor(lp, o, 64));
-            lm = fminf(lm, __shfl_xor(lm, o, 64));
-        }
-        if (g == 0) {
-            const size_t base = ((size_t)tile * ngroups + grp) * 2 * kChainTile + c;
-            a.L[base] = lp;
-            a.L[base + kChainTile] = lm;
-            a.Ug[base] = up;
-            a.Ug[base + kChainTile] = um;
+        for (int h = 0; h < 2; ++h) {
+            const int ct = 2 * half + h;
+            const int cbase = C0 + wc * 64 + ct * 16;
+            if (cbase >= a.z_pad) break;
+            const int tile = cbase / kChainTile, chain = cbase + c;
+            const bool active = chain < a.z;
+            const float ed = active ? (float)(a.dn[chain] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+            const float Ek = (float)a.E[chain] * kHighGrow;
+            const float th = (float)a.theta[chain];
+            float up = kInf, um = kInf, lp = kInf, lm = kInf;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const int q = ((R0 + wr * 64) >> 4) + rt;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
+                    const int row = 16 * q + out_row<false>(g, r);
+                    const float gv = acc[rt][ct][r];
+                    float s_ = sv[h][rt][r];
+                    if (pending) {
+                        s_ = fmaf(-th, gp[h][rt][r], s_);
+                        S[idx] = s_;
+                    }
+                    Gb[idx] = gv;
+                    const float na = a.rownorm[row];
+                    const float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                    const float e = na * ed;
+                    float lo_p, hi_p, lo_m, hi_m;
+                    ratio_bounds(s_, gv, dl, e, lo_p, hi_p, lo_m, hi_m);
+                    up = fminf(up, hi_p);
+                    um = fminf(um, hi_m);
+                    lp = fminf(lp, lo_p);
+                    lm = fminf(lm, lo_m);
+                }
+            }
+#pragma unroll
+            for (int o = 16; o <= 32; o <<= 1) {
+                up = fminf(up, __shfl_xor(up, o, 64));
+                um = fminf(um, __shfl_xor(um, o, 64));
+                lp = fminf(lp, __shfl_xor(lp, o, 64));
+                lm = fminf(lm, __shfl_xor(lm, o, 64));
+            }
+            if (g == 0) {
+                const size_t base = ((size_t)tile * ngroups + grp) * 2 * kChainTile + c;
+                a.L[base] = lp;
+                a.L[base + kChainTile] = lm;
+                a.Ug[base] = up;
+                a.Ug[base + kChainTile] = um;
+            }
         }
     }
 }
@@ -1008,6 +1126,7 @@ __global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint
                                                                 int gen_dirs, uint64_t dir_step)
 {
     __shared__ ChainLds cs_lds;
+    __shared__ __align__(16) unsigned char stage_lds[kChordStageBytes];
     ChainLds* cs = &cs_lds;
     const int tid = threadIdx.x;
     const int tile = blockIdx.x, c0 = tile * kChainTile;
@@ -1044,7 +1163,7 @@ __global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint
             }
         }
         __syncthreads();
-        exact_chords<P>(a, cs, tile, c0, step, s_rel, T);
+        exact_chords<P>(a, cs, tile, c0, step, s_rel, T, (double*)stage_lds, kChordStageBytes);
         __syncthreads();
         if (tid < kChainTile) {
             const int chain = c0 + tid;
