@@ -134,6 +134,7 @@ struct PrecondBufs {
     double *mean, *Sd, *W, *B, *H;      // n, n, n x r, z x r, n x r
     double *GB, *C, *Cinv, *K;          // r x r each
     double *gU, *gl, *rowterm, *nll;    // n x r, n, n, 2 (NLL, log det C)
+    double* part;                       // split-K partial sums of H and G
     int* status;
 };
 size_t precond_bytes(int n, int r, int z, int lda);

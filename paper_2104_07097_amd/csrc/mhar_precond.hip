@@ -68,22 +68,39 @@ __global__ void scales_kernel(int n, int r, const double* U, const double* logsi
     }
 }
 
-// column means and (1/z) variances of the states
-__global__ void mean_sd_kernel(int n, int z, int lda, const double* __restrict__ X, double* mean,
-                               double* Sd)
+// column means and (1/z) variances of the states (two passes): one block of
+// 8 waves per 64 coordinates, lane = coordinate, each wave a fixed stripe of
+// the states, partial sums combined in a fixed order
+__global__ __launch_bounds__(512) void mean_sd_kernel(int n, int z, int lda,
+                                                      const double* __restrict__ X, double* mean,
+                                                      double* Sd)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ double part[8][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int k = 0; k < z; ++k) s += X[(size_t)k * lda + i];
-    const double mu = s / z;
+    if (i < n)
+        for (int k = wave; k < z; k += 8) s += X[(size_t)k * lda + i];
+    part[wave][lane] = s;
+    __syncthreads();
+    double mu = 0.0;
+    for (int w = 0; w < 8; ++w) mu += part[w][lane];
+    mu /= z;
+    __syncthreads();
     double v = 0.0;
-    for (int k = 0; k < z; ++k) {
-        const double y = X[(size_t)k * lda + i] - mu;
-        v = fma(y, y, v);
+    if (i < n)
+        for (int k = wave; k < z; k += 8) {
+            const double y = X[(size_t)k * lda + i] - mu;
+            v = fma(y, y, v);
+        }
+    part[wave][lane] = v;
+    __syncthreads();
+    if (wave == 0 && i < n) {
+        double vv = 0.0;
+        for (int w = 0; w < 8; ++w) vv += part[w][lane];
+        mean[i] = mu;
+        Sd[i] = vv / z;
     }
-    mean[i] = mu;
-    Sd[i] = v / z;
 }
 
 __global__ void w_kernel(int n, int r, const double* U, const double* logsig, double* W)
@@ -96,99 +113,182 @@ __global__ void w_kernel(int n, int r, const double* U, const double* logsig, do
     }
 }
 
-// B[k][q] = sum_i (X[k][i] - mean_i) W[i][q]: one block per state, one lane per rank column
-__global__ void b_kernel(int n, int r, int lda, const double* __restrict__ X,
-                         const double* __restrict__ mean, const double* __restrict__ W, double* B)
+// B[k][q] = sum_i (X[k][i] - mean_i) W[i][q]: one wave per state (8 per block),
+// one lane per rank column, loads of a block of 8 coordinates issued together
+__global__ __launch_bounds__(512) void b_kernel(int n, int r, int z, int lda,
+                                                const double* __restrict__ X,
+                                                const double* __restrict__ mean,
+                                                const double* __restrict__ W, double* B)
 {
-    const int k = blockIdx.x, q = threadIdx.x;
-    if (q >= r) return;
+    const int q = threadIdx.x & 63, k = blockIdx.x * 8 + (threadIdx.x >> 6);
+    if (q >= r || k >= z) return;
     const double* xr = X + (size_t)k * lda;
     double v = 0.0;
-    for (int i = 0; i < n; ++i) v = fma(xr[i] - mean[i], W[(size_t)i * r + q], v);
+    int i = 0;
+    for (; i + 8 <= n; i += 8) {
+        double y[8], w[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            y[u] = xr[i + u] - mean[i + u];
+            w[u] = W[(size_t)(i + u) * r + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v = fma(y[u], w[u], v);
+    }
+    for (; i < n; ++i) v = fma(xr[i] - mean[i], W[(size_t)i * r + q], v);
     B[(size_t)k * r + q] = v;
 }
 
-// H[i][q] = (1/z) sum_k (X[k][i] - mean_i) B[k][q]: one block per coordinate
-__global__ void h_kernel(int n, int r, int z, int lda, const double* __restrict__ X,
-                         const double* __restrict__ mean, const double* __restrict__ B, double* H)
+// H[i][q] = (1/z) sum_k (X[k][i] - mean_i) B[k][q], split over kSplit chunks of
+// states: block (i-group of 8, chunk) has one wave per coordinate, lane = q;
+// the chunks' partial sums are added in chunk order by h_reduce_kernel.
+constexpr int kSplit = 32;
+__global__ __launch_bounds__(512) void h_part_kernel(int n, int r, int z, int lda,
+                                                     const double* __restrict__ X,
+                                                     const double* __restrict__ mean,
+                                                     const double* __restrict__ B, double* part)
 {
-    const int i = blockIdx.x, q = threadIdx.x;
-    if (q >= r) return;
+    const int q = threadIdx.x & 63, i = blockIdx.x * 8 + (threadIdx.x >> 6), p = blockIdx.y;
+    if (q >= r || i >= n) return;
+    const int per = (z + kSplit - 1) / kSplit, k0 = p * per, k1 = min(z, k0 + per);
     const double mu = mean[i];
     double v = 0.0;
-    for (int k = 0; k < z; ++k) v = fma(X[(size_t)k * lda + i] - mu, B[(size_t)k * r + q], v);
-    H[(size_t)i * r + q] = v / z;
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        double y[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            y[u] = X[(size_t)(k + u) * lda + i] - mu;
+            b[u] = B[(size_t)(k + u) * r + q];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v = fma(y[u], b[u], v);
+    }
+    for (; k < k1; ++k) v = fma(X[(size_t)k * lda + i] - mu, B[(size_t)k * r + q], v);
+    part[((size_t)p * n + i) * r + q] = v;
 }
 
-// G = B^T B / z and C = I + U^T W, one thread per (p, q)
-__global__ void gc_kernel(int n, int r, int z, const double* __restrict__ B,
-                          const double* __restrict__ U, const double* __restrict__ W, double* G,
-                          double* C)
+__global__ void h_reduce_kernel(int n, int r, int z, const double* __restrict__ part, double* H)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= r * r) return;
-    const int p = e / r, q = e - p * r;
+    const int64_t total = (int64_t)n * r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int p = 0; p < kSplit; ++p) v += part[(size_t)p * total + e];
+        H[e] = v / z;
+    }
+}
+
+// Partial sums of G = B^T B over kSplit chunks of states: block p stages its
+// rows of B in LDS, 64 at a time; each thread owns 8 of the r x r entries.
+__global__ __launch_bounds__(512) void g_part_kernel(int r, int z, const double* __restrict__ B,
+                                                     double* part)
+{
+    __shared__ double Bs[64][kMaxMeq + 1];
+    const int tid = threadIdx.x, p = blockIdx.x;
+    const int per = (z + kSplit - 1) / kSplit, k0 = p * per, k1 = min(z, k0 + per);
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+    for (int kb = k0; kb < k1; kb += 64) {
+        const int nb = min(64, k1 - kb);
+        __syncthreads();
+        for (int e = tid; e < nb * r; e += 512) {
+            const int kk = e / r, a = e - kk * r;
+            Bs[kk][a] = B[(size_t)(kb + kk) * r + a];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * 512;
+            if (e < r * r) {
+                const int a = e / r, b = e - a * r;
+                double g = acc[u];
+                for (int kk = 0; kk < nb; ++kk) g = fma(Bs[kk][a], Bs[kk][b], g);
+                acc[u] = g;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int e = tid + u * 512;
+        if (e < r * r) part[(size_t)p * r * r + e] = acc[u];
+    }
+}
+
+// G = (sum of the chunks in chunk order) / z; C = I + U^T W (block per row a,
+// thread per column b, sequential over the coordinates)
+__global__ void gc_reduce_kernel(int n, int r, int z, const double* __restrict__ part,
+                                 const double* __restrict__ U, const double* __restrict__ W,
+                                 double* G, double* C)
+{
+    const int a = blockIdx.x, b = threadIdx.x;
+    if (b >= r) return;
+    const int e = a * r + b;
     double g = 0.0;
-    for (int k = 0; k < z; ++k) g = fma(B[(size_t)k * r + p], B[(size_t)k * r + q], g);
+    for (int p = 0; p < kSplit; ++p) g += part[(size_t)p * r * r + e];
     G[e] = g / z;
-    double c = (p == q) ? 1.0 : 0.0;
-    for (int i = 0; i < n; ++i) c = fma(U[(size_t)i * r + p], W[(size_t)i * r + q], c);
+    double c = (a == b) ? 1.0 : 0.0;
+    for (int i = 0; i < n; ++i) c = fma(U[(size_t)i * r + a], W[(size_t)i * r + b], c);
     C[e] = c;
 }
 
-// Cholesky of C (r <= 64), log det C, C^{-1}, K = I + C^{-1} G; one workgroup
-__global__ void chol_kernel(int r, const double* C, const double* G, double* Cinv, double* K,
-                            double* logdet, int* status)
+// Cholesky of C (r <= 64), log det C, C^{-1}, K = I + C^{-1} G; one wave.
+// Right-looking factorisation with lane i owning row i; C^{-1} column q is
+// solved by lane q (forward then backward substitution) in LDS.
+__global__ __launch_bounds__(64) void chol_kernel(int r, const double* C, const double* G,
+                                                  double* Cinv, double* K, double* logdet,
+                                                  int* status)
 {
     __shared__ double L[kMaxMeq * kMaxMeq];
-    __shared__ int bad;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < r * r; e += nt) L[e] = C[e];
+    __shared__ double Y[kMaxMeq * kMaxMeq];
+    const int lane = threadIdx.x;
+    for (int e = lane; e < r * r; e += 64) L[e] = C[e];
     __syncthreads();
-    if (tid == 0) {
-        bad = 0;
-        double ld = 0.0;
-        for (int j = 0; j < r && !bad; ++j) {
-            double piv = L[j * r + j];
-            for (int k = 0; k < j; ++k) piv -= L[j * r + k] * L[j * r + k];
-            if (!(piv > 0.0)) {
-                bad = 1;
-                break;
-            }
-            const double ljj = sqrt(piv);
-            L[j * r + j] = ljj;
-            ld += 2.0 * log(ljj);
-            for (int i = j + 1; i < r; ++i) {
-                double v = L[i * r + j];
-                for (int k = 0; k < j; ++k) v -= L[i * r + k] * L[j * r + k];
-                L[i * r + j] = v / ljj;
-            }
+    int bad = 0;
+    double ld = 0.0;
+    for (int j = 0; j < r; ++j) {
+        const double piv = L[j * r + j];
+        if (!(piv > 0.0)) {
+            bad = 1;
+            break;
         }
+        const double ljj = sqrt(piv);
+        ld += 2.0 * log(ljj);
+        __syncthreads();
+        if (lane == j) L[j * r + j] = ljj;
+        if (lane > j && lane < r) L[lane * r + j] /= ljj;
+        __syncthreads();
+        if (lane > j && lane < r) {
+            const double lij = L[lane * r + j];
+            for (int k = j + 1; k <= lane; ++k) L[lane * r + k] -= lij * L[k * r + j];
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
         *logdet = ld;
         *status = bad;
     }
-    __syncthreads();
     if (bad) return;
-    // column q of C^{-1}: solve L L^T y = e_q
-    for (int q = tid; q < r; q += nt) {
-        double y[kMaxMeq];
+    if (lane < r) {
+        const int q = lane;
         for (int i = 0; i < r; ++i) {
             double v = (i == q) ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) v -= L[i * r + k] * y[k];
-            y[i] = v / L[i * r + i];
+            for (int k = 0; k < i; ++k) v -= L[i * r + k] * Y[k * r + q];
+            Y[i * r + q] = v / L[i * r + i];
         }
         for (int i = r - 1; i >= 0; --i) {
-            double v = y[i];
-            for (int k = i + 1; k < r; ++k) v -= L[k * r + i] * y[k];
-            y[i] = v / L[i * r + i];
+            double v = Y[i * r + q];
+            for (int k = i + 1; k < r; ++k) v -= L[k * r + i] * Y[k * r + q];
+            Y[i * r + q] = v / L[i * r + i];
         }
-        for (int i = 0; i < r; ++i) Cinv[i * r + q] = y[i];
     }
     __syncthreads();
-    for (int e = tid; e < r * r; e += nt) {
+    for (int e = lane; e < r * r; e += 64) Cinv[e] = Y[e];
+    for (int e = lane; e < r * r; e += 64) {
         const int p = e / r, q = e - p * r;
         double v = (p == q) ? 1.0 : 0.0;
-        for (int k = 0; k < r; ++k) v = fma(Cinv[p * r + k], G[k * r + q], v);
+        for (int k = 0; k < r; ++k) v = fma(Y[p * r + k], G[k * r + q], v);
         K[e] = v;
     }
 }
@@ -238,17 +338,33 @@ __global__ void grad_kernel(int n, int r, const double* __restrict__ W, const do
     }
 }
 
-// NLL = sum_i rowterm_i + log det C / 2 - tr(C^{-1} G) / 2 (fixed summation order)
-__global__ void nll_kernel(int n, int r, const double* rowterm, const double* Cinv,
-                           const double* G, const double* logdet, double* nll)
+// NLL = sum_i rowterm_i + log det C / 2 - tr(C^{-1} G) / 2: one block of 256,
+// contiguous partial sums per thread combined by a fixed-shape tree
+__global__ __launch_bounds__(256) void nll_kernel(int n, int r, const double* rowterm,
+                                                  const double* Cinv, const double* G,
+                                                  const double* logdet, double* nll)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double ps[256], pt[256];
+    const int tid = threadIdx.x;
+    const int per = (n + 255) / 256;
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += rowterm[i];
+    for (int i = tid * per; i < min(n, (tid + 1) * per); ++i) s += rowterm[i];
     double tr = 0.0;
-    for (int p = 0; p < r; ++p)
-        for (int q = 0; q < r; ++q) tr = fma(Cinv[p * r + q], G[q * r + p], tr);
-    *nll = s + 0.5 * (*logdet) - 0.5 * tr;
+    for (int e = tid; e < r * r; e += 256) {
+        const int p = e / r, q = e - p * r;
+        tr = fma(Cinv[p * r + q], G[q * r + p], tr);
+    }
+    ps[tid] = s;
+    pt[tid] = tr;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+            ps[tid] += ps[tid + h];
+            pt[tid] += pt[tid + h];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *nll = ps[0] + 0.5 * (*logdet) - 0.5 * pt[0];
 }
 
 // One Adam (Kingma & Ba) update in the scale-free coordinates (V, l), U = diag(exp(l)) V.
@@ -304,6 +420,7 @@ size_t precond_bytes(int n, int r, int z, int lda)
     b += 4 * al(rr * 8);              // G, C, Cinv, K
     b += al(64);                      // nll, logdet
     b += al(64);                      // status
+    b += al((size_t)kSplit * (nr > rr ? nr : rr) * 8);   // split-K partial sums
     return b;
 }
 
@@ -340,6 +457,7 @@ void precond_carve(PrecondBufs* p, void* ws)
     p->K = (double*)take(rr * 8);
     p->nll = (double*)take(64);
     p->status = (int*)take(64);
+    p->part = (double*)take((size_t)kSplit * (nr > rr ? nr : rr) * 8);
 }
 
 hipError_t launch_precond_init(const PrecondBufs& p, uint64_t seed, hipStream_t stream)
@@ -359,21 +477,24 @@ hipError_t launch_precond_set_scales(const PrecondBufs& p, hipStream_t stream)
 hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_t stream)
 {
     double* rowterm = p.rowterm;
-    hipLaunchKernelGGL(mean_sd_kernel, dim3(blocks_for(p.n, 64)), dim3(64), 0, stream, p.n, p.z,
+    hipLaunchKernelGGL(mean_sd_kernel, dim3((p.n + 63) / 64), dim3(512), 0, stream, p.n, p.z,
                        p.lda, X, p.mean, p.Sd);
     hipLaunchKernelGGL(w_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0, stream,
                        p.n, p.r, p.U, p.logsig, p.W);
-    hipLaunchKernelGGL(b_kernel, dim3(p.z), dim3(64), 0, stream, p.n, p.r, p.lda, X, p.mean, p.W,
-                       p.B);
-    hipLaunchKernelGGL(h_kernel, dim3(p.n), dim3(64), 0, stream, p.n, p.r, p.z, p.lda, X, p.mean,
-                       p.B, p.H);
-    hipLaunchKernelGGL(gc_kernel, dim3(blocks_for(p.r * p.r, 64)), dim3(64), 0, stream, p.n, p.r,
-                       p.z, p.B, p.U, p.W, p.GB, p.C);
+    hipLaunchKernelGGL(b_kernel, dim3((p.z + 7) / 8), dim3(512), 0, stream, p.n, p.r, p.z, p.lda,
+                       X, p.mean, p.W, p.B);
+    hipLaunchKernelGGL(h_part_kernel, dim3((p.n + 7) / 8, kSplit), dim3(512), 0, stream, p.n, p.r,
+                       p.z, p.lda, X, p.mean, p.B, p.part);
+    hipLaunchKernelGGL(h_reduce_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0,
+                       stream, p.n, p.r, p.z, p.part, p.H);
+    hipLaunchKernelGGL(g_part_kernel, dim3(kSplit), dim3(512), 0, stream, p.r, p.z, p.B, p.part);
+    hipLaunchKernelGGL(gc_reduce_kernel, dim3(p.r), dim3(64), 0, stream, p.n, p.r, p.z, p.part,
+                       p.U, p.W, p.GB, p.C);
     hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, stream, p.r, p.C, p.GB, p.Cinv, p.K,
                        p.nll + 1, p.status);
     hipLaunchKernelGGL(grad_kernel, dim3(p.n), dim3(64), 0, stream, p.n, p.r, p.W, p.H, p.K, p.Cinv,
                        p.GB, p.logsig, p.Sd, p.gU, p.gl, rowterm);
-    hipLaunchKernelGGL(nll_kernel, dim3(1), dim3(64), 0, stream, p.n, p.r, rowterm, p.Cinv, p.GB,
+    hipLaunchKernelGGL(nll_kernel, dim3(1), dim3(256), 0, stream, p.n, p.r, rowterm, p.Cinv, p.GB,
                        p.nll + 1, p.nll);
     return hipGetLastError();
 }
