@@ -287,8 +287,78 @@ def bench_rotbox(args):
     return line
 
 
+# The paper's Table 5 (Appendix B): MHAR on a P100 in FP64 at the best z it
+# found, hypercube [-1,1]^n (rows [I; -I]) and simplex {x >= 0, sum x = 1};
+# (figure, n, z, mean samples per second as printed).
+PAPER_TABLE5 = [
+    ("hypercube", 3, 10000, 25357073.87), ("hypercube", 5, 10000, 13206089.93),
+    ("hypercube", 15, 10000, 25344794.68), ("hypercube", 25, 5000, 10839474.35),
+    ("hypercube", 50, 2500, 5151516.81), ("hypercube", 100, 4000, 4363525.70),
+    ("hypercube", 250, 3000, 1219419.53), ("hypercube", 500, 4000, 621554.24),
+    ("hypercube", 1000, 4000, 248513.69), ("hypercube", 2500, 1500, 50808.74),
+    ("hypercube", 5000, 1000, 16161.69),
+    ("simplex", 3, 10000, 19795014.21), ("simplex", 5, 10000, 22878783.33),
+    ("simplex", 15, 10000, 24269548.32), ("simplex", 25, 10000, 24338761.06),
+    ("simplex", 50, 10000, 13425900.57), ("simplex", 100, 3000, 7255837.08),
+    ("simplex", 250, 4000, 2656449.22), ("simplex", 500, 1500, 944784.52),
+    ("simplex", 1000, 500, 329315.49), ("simplex", 2500, 500, 77312.01),
+    ("simplex", 5000, 1000, 22437.63),
+]
+
+
+def bench_table5(args):
+    """Every row of the paper's Table 5 on this GPU.  The samples are the FP64
+    chord in every screening precision (the chord is evaluated exactly), so
+    each precision reproduces the paper's 64-bit samples; FP64 screening runs
+    where n <= 1152."""
+    import math
+    import torch
+    from paper_2104_07097_amd import instances as inst
+    rows = []
+    budget = max(0.05, args.table5_seconds)
+    for fig, n, z, paper in PAPER_TABLE5:
+        p = inst.hypercube(n, z) if fig == "hypercube" else inst.simplex(n, z)
+        row = {"figure": fig, "n": n, "z": z, "paper_chain_steps_per_sec": paper}
+        best = None
+        for prec in ("fp64", "fp32", "bf16x3"):
+            if prec == "fp64" and n > 1152:
+                continue
+            prob, ch = _make(p, prec)
+            ch.step(20)
+            probe = _timed_steps(ch, 20)
+            steps = int(min(20000, max(20, budget / max(probe / 20, 1e-7))))
+            sec = _timed_steps(ch, steps)
+            st = ch.stats()
+            flags = ch.sync()
+            cs = z * steps / sec
+            row[prec] = {"chain_steps_per_sec": cs, "ms_per_step": sec * 1e3 / steps, "steps": steps,
+                         "path": KERNEL_PATHS.get(st["kernel"], "?"), "flags": flags}
+            if best is None or cs > row[best]["chain_steps_per_sec"]:
+                best = prec
+            ch.close()
+            prob.close()
+            torch.cuda.empty_cache()
+        row["best"] = best
+        row["speedup_vs_paper"] = row[best]["chain_steps_per_sec"] / paper
+        if "fp64" in row:
+            row["fp64_speedup_vs_paper"] = row["fp64"]["chain_steps_per_sec"] / paper
+        log(f"[bench] {fig} n={n} z={z}: best {best} "
+            f"{row[best]['chain_steps_per_sec'] / 1e6:.3f} M chain-steps/s "
+            f"({row['speedup_vs_paper']:.1f}x the paper's P100)")
+        rows.append(row)
+    geo = math.exp(sum(math.log(r["speedup_vs_paper"]) for r in rows) / len(rows))
+    line = {"metric": "chain-steps/sec on the paper's Table 5 workloads, MI355X vs the paper's P100",
+            "value": geo, "unit": "x (geometric mean over the rows)", "n_gpus": 1,
+            "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "paper Table 5: hypercube [-1,1]^n as [I;-I]x<=1 from the origin "
+                                   "and simplex {x>=0, sum x=1} from its centre, n=3..5000, the "
+                                   "paper's z per row; FP64 chord in every screening precision"},
+            "rows": rows}
+    return line
+
+
 OTHER_WORKLOADS = {"cube10": bench_cube10, "simplex_cut": bench_simplex_cut,
-                   "batched": bench_batched, "rotbox": bench_rotbox}
+                   "batched": bench_batched, "rotbox": bench_rotbox, "table5": bench_table5}
 
 
 def main():
@@ -302,11 +372,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
     ap.add_argument("--workload", default="randpoly",
-                    choices=["randpoly", "cube10", "simplex_cut", "batched", "rotbox"],
+                    choices=["randpoly", "cube10", "simplex_cut", "batched", "rotbox", "table5"],
                     help="randpoly (default) is the single-GPU configuration of the headline "
                          "metric; the others are the remaining configurations")
     ap.add_argument("--rank", type=int, default=64, help="rotbox: rank of the learned covariance")
     ap.add_argument("--burnin", type=int, default=500, help="rotbox: burn-in (training) steps")
+    ap.add_argument("--table5-seconds", type=float, default=0.25,
+                    help="table5: timed seconds per (row, precision)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()

@@ -135,7 +135,9 @@ mhar_status_t mhar_options_default(mhar_options_t* opt);
 /* ---------------------------------------------------------------------- */
 
 /* Device workspace bytes needed by mhar_problem_create for these sizes.
- * Supported: 1 <= n <= 1152, 1 <= m <= 2^24, 0 <= m_eq < n, m_eq <= 64. */
+ * Supported: 1 <= n <= 1152 (up to 8192 in FP32 / BF16X3 with path AUTO or
+ * TILED, which then runs the tiled path; batches take n <= 1152),
+ * 1 <= m <= 2^24, 0 <= m_eq < n, m_eq <= 64. */
 mhar_status_t mhar_problem_workspace_size(int64_t n, int64_t m, int64_t m_eq,
                                           const mhar_options_t* opt, size_t* bytes);
 

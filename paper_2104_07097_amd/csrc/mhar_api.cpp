@@ -131,10 +131,15 @@ mhar_status_t check_options(const mhar_options_t* opt, mhar_options_t* out)
     return MHAR_OK;
 }
 
-mhar_status_t check_dims(int64_t n, int64_t m, int64_t m_eq, ProblemDims* d)
+// n above kMaxN is served by the tiled path only (FP32 / BF16X3, path AUTO or TILED)
+mhar_status_t check_dims(int64_t n, int64_t m, int64_t m_eq, const mhar_options_t& o,
+                         ProblemDims* d)
 {
-    if (n < 1 || n > kMaxN)
-        return fail(MHAR_E_SHAPE, "n must be in [1, " + std::to_string(kMaxN) + "]");
+    const bool tiled_ok = o.precision != MHAR_FP64 &&
+                          (o.path == MHAR_PATH_AUTO || o.path == MHAR_PATH_TILED);
+    const int64_t nmax = tiled_ok ? kMaxNTiled : kMaxN;
+    if (n < 1 || n > nmax)
+        return fail(MHAR_E_SHAPE, "n must be in [1, " + std::to_string(nmax) + "] for this precision and path");
     if (m < 1 || m > (int64_t(1) << 24)) return fail(MHAR_E_SHAPE, "m must be in [1, 2^24]");
     if (m_eq < 0 || m_eq > kMaxMeq || m_eq >= n)
         return fail(MHAR_E_SHAPE, "m_eq must be in [0, min(64, n-1)]");
@@ -391,7 +396,7 @@ mhar_status_t mhar_problem_workspace_size(int64_t n, int64_t m, int64_t m_eq,
     mhar_status_t st = check_options(opt, &o);
     if (st) return st;
     ProblemDims d;
-    st = check_dims(n, m, m_eq, &d);
+    st = check_dims(n, m, m_eq, o, &d);
     if (st) return st;
     *bytes = carve_problem(d, o.precision, nullptr, nullptr);
     return MHAR_OK;
@@ -410,7 +415,7 @@ mhar_status_t mhar_problem_create(int64_t n, int64_t m, const double* A, const d
     mhar_status_t st = check_options(opt, &o);
     if (st) return st;
     ProblemDims d;
-    st = check_dims(n, m, m_eq, &d);
+    st = check_dims(n, m, m_eq, o, &d);
     if (st) return st;
     if (!workspace || !aligned256(workspace)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
     size_t need = carve_problem(d, o.precision, nullptr, nullptr);
@@ -523,7 +528,7 @@ mhar_status_t mhar_chains_create(mhar_problem_t p, int64_t z, const double* X0, 
         c->tiled = 1;
     } else if (p->path == MHAR_PATH_AUTO) {
         if (rs > 0) c->split = rs;
-        else c->tiled = use_tiled(p, z_pad);
+        else c->tiled = p->lda > kMaxN || use_tiled(p, z_pad);
     }
     hipError_t e = launch_fill_i32((int*)c->theta, (int64_t)z_pad * 2, 0, stream);
     if (e == hipSuccess) e = launch_fill_i32((int*)c->E, (int64_t)z_pad * 2, 0, stream);
@@ -757,6 +762,8 @@ static mhar_status_t batch_units(int32_t count, const mhar_chains_t* chains, int
     int total = 0;
     for (int i = 0; i < count; ++i) {
         if (!chains[i]) return fail(MHAR_E_INVALID_ARG, "NULL chains handle in the batch");
+        if (chains[i]->p->lda > kMaxN)
+            return fail(MHAR_E_UNSUPPORTED, "batched launches take problems with n <= " + std::to_string(kMaxN));
         if (i > 0 && chains[i]->p->prec != chains[0]->p->prec)
             return fail(MHAR_E_INVALID_ARG, "all problems of a batch must share one precision");
         for (int j = 0; j < i; ++j)

@@ -14,6 +14,7 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kRowGroup = 64;    // rows one wave handles per pass (4 MFMA row blocks)
 constexpr int kKAlign = 32;      // padded row length (K) granularity
 constexpr int kMaxN = 1152;      // LDS holds 16 padded FP64 rows of length <= kMaxN
+constexpr int kMaxNTiled = 8192; // the tiled path keeps no row of length n in LDS
 constexpr int kMaxMeq = 64;
 
 enum Prec { kFP64 = 0, kFP32 = 1, kBF16X3 = 2 };

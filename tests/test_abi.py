@@ -38,7 +38,7 @@ def test_options_and_strings():
 
 
 @pytest.mark.parametrize("n,m,m_eq,code", [(0, 10, 0, mhar.E_SHAPE), (5, 0, 0, mhar.E_SHAPE),
-                                           (2000, 10, 0, mhar.E_SHAPE), (5, 10, 5, mhar.E_SHAPE),
+                                           (9000, 10, 0, mhar.E_SHAPE), (5, 10, 5, mhar.E_SHAPE),
                                            (100, 10, 65, mhar.E_SHAPE)])
 def test_workspace_size_rejects_bad_shapes(n, m, m_eq, code):
     lib = mhar.load()
@@ -82,3 +82,15 @@ def test_path_option_checked(prec, path, code):
     o = mhar.options(prec, path=path)
     sz = ctypes.c_size_t()
     assert lib.mhar_problem_workspace_size(50, 100, 0, ctypes.byref(o), ctypes.byref(sz)) == code
+
+
+@pytest.mark.parametrize("n,prec,path,code", [(2000, "bf16x3", "auto", mhar.OK), (8192, "fp32", "tiled", mhar.OK),
+                                              (2000, "fp64", "auto", mhar.E_SHAPE),
+                                              (2000, "fp32", "general", mhar.E_SHAPE),
+                                              (2000, "fp32", "resident", mhar.E_SHAPE),
+                                              (8193, "bf16x3", "tiled", mhar.E_SHAPE)])
+def test_large_n_only_on_the_tiled_path(n, prec, path, code):
+    lib = mhar.load()
+    o = mhar.options(prec, path=path)
+    sz = ctypes.c_size_t()
+    assert lib.mhar_problem_workspace_size(n, 3 * n, 1, ctypes.byref(o), ctypes.byref(sz)) == code

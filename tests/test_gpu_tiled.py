@@ -145,3 +145,28 @@ def test_tiled_full_size_sampled_parity(orc):
         err = gu.rel_err(got[k:k + 1], want)
         assert err <= 1e-11, (k, err)
     assert gu.feasible(p, got)
+
+
+@pytest.mark.parametrize("fig", ["simplex", "hypercube"])
+def test_tiled_large_n_parity(orc, fig):
+    """n = 1500 (beyond the single-kernel paths' 1152): the tiled path is chosen
+    automatically; one step from a mid-run state against the oracle on every
+    walk, and 12 steps from the start."""
+    n, z = 1500, 24
+    p = inst.simplex(n, z) if fig == "simplex" else inst.hypercube(n, z)
+    P = gu.oracle_projection(orc, p)
+    gu.announce("tiled large n", fig)
+    _, ch = gu.make(p, "bf16x3", recompute_every=5)
+    assert ch.stats()["kernel"] == 3
+    ch.step(12)
+    got12, st = gu.state(ch)
+    want12, _, _ = orc.run(p.A, p.b, p.X0, 12, seed=0, P=P)
+    assert not st.any()
+    assert gu.rel_err(got12, want12) <= 1e-9
+    ch.set_state(torch.tensor(want12, device=gu.device()), 12)
+    ch.step(1)
+    got, st = gu.state(ch)
+    want, _, _ = orc.run(p.A, p.b, want12, 1, seed=0, P=P, step0=12)
+    assert not st.any()
+    assert gu.rel_err(got, want) <= 1e-11
+    assert gu.feasible(p, got)
