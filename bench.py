@@ -357,8 +357,66 @@ def bench_table5(args):
     return line
 
 
+def fr_run(fig, n, seed, samples_per_walk=5, z=1000, precision="fp32"):
+    """The paper's convergence check for one simulation: z walks from the
+    centre, phi = (n-1)^3 (simplex) or n^3 (hypercube) burn-in steps, then
+    samples_per_walk states per walk phi steps apart, compared with as many
+    exact uniform points by the Friedman-Rafsky test.  Returns (z-value, steps,
+    seconds)."""
+    import numpy as np
+    import torch
+    from paper_2104_07097_amd import instances as inst
+    from paper_2104_07097_amd import mhar
+    from paper_2104_07097_amd.stats import friedman_rafsky
+    p = inst.hypercube(n, z) if fig == "hypercube" else inst.simplex(n, z)
+    phi = n ** 3 if fig == "hypercube" else (n - 1) ** 3
+    dev = torch.device("cuda:0")
+    t = lambda a: None if a is None else torch.tensor(a, device=dev, dtype=torch.float64)
+    prob = mhar.Problem(t(p.A), t(p.b), t(p.A_eq), t(p.b_eq), precision=precision)
+    ch = mhar.Chains(prob, t(p.X0), seed=seed)
+    t0 = time.perf_counter()
+    ch.step(phi)
+    rec = ch.record(samples_per_walk * phi, phi, z)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    S = rec.cpu().numpy().reshape(-1, n)
+    flags = ch.sync()
+    ch.close()
+    prob.close()
+    rng = np.random.default_rng(10_000 + seed)
+    U = inst.exact_cube(rng, len(S), n) if fig == "hypercube" else inst.exact_simplex(rng, len(S), n)
+    _, zval = friedman_rafsky(S, U)
+    return zval, (samples_per_walk + 1) * phi, sec, flags
+
+
+def bench_fr(args):
+    """The paper's Friedman-Rafsky check (its S6 independence test): simplex and
+    hypercube, n = 5, 15, 25, 50, z = 1000, args.fr_sims simulations each."""
+    rows = []
+    for fig in ("simplex", "hypercube"):
+        for n in (5, 15, 25, 50):
+            zs = []
+            for k in range(args.fr_sims):
+                zval, steps, sec, flags = fr_run(fig, n, seed=k)
+                zs.append(zval)
+                log(f"[bench] FR {fig} n={n} sim {k}: z={zval:+.2f} ({steps} steps, {sec:.1f} s, flags {flags})")
+            rows.append({"figure": fig, "n": n, "z_values": zs,
+                         "accepted": sum(v >= -1.64 for v in zs), "simulations": len(zs)})
+    acc = sum(r["accepted"] for r in rows)
+    tot = sum(r["simulations"] for r in rows)
+    return {"metric": "Friedman-Rafsky z >= -1.64 (the paper's acceptance threshold)",
+            "value": acc / tot, "unit": "fraction of simulations accepted", "n_gpus": 1,
+            "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": "simplex and hypercube, n in {5,15,25,50}, z=1000 walks from the "
+                                   "centre, burn-in and thinning phi=(n-1)^3 (simplex) or n^3 "
+                                   "(hypercube), 5000 samples vs 5000 exact uniform points, FP32 "
+                                   "screening (exact FP64 chord)"},
+            "rows": rows}
+
+
 OTHER_WORKLOADS = {"cube10": bench_cube10, "simplex_cut": bench_simplex_cut,
-                   "batched": bench_batched, "rotbox": bench_rotbox, "table5": bench_table5}
+                   "batched": bench_batched, "rotbox": bench_rotbox, "table5": bench_table5,
+                   "fr": bench_fr}
 
 
 def main():
@@ -372,11 +430,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
     ap.add_argument("--workload", default="randpoly",
-                    choices=["randpoly", "cube10", "simplex_cut", "batched", "rotbox", "table5"],
+                    choices=["randpoly", "cube10", "simplex_cut", "batched", "rotbox", "table5", "fr"],
                     help="randpoly (default) is the single-GPU configuration of the headline "
                          "metric; the others are the remaining configurations")
     ap.add_argument("--rank", type=int, default=64, help="rotbox: rank of the learned covariance")
     ap.add_argument("--burnin", type=int, default=500, help="rotbox: burn-in (training) steps")
+    ap.add_argument("--fr-sims", type=int, default=3, help="fr: simulations per (figure, n)")
     ap.add_argument("--table5-seconds", type=float, default=0.25,
                     help="table5: timed seconds per (row, precision)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,

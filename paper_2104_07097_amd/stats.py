@@ -1,5 +1,5 @@
-"""Host-side statistics for judging samplers: effective sample size and
-Kolmogorov-Smirnov distances.
+"""Host-side statistics for judging samplers: effective sample size,
+Kolmogorov-Smirnov distances and the Friedman-Rafsky two-sample test.
 
 The ESS estimator follows the multi-chain recipe of Gelman et al.,
 *Bayesian Data Analysis* (3rd ed., S11.5) as used by Stan: split each chain
@@ -89,3 +89,49 @@ def ks_two_sample(a: np.ndarray, b: np.ndarray) -> float:
     fa = np.searchsorted(a, grid, side="right") / a.size
     fb = np.searchsorted(b, grid, side="right") / b.size
     return float(np.abs(fa - fb).max())
+
+
+def friedman_rafsky(x: np.ndarray, y: np.ndarray) -> tuple[int, float]:
+    """Friedman-Rafsky multivariate two-sample test (Friedman & Rafsky, Ann.
+    Statist. 7(4), 1979), the convergence check the paper applies to MHAR.
+
+    Pool the samples (rows of x and y), build the Euclidean minimum spanning
+    tree, and count runs R = (edges joining a point of x to a point of y) + 1.
+    Under the null hypothesis of equal laws
+      E[R]   = 2 m n / N + 1,
+      Var[R] = 2 m n / (N (N - 1)) * [ (2 m n - N) / N
+               + (C - N + 2) / ((N - 2)(N - 3)) * (N (N - 1) - 4 m n + 2) ],
+    with m, n the sample sizes, N = m + n and C the number of pairs of tree
+    edges that share a node.  Returns (R, z = (R - E[R]) / sd[R]); few runs
+    (z very negative) mean the samples come from different laws."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    m, n = len(x), len(y)
+    N = m + n
+    pts = np.vstack([x, y])
+    # Prim's algorithm on squared Euclidean distances (same tree), one row of
+    # distances at a time: O(N^2 dim) work, O(N) memory
+    sq = np.einsum("ij,ij->i", pts, pts)
+    in_tree = np.zeros(N, dtype=bool)
+    best = np.full(N, np.inf)
+    parent = np.full(N, -1, dtype=np.int64)
+    best[0] = 0.0
+    for _ in range(N):
+        u = int(np.argmin(np.where(in_tree, np.inf, best)))
+        in_tree[u] = True
+        d = sq - 2.0 * (pts @ pts[u]) + sq[u]
+        upd = (~in_tree) & (d < best)
+        best[upd] = d[upd]
+        parent[upd] = u
+    child = np.nonzero(parent >= 0)[0]
+    rows, cols = parent[child], child
+    label = np.concatenate([np.zeros(m, dtype=bool), np.ones(n, dtype=bool)])
+    cross = int(np.sum(label[rows] != label[cols]))
+    R = cross + 1
+    deg = np.bincount(np.concatenate([rows, cols]), minlength=N)
+    C = float(np.sum(deg * (deg - 1) / 2.0))
+    mn = float(m) * float(n)
+    mean = 2.0 * mn / N + 1.0
+    var = (2.0 * mn / (N * (N - 1.0))) * ((2.0 * mn - N) / N + (C - N + 2.0) / ((N - 2.0) * (N - 3.0))
+                                          * (N * (N - 1.0) - 4.0 * mn + 2.0))
+    return R, float((R - mean) / np.sqrt(var))

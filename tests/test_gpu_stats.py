@@ -63,3 +63,18 @@ def test_cube_stationary_from_exact_start():
     assert not st.any() and gu.feasible(p, X)
     for j in range(n):
         assert stats.kstest(X[:, j], stats.uniform(-1, 2).cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("fig,n", [("simplex", 5), ("hypercube", 5), ("simplex", 15), ("hypercube", 15)])
+def test_friedman_rafsky_paper_protocol(fig, n):
+    """The paper's independence check (S6) at its settings for n = 5 and 15:
+    z = 1000 walks from the centre, burn-in phi = (n-1)^3 or n^3 steps, then 5
+    samples per walk phi steps apart against 5000 exact uniform points.  The
+    paper accepts at z >= -1.64 (5 % one-sided); the gate here is 0.1 % so
+    that it fails only for a real difference of laws."""
+    import bench
+    gu.announce("friedman-rafsky", fig, n)
+    zval, steps, sec, flags = bench.fr_run(fig, n, seed=1)
+    print(f"  FR z = {zval:+.2f} after {steps} steps", flush=True)
+    assert flags == 0
+    assert zval > -3.09

@@ -1,7 +1,9 @@
-"""Pins for the host-side ESS estimator (closed forms)."""
+"""Pins for the host-side statistics: the ESS estimator against closed forms,
+the Friedman-Rafsky statistic against its null distribution (simulation) and
+against clearly different laws."""
 import numpy as np
 
-from paper_2104_07097_amd.stats import ess, ks_distance, ks_two_sample
+from paper_2104_07097_amd.stats import ess, friedman_rafsky, ks_distance, ks_two_sample
 
 
 def test_ess_iid():
@@ -30,3 +32,29 @@ def test_ks_helpers():
     assert ks_distance(u, lambda v: v) < 0.03
     assert ks_distance(u, lambda v: v**2) > 0.2
     assert ks_two_sample(u, rng.uniform(size=5000)) < 0.04
+
+
+def test_friedman_rafsky_null_is_standard_normal():
+    # equal laws: z over 200 independent replicates has mean ~0 and sd ~1
+    rng = np.random.default_rng(5)
+    zs = [friedman_rafsky(rng.uniform(-1, 1, (60, 3)), rng.uniform(-1, 1, (80, 3)))[1]
+          for _ in range(200)]
+    assert abs(np.mean(zs)) < 0.25
+    assert 0.75 < np.std(zs) < 1.25
+
+
+def test_friedman_rafsky_detects_different_laws():
+    rng = np.random.default_rng(6)
+    x = rng.uniform(-1, 1, (300, 5))
+    shifted = rng.uniform(-1, 1, (300, 5)) + np.array([0.8, 0, 0, 0, 0])
+    squeezed = rng.uniform(-0.7, 0.7, (300, 5))
+    assert friedman_rafsky(x, shifted)[1] < -4.0
+    assert friedman_rafsky(x, squeezed)[1] < -4.0
+
+
+def test_friedman_rafsky_runs_by_hand():
+    # 1-D points: the MST is the sorted chain, so R - 1 counts label changes
+    x = np.array([[0.0], [1.0], [2.0]])
+    y = np.array([[0.5], [5.0]])
+    R, _ = friedman_rafsky(x, y)
+    assert R == 1 + 3   # order 0(x) .5(y) 1(x) 2(x) 5(y): changes x-y, y-x, x-y
