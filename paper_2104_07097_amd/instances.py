@@ -141,11 +141,12 @@ def batched(count: int = 256, z_each: int = 256, n_lo: int = 20, n_hi: int = 400
 
 
 def triangle(z: int, seed: int = 7) -> Polytope:
-    """2-D triangle with vertices (0,0), (2,0), (0.5,1); z chains at its centroid."""
+    """2-D triangle y >= 0, x + 1.5 y <= 2, -2 x + 0.5 y <= 0 (vertices (0,0),
+    (2,0), (2/7, 8/7)); z chains at the interior point (5/6, 1/3)."""
     A = np.array([[0.0, -1.0], [1.0, 1.5], [-2.0, 0.5]])
     b = np.array([0.0, 2.0, 0.0])
-    centroid = np.array([2.5 / 3.0, 1.0 / 3.0])
-    return Polytope("triangle", A, b, np.tile(centroid, (z, 1)))
+    start = np.array([2.5 / 3.0, 1.0 / 3.0])
+    return Polytope("triangle", A, b, np.tile(start, (z, 1)))
 
 
 # --------------------------------------------------------------------------
