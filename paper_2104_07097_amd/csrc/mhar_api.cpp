@@ -59,15 +59,21 @@ struct mhar_batch {
     int count;
     int prec;
     std::vector<mhar_chains*> chains;
-    std::vector<int> saved_split;
+    std::vector<int> saved_split, saved_tiled;
     StepArgs* descs_dev;
     int2* units_dev;
     unsigned* next_dev;
     StepArgs* descs_host;   // pinned
     hipEvent_t copied;
     bool copy_pending;
-    int nunits, max_lda, grid;
+    int nunits, max_lda, grid;      // general-kernel units (small problems)
     double work_per_step;
+    // large problems: grouped tiled launches over a table of tiles
+    int ntu, nst, nrt;              // chords units, screening tiles, recompute tiles
+    int2* tunits_dev;
+    int4* stiles_dev;
+    int4* rtiles_dev;
+    std::vector<unsigned char> due; // per step of a launch: some problem recomputes after it
 };
 
 namespace {
@@ -742,46 +748,92 @@ mhar_status_t mhar_precond_destroy(mhar_chains_t c)
     return MHAR_OK;
 }
 
-static size_t carve_batch(int count, int nunits, void* ws, mhar_batch* b)
+// Work items of a batch.  Problems that run the tiled path on their own are
+// stepped by grouped tiled launches (one table entry per screening tile,
+// 16-walk chords unit and recompute tile); the others by the persistent
+// general kernel over (problem, 16-walk tile) units in decreasing order of
+// cost (longest processing time first).
+struct BatchPlan {
+    int prec = 0;
+    int max_lda = 0;
+    double work = 0.0;
+    std::vector<int2> gen_units, tiled_units;
+    std::vector<int4> stiles, rtiles;
+};
+
+// Path of a handle inside a batch: the register-resident kernel cannot be
+// batched, so a resident handle runs tiled if its shape qualifies for the
+// tiled path, else the general kernel.
+static bool tiled_in_batch(const mhar_chains* c)
+{
+    return c->tiled || (c->split > 0 && use_tiled(c->p, c->z_pad));
+}
+
+static mhar_status_t plan_batch(int32_t count, const mhar_chains_t* chains, BatchPlan* pl)
+{
+    if (count < 1 || !chains) return fail(MHAR_E_INVALID_ARG, "need count >= 1 and a chains array");
+    std::vector<std::pair<double, int2>> order;
+    for (int i = 0; i < count; ++i) {
+        const mhar_chains* c = chains[i];
+        if (!c) return fail(MHAR_E_INVALID_ARG, "NULL chains handle in the batch");
+        if (i > 0 && c->p->prec != chains[0]->p->prec)
+            return fail(MHAR_E_INVALID_ARG, "all problems of a batch must share one precision");
+        for (int j = 0; j < i; ++j)
+            if (chains[j] == c) return fail(MHAR_E_INVALID_ARG, "a chains handle appears twice");
+        const mhar_problem* p = c->p;
+        const double cost = (double)p->m_pad * p->lda;
+        pl->work += cost * c->z_pad;
+        if (tiled_in_batch(c)) {
+            for (int t = 0; t < c->z_pad / kChainTile; ++t) pl->tiled_units.push_back(int2{i, t});
+            const int nrb = (p->m_pad + kScreenRows - 1) / kScreenRows;
+            const int ncb = (c->z_pad + kScreenWalks - 1) / kScreenWalks;
+            for (int rb = 0; rb < nrb; ++rb)
+                for (int cb = 0; cb < ncb; ++cb) pl->stiles.push_back(int4{i, rb, cb, 0});
+            const int rrb = (p->m_pad + kRecRows - 1) / kRecRows;
+            const int rcb = (c->z_pad + kRecWalks - 1) / kRecWalks;
+            for (int rb = 0; rb < rrb; ++rb)
+                for (int cb = 0; cb < rcb; ++cb) pl->rtiles.push_back(int4{i, rb, cb, 0});
+        } else {
+            if (p->lda > kMaxN)
+                return fail(MHAR_E_UNSUPPORTED, "a problem with n > " + std::to_string(kMaxN) + " must run tiled");
+            pl->max_lda = std::max(pl->max_lda, p->lda);
+            for (int t = 0; t < c->z_pad / kChainTile; ++t) order.push_back({cost, int2{i, t}});
+        }
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) { return x.first > y.first; });
+    for (const auto& o : order) pl->gen_units.push_back(o.second);
+    pl->prec = chains[0]->p->prec;
+    return MHAR_OK;
+}
+
+static size_t carve_batch(int count, const BatchPlan& pl, void* ws, mhar_batch* b)
 {
     Carver c(ws);
     StepArgs* d = c.take<StepArgs>(count);
-    int2* u = c.take<int2>(nunits);
+    int2* u = c.take<int2>(std::max<size_t>(pl.gen_units.size(), 1));
+    int2* tu = c.take<int2>(std::max<size_t>(pl.tiled_units.size(), 1));
+    int4* st = c.take<int4>(std::max<size_t>(pl.stiles.size(), 1));
+    int4* rt = c.take<int4>(std::max<size_t>(pl.rtiles.size(), 1));
     unsigned* nx = c.take<unsigned>(64);
     if (b) {
         b->descs_dev = d;
         b->units_dev = u;
+        b->tunits_dev = tu;
+        b->stiles_dev = st;
+        b->rtiles_dev = rt;
         b->next_dev = nx;
     }
     return c.used;
 }
 
-static mhar_status_t batch_units(int32_t count, const mhar_chains_t* chains, int* nunits, int* prec)
-{
-    if (count < 1 || !chains) return fail(MHAR_E_INVALID_ARG, "need count >= 1 and a chains array");
-    int total = 0;
-    for (int i = 0; i < count; ++i) {
-        if (!chains[i]) return fail(MHAR_E_INVALID_ARG, "NULL chains handle in the batch");
-        if (chains[i]->p->lda > kMaxN)
-            return fail(MHAR_E_UNSUPPORTED, "batched launches take problems with n <= " + std::to_string(kMaxN));
-        if (i > 0 && chains[i]->p->prec != chains[0]->p->prec)
-            return fail(MHAR_E_INVALID_ARG, "all problems of a batch must share one precision");
-        for (int j = 0; j < i; ++j)
-            if (chains[j] == chains[i]) return fail(MHAR_E_INVALID_ARG, "a chains handle appears twice");
-        total += chains[i]->z_pad / kChainTile;
-    }
-    *nunits = total;
-    *prec = chains[0]->p->prec;
-    return MHAR_OK;
-}
-
 mhar_status_t mhar_batch_workspace_size(int32_t count, const mhar_chains_t* chains, size_t* bytes)
 {
     if (!bytes) return fail(MHAR_E_INVALID_ARG, "bytes is NULL");
-    int nunits = 0, prec = 0;
-    mhar_status_t st = batch_units(count, chains, &nunits, &prec);
+    BatchPlan pl;
+    mhar_status_t st = plan_batch(count, chains, &pl);
     if (st) return st;
-    *bytes = carve_batch(count, nunits, nullptr, nullptr);
+    *bytes = carve_batch(count, pl, nullptr, nullptr);
     return MHAR_OK;
 }
 
@@ -790,33 +842,26 @@ mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void
 {
     if (!out) return fail(MHAR_E_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    int nunits = 0, prec = 0;
-    mhar_status_t st = batch_units(count, chains, &nunits, &prec);
+    BatchPlan pl;
+    mhar_status_t st = plan_batch(count, chains, &pl);
     if (st) return st;
     if (!ws || !aligned256(ws)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < carve_batch(count, nunits, nullptr, nullptr)) return fail(MHAR_E_WORKSPACE, "batch workspace too small");
+    if (ws_bytes < carve_batch(count, pl, nullptr, nullptr)) return fail(MHAR_E_WORKSPACE, "batch workspace too small");
     mhar_batch* b = new mhar_batch{};
     b->count = count;
-    b->prec = prec;
-    b->nunits = nunits;
-    carve_batch(count, nunits, ws, b);
-    b->max_lda = 0;
-    b->work_per_step = 0.0;
-    // units in decreasing order of cost (longest processing time first)
-    std::vector<std::pair<double, int2>> order;
+    b->prec = pl.prec;
+    b->nunits = (int)pl.gen_units.size();
+    b->ntu = (int)pl.tiled_units.size();
+    b->nst = (int)pl.stiles.size();
+    b->nrt = (int)pl.rtiles.size();
+    b->max_lda = pl.max_lda;
+    b->work_per_step = pl.work;
+    carve_batch(count, pl, ws, b);
     for (int i = 0; i < count; ++i) {
-        mhar_chains* c = chains[i];
-        b->chains.push_back(c);
-        b->saved_split.push_back(c->split);
-        b->max_lda = std::max(b->max_lda, c->p->lda);
-        const double cost = (double)c->p->m_pad * c->p->lda;
-        for (int t = 0; t < c->z_pad / kChainTile; ++t) order.push_back({cost, int2{i, t}});
-        b->work_per_step += cost * c->z_pad;
+        b->chains.push_back(chains[i]);
+        b->saved_split.push_back(chains[i]->split);
+        b->saved_tiled.push_back(chains[i]->tiled);
     }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) { return x.first > y.first; });
-    std::vector<int2> units(nunits);
-    for (int u = 0; u < nunits; ++u) units[u] = order[u].second;
     auto cleanup = [&](mhar_status_t code) {
         if (b->descs_host) hipHostFree(b->descs_host);
         delete b;
@@ -824,17 +869,24 @@ mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void
     };
     hipError_t e = hipHostMalloc((void**)&b->descs_host, sizeof(StepArgs) * count, hipHostMallocDefault);
     if (e != hipSuccess) return cleanup(hip_fail(e, "pinned descriptor buffer"));
-    e = hipMemcpy(b->units_dev, units.data(), sizeof(int2) * nunits, hipMemcpyHostToDevice);
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    up(b->units_dev, pl.gen_units.data(), sizeof(int2) * pl.gen_units.size());
+    up(b->tunits_dev, pl.tiled_units.data(), sizeof(int2) * pl.tiled_units.size());
+    up(b->stiles_dev, pl.stiles.data(), sizeof(int4) * pl.stiles.size());
+    up(b->rtiles_dev, pl.rtiles.data(), sizeof(int4) * pl.rtiles.size());
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->copied, hipEventDisableTiming);
     if (e != hipSuccess) return cleanup(hip_fail(e, "batch setup"));
     int dev = 0, cus = 1;
     e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return cleanup(hip_fail(e, "device query"));
-    b->grid = std::min(nunits, cus * batch_blocks_per_cu(prec, b->max_lda));
-    // the batched launch runs the general kernel: resident handles switch over
+    b->grid = b->nunits ? std::min(b->nunits, cus * batch_blocks_per_cu(b->prec, b->max_lda)) : 0;
+    // resident handles switch to the tiled path or the general kernel
     for (mhar_chains* c : b->chains) {
         if (c->split > 0) {
+            c->tiled = tiled_in_batch(c) ? 1 : 0;
             c->split = 0;
             c->force_recompute = 1;
         }
@@ -874,9 +926,25 @@ mhar_status_t mhar_batch_step(mhar_batch_t b, int64_t steps, void* stream_)
                                 hipMemcpyHostToDevice, stream), "descriptor copy");
         MHAR_HIP(hipEventRecord(b->copied, stream), "descriptor copy event");
         b->copy_pending = true;
-        MHAR_HIP(launch_fill_i32((int*)b->next_dev, 1, 0, stream), "queue reset");
-        MHAR_HIP(launch_batch(b->prec, b->descs_dev, b->units_dev, b->nunits, b->next_dev, b->max_lda,
-                              b->grid, stream), "batched launch");
+        if (b->nunits > 0) {
+            MHAR_HIP(launch_fill_i32((int*)b->next_dev, 1, 0, stream), "queue reset");
+            MHAR_HIP(launch_batch(b->prec, b->descs_dev, b->units_dev, b->nunits, b->next_dev,
+                                  b->max_lda, b->grid, stream), "batched launch");
+        }
+        if (b->ntu > 0) {
+            // which steps of this launch some tiled problem recomputes after
+            int first = 0;
+            b->due.assign((size_t)k, 0);
+            for (int i = 0; i < b->count; ++i) {
+                if (!b->chains[i]->tiled) continue;   // general-kernel part
+                const StepArgs& a = b->descs_host[i];
+                first |= a.recompute_first;
+                for (int64_t s = (a.R - 1 - a.since0); s < k; s += a.R) b->due[(size_t)s] = 1;
+            }
+            MHAR_HIP(launch_grouped(b->prec, b->descs_dev, b->stiles_dev, b->nst, b->tunits_dev,
+                                    b->ntu, b->rtiles_dev, b->nrt, (int)k, first, b->due.data(),
+                                    stream), "grouped tiled launch");
+        }
         for (mhar_chains* c : b->chains) advance_schedule(c, k);
         done += k;
     }
@@ -891,6 +959,7 @@ mhar_status_t mhar_batch_destroy(mhar_batch_t b)
         mhar_chains* c = b->chains[i];
         if (b->saved_split[i] > 0 && c->pc_rank == 0) {
             c->split = b->saved_split[i];
+            c->tiled = b->saved_tiled[i];
             c->force_recompute = 1;
         }
     }

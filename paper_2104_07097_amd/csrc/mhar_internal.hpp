@@ -15,6 +15,10 @@ constexpr int kRowGroup = 64;    // rows one wave handles per pass (4 MFMA row b
 constexpr int kKAlign = 32;      // padded row length (K) granularity
 constexpr int kMaxN = 1152;      // LDS holds 16 padded FP64 rows of length <= kMaxN
 constexpr int kMaxNTiled = 8192; // the tiled path keeps no row of length n in LDS
+constexpr int kScreenRows = 256; // tiled path: rows x walks of a screening tile
+constexpr int kScreenWalks = 128;
+constexpr int kRecRows = 256;    // tiled path: rows x walks of a recompute tile
+constexpr int kRecWalks = 64;
 constexpr int kMaxMeq = 64;
 
 enum Prec { kFP64 = 0, kFP32 = 1, kBF16X3 = 2 };
@@ -102,6 +106,13 @@ hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream);
 // tiled path for large problems (FP32 / BF16X3): per step a screening GEMM and
 // a chords + directions kernel, and an FP64 recompute GEMM every R steps
 hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream);
+// the tiled path over many problems at once: per step one grouped screening
+// launch over the tile table, one grouped chords launch over the 16-walk
+// units and, after the steps flagged in `due` (host array of `steps`), one
+// grouped recompute launch (each tile checks its own problem's schedule)
+hipError_t launch_grouped(int prec, const StepArgs* descs, const int4* stiles, int nst,
+                          const int2* units, int nunits, const int4* rtiles, int nrt, int steps,
+                          int first, const unsigned char* due, hipStream_t stream);
 
 // one-time setup
 hipError_t launch_convert_problem(int prec, int n, int m, int m_pad, int lda, const double* A,

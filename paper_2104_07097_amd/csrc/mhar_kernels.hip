@@ -853,8 +853,8 @@ __global__ __launch_bounds__(kThreads) void mhar_batch_kernel(const StepArgs* __
 // LDS the chords kernel lends to the exact evaluation: 96 candidates and the
 // x and d rows of 16 walks, 64 coordinates at a time
 constexpr int kChordStageBytes = (96 + 2 * kChainTile) * (64 + 2) * 8;
-constexpr int kTR = 256;   // rows per screening tile
-constexpr int kTW = 128;   // walks per screening tile
+constexpr int kTR = kScreenRows;   // rows per screening tile
+constexpr int kTW = kScreenWalks;  // walks per screening tile
 constexpr int kTK = 32;    // K per LDS stage
 
 template <int P> struct TileFmt;
@@ -884,8 +884,22 @@ __device__ __forceinline__ int xcd_tile(int bid, int total)
     return (bid & 7) * per + (bid >> 3);
 }
 
+// Slack schedule of step s of a launch (s = 0 is the launch's first step):
+// every step sets pending = 1, T += 1, since += 1, and an exact recompute
+// after a step where since reaches R resets pending = 0, T = 2, since = 0.
+__device__ __forceinline__ void sched_at(const StepArgs& a, int s, int& pending, int& T,
+                                         bool& recompute_after)
+{
+    const int since = (a.since0 + s) % a.R;
+    pending = (s == 0) ? a.pending0 : (since != 0);
+    T = (a.since0 + s < a.R) ? a.T0 + s : 2 + since;
+    recompute_after = since + 1 == a.R;
+}
+
+// One (256-row block rb, 128-walk block cb) tile of the screening GEMM and its epilogue.
 template <int P>
-__global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int pending, int T)
+__device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int T,
+                            unsigned char* smem)
 {
     typedef TileFmt<P> F;
     constexpr int kChunkRow = kTK / F::per16;              // 16-byte chunks per row and plane
@@ -893,12 +907,6 @@ __global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int 
     constexpr int kChunks = F::planes * (kTR + kTW) * kChunkRow;
     constexpr int kPer = kChunks / kThreads;               // 6
     static_assert(kChunks % kThreads == 0, "chunk split");
-    extern __shared__ __align__(16) unsigned char smem[];
-
-    const int nrb = (a.m_pad + kTR - 1) / kTR, ncb = (a.z_pad + kTW - 1) / kTW;
-    const int t = xcd_tile(blockIdx.x, nrb * ncb);
-    if (t >= nrb * ncb) return;
-    const int rb = t / ncb, cb = t - rb * ncb;
     const int R0 = rb * kTR, C0 = cb * kTW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
@@ -1118,18 +1126,43 @@ __global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int 
     }
 }
 
+template <int P>
+__global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int pending, int T)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nrb = (a.m_pad + kTR - 1) / kTR, ncb = (a.z_pad + kTW - 1) / kTW;
+    const int t = xcd_tile(blockIdx.x, nrb * ncb);
+    if (t >= nrb * ncb) return;
+    screen_tile<P>(a, t / ncb, t % ncb, pending, T, smem);
+}
+
+// Screening tiles of many problems: entry (problem, rb, cb) per workgroup.
+template <int P>
+__global__ __launch_bounds__(kThreads) void grouped_screen_kernel(const StepArgs* __restrict__ descs,
+                                                                  const int4* __restrict__ tiles,
+                                                                  int ntiles, int s)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if ((int)blockIdx.x >= ntiles) return;
+    const int4 e = tiles[blockIdx.x];
+    const StepArgs& a = descs[e.x];
+    int pending, T;
+    bool due;
+    sched_at(a, s, pending, T, due);
+    screen_tile<P>(a, e.y, e.z, pending, T, smem);
+}
+
 // Chords of step `step` for one 16-walk tile (do_chords), then the directions
 // of step `dir_step` (gen_dirs) as FP64 rows, norms and the screening operand.
 template <int P>
-__global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint64_t step,
-                                                                int s_rel, int T, int do_chords,
-                                                                int gen_dirs, uint64_t dir_step)
+__device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_rel, int T,
+                            int do_chords, int gen_dirs, uint64_t dir_step)
 {
     __shared__ ChainLds cs_lds;
     __shared__ __align__(16) unsigned char stage_lds[kChordStageBytes];
     ChainLds* cs = &cs_lds;
     const int tid = threadIdx.x;
-    const int tile = blockIdx.x, c0 = tile * kChainTile;
+    const int c0 = tile * kChainTile;
     const int lda = a.lda, n = a.n;
     if (do_chords) {
         const int ngroups = a.m_pad / kRowGroup;
@@ -1200,25 +1233,44 @@ __global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint
     }
 }
 
+template <int P>
+__global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint64_t step,
+                                                                int s_rel, int T, int do_chords,
+                                                                int gen_dirs, uint64_t dir_step)
+{
+    chords_tile<P>(a, blockIdx.x, step, s_rel, T, do_chords, gen_dirs, dir_step);
+}
+
+// Chords (and next directions) of many problems: entry (problem, 16-walk tile).
+template <int P>
+__global__ __launch_bounds__(kThreads) void grouped_chords_kernel(const StepArgs* __restrict__ descs,
+                                                                  const int2* __restrict__ units,
+                                                                  int nunits, int s, int do_chords,
+                                                                  int gen_dirs)
+{
+    if ((int)blockIdx.x >= nunits) return;
+    const int2 u = units[blockIdx.x];
+    const StepArgs& a = descs[u.x];
+    int pending, T;
+    bool due;
+    sched_at(a, s, pending, T, due);
+    const uint64_t step = a.step0 + (uint64_t)s;
+    chords_tile<P>(a, u.y, step, s, T, do_chords, gen_dirs, do_chords ? step + 1 : step);
+}
+
 // Exact FP64 slack s = b - A X over (256-row x 64-walk) tiles on the FP64
 // matrix cores, stored in the screening layout; workgroups of the first row
 // block also reset the drift coefficient of their walks.
-constexpr int kRR = 256, kRW = 64, kRK = 16;
+constexpr int kRR = kRecRows, kRW = kRecWalks, kRK = 16;
 constexpr int kRRowBytes = kRK * 8 + 16;
 constexpr int kRStage = (kRR + kRW) * kRRowBytes;
 
-__global__ __launch_bounds__(kThreads) void tiled_recompute_kernel(StepArgs a)
+__device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char* smem)
 {
     constexpr int kChunkRow = kRK * 8 / 16;                 // 8
     constexpr int kAChunks = kRR * kChunkRow;               // 2048
     constexpr int kPer = (kRR + kRW) * kChunkRow / kThreads;  // 5
     static_assert((kRR + kRW) * kChunkRow % kThreads == 0, "chunk split");
-    extern __shared__ __align__(16) unsigned char smem[];
-
-    const int nrb = (a.m_pad + kRR - 1) / kRR, ncb = (a.z_pad + kRW - 1) / kRW;
-    const int t = xcd_tile(blockIdx.x, nrb * ncb);
-    if (t >= nrb * ncb) return;
-    const int rb = t / ncb, cb = t - rb * ncb;
     const int R0 = rb * kRR, C0 = cb * kRW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
@@ -1340,6 +1392,37 @@ __global__ __launch_bounds__(kThreads) void tiled_recompute_kernel(StepArgs a)
         fl |= __shfl_xor(fl, 32, 64);
         if (g == 0 && fl) atomicOr(&a.flags[chain], fl);
     }
+}
+
+__global__ __launch_bounds__(kThreads) void tiled_recompute_kernel(StepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nrb = (a.m_pad + kRR - 1) / kRR, ncb = (a.z_pad + kRW - 1) / kRW;
+    const int t = xcd_tile(blockIdx.x, nrb * ncb);
+    if (t >= nrb * ncb) return;
+    recompute_tile(a, t / ncb, t % ncb, smem);
+}
+
+// Recompute tiles of many problems: entry (problem, rb, cb).  first != 0: the
+// problems flagged recompute_first, before the launch's first step; else the
+// problems whose schedule has a recompute after step s.
+__global__ __launch_bounds__(kThreads) void grouped_recompute_kernel(const StepArgs* __restrict__ descs,
+                                                                     const int4* __restrict__ tiles,
+                                                                     int ntiles, int s, int first)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if ((int)blockIdx.x >= ntiles) return;
+    const int4 e = tiles[blockIdx.x];
+    const StepArgs& a = descs[e.x];
+    bool run;
+    if (first) {
+        run = a.recompute_first != 0;
+    } else {
+        int pending, T;
+        sched_at(a, s, pending, T, run);
+    }
+    if (!run) return;
+    recompute_tile(a, e.y, e.z, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1627,6 +1710,53 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream)
         if (e != hipSuccess) return e;
     }
     return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, int nst,
+                                   const int2* units, int nunits, const int4* rtiles, int nrt,
+                                   int steps, int first, const unsigned char* due,
+                                   hipStream_t stream)
+{
+    const size_t lds_s = 2 * (size_t)screen_stage_bytes<P>();
+    const size_t lds_r = 2 * (size_t)kRStage;
+    hipError_t e = hipFuncSetAttribute((const void*)grouped_screen_kernel<P>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)grouped_recompute_kernel,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
+    if (e != hipSuccess) return e;
+    if (first)
+        hipLaunchKernelGGL(grouped_recompute_kernel, dim3(nrt), dim3(kThreads), lds_r, stream, descs,
+                           rtiles, nrt, 0, 1);
+    if (steps > 0)
+        hipLaunchKernelGGL(grouped_chords_kernel<P>, dim3(nunits), dim3(kThreads), 0, stream, descs,
+                           units, nunits, 0, 0, 1);
+    for (int s = 0; s < steps; ++s) {
+        hipLaunchKernelGGL(grouped_screen_kernel<P>, dim3(nst), dim3(kThreads), lds_s, stream, descs,
+                           stiles, nst, s);
+        hipLaunchKernelGGL(grouped_chords_kernel<P>, dim3(nunits), dim3(kThreads), 0, stream, descs,
+                           units, nunits, s, 1, (int)(s + 1 < steps));
+        if (due[s])
+            hipLaunchKernelGGL(grouped_recompute_kernel, dim3(nrt), dim3(kThreads), lds_r, stream,
+                               descs, rtiles, nrt, s, 0);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grouped(int prec, const StepArgs* descs, const int4* stiles, int nst,
+                          const int2* units, int nunits, const int4* rtiles, int nrt, int steps,
+                          int first, const unsigned char* due, hipStream_t stream)
+{
+    switch (prec) {
+    case kFP32: return launch_grouped_t<kFP32>(descs, stiles, nst, units, nunits, rtiles, nrt, steps,
+                                               first, due, stream);
+    case kBF16X3: return launch_grouped_t<kBF16X3>(descs, stiles, nst, units, nunits, rtiles, nrt,
+                                                   steps, first, due, stream);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream)

@@ -57,3 +57,45 @@ def test_batch_rejects_mixed_precision():
     with pytest.raises(mhar.MharError) as ei:
         mhar.Batch([a, b])
     assert ei.value.code == mhar.E_INVALID_ARG
+
+
+def _mixed_problems():
+    # the first runs the tiled path on its own, the next two the resident kernel
+    # (tiled inside a batch), the last two the resident kernel (general kernel
+    # inside a batch)
+    return [inst.randpoly(n=300, m=1200, z=200, seed=51),
+            inst.simplex_cut(n=150, m_extra=2000, m_eq_extra=3, z=150, seed=52),
+            inst.rotbox(n=200, m_extra=1500, z=100, seed=53)[0],
+            inst.randpoly(n=30, m=200, z=40, seed=54),
+            inst.cube10(16)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_grouped_tiled_batch_equals_individual_runs(prec):
+    """Large problems of a batch run grouped tiled launches (one table of tiles
+    over all of them), small ones the persistent general kernel.  Handles are
+    stepped apart first by different amounts, so their recompute schedules
+    (R = 7) are out of phase inside the batch; the result must be bitwise that
+    of stepping each handle alone."""
+    probs = _mixed_problems()
+    offsets = [0, 3, 5, 1, 2]
+    gu.announce("grouped batch", prec)
+    singles = []
+    for p, off in zip(probs, offsets):
+        _, ch = gu.make(p, prec, recompute_every=7)
+        ch.step(off + 30)
+        singles.append(gu.state(ch)[0])
+    made = [gu.make(p, prec, recompute_every=7) for p in probs]
+    for (_, ch), off in zip(made, offsets):
+        if off:
+            ch.step(off)
+    batch = mhar.Batch([ch for _, ch in made])
+    # inside the batch the three large problems run the grouped tiled path
+    assert [ch.stats()["kernel"] for _, ch in made] == [3, 3, 3, 1, 1]
+    batch.step(13)
+    batch.step(17)
+    for (_, ch), want, p in zip(made, singles, probs):
+        got, st = gu.state(ch)
+        assert not st.any(), p.name
+        assert np.array_equal(got, want), p.name
+    batch.close()
