@@ -127,3 +127,41 @@ def test_largest_n():
         want, _, _ = orc.run(p.A, p.b, p.X0, 4, seed=0)
         assert not st.any()
         assert gu.rel_err(got, want) <= 1e-9, prec
+
+
+@pytest.mark.parametrize("path", ["auto", "general", "tiled"])
+def test_nan_inputs_rejected(path):
+    """A NaN in A, b or a start point makes that walk's start slack NaN, which
+    the interior check rejects on every kernel path."""
+    dev = gu.device()
+    base = inst.randpoly(n=12, m=50, z=5, seed=9)
+    cases = []
+    A = base.A.copy()
+    A[3, 4] = np.nan
+    cases.append((A, base.b, base.X0))
+    b = base.b.copy()
+    b[7] = np.nan
+    cases.append((base.A, b, base.X0))
+    X0 = base.X0.copy()
+    X0[2, 1] = np.nan
+    cases.append((base.A, base.b, X0))
+    gu.announce("nan inputs", path)
+    for A_, b_, X_ in cases:
+        prob = mhar.Problem(torch.tensor(A_, device=dev), torch.tensor(b_, device=dev),
+                            precision="fp32", path=path)
+        with pytest.raises(mhar.MharError) as ei:
+            mhar.Chains(prob, torch.tensor(X_, device=dev))
+        assert ei.value.code == mhar.E_NOT_INTERIOR
+
+
+def test_unbounded_flag_tiled():
+    # the half-line x <= 1: every line through a start point is unbounded below
+    A = np.array([[1.0]])
+    b = np.array([1.0])
+    p = inst.Polytope("halfline", A, b, np.zeros((20, 1)))
+    gu.announce("unbounded tiled")
+    _, ch = gu.make(p, "bf16x3", path="tiled")
+    ch.step(3)
+    X, st = gu.state(ch)
+    assert np.all(st & mhar.CHAIN_UNBOUNDED)
+    assert np.all(X == 0.0)
