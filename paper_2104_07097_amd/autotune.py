@@ -2,7 +2,7 @@
 
 For a shape bucket (n, m, m_eq, z rounded up to powers of two) it times short
 runs of candidate option sets -- screening precision, exact-recompute period
-R and steps per launch -- on a synthetic problem of that shape, and caches
+R, steps per launch and kernel path -- on a synthetic problem of that shape, and caches
 the fastest in a JSON file (``MHAR_AUTOTUNE_CACHE``, default
 ``~/.cache/mhar_autotune.json``).  Every candidate produces the same
 trajectories (the chord is evaluated exactly in FP64 whatever the options),
@@ -20,10 +20,12 @@ import numpy as np
 from . import instances as inst
 from . import mhar
 
-DEFAULT_CANDIDATES = [
-    {"precision": p, "recompute_every": r, "steps_per_launch": 0}
-    for p in ("fp32", "bf16x3") for r in (25, 50, 100)
-]
+DEFAULT_CANDIDATES = (
+    [{"precision": p, "recompute_every": r, "steps_per_launch": 0, "path": "auto"}
+     for p in ("fp32", "bf16x3") for r in (25, 50, 100)]
+    + [{"precision": p, "recompute_every": 50, "steps_per_launch": 0, "path": path}
+       for p in ("fp32", "bf16x3") for path in ("tiled", "general")]
+)
 
 
 def _bucket(v: int) -> int:
@@ -76,7 +78,11 @@ def tune(p: inst.Polytope, candidates=None, steps: int = 200, use_cache: bool = 
         return cache[key]["options"]
     results = []
     for opts in candidates or DEFAULT_CANDIDATES:
-        results.append((time_options(p, opts, steps=steps), opts))
+        try:
+            results.append((time_options(p, opts, steps=steps), opts))
+        except mhar.MharError as e:
+            if e.code not in (mhar.E_UNSUPPORTED, mhar.E_SHAPE):
+                raise   # a path that does not fit this shape is skipped; anything else is an error
     results.sort(key=lambda x: x[0])
     best_sec, best = results[0]
     if use_cache:

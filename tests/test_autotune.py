@@ -29,3 +29,19 @@ def test_tune_picks_fastest_and_caches(tmp_path, monkeypatch):
     assert again == best and len(calls) == 3
     data = json.load(open(tmp_path / "cache.json"))
     assert list(data) == [autotune.shape_key(10, 40, 0, 16)]
+
+
+def test_tune_skips_paths_that_do_not_fit(tmp_path, monkeypatch):
+    from paper_2104_07097_amd import mhar
+    monkeypatch.setenv("MHAR_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+
+    def timer(p, opts, steps=200, warmup=20):
+        if opts.get("path") == "resident":
+            raise mhar.MharError(mhar.E_UNSUPPORTED, "does not fit")
+        return 1.0 if opts.get("path") == "tiled" else 2.0
+
+    monkeypatch.setattr(autotune, "time_options", timer)
+    cands = [{"precision": "fp32", "recompute_every": 50, "steps_per_launch": 0, "path": q}
+             for q in ("resident", "general", "tiled")]
+    best = autotune.tune(inst.randpoly(n=10, m=40, z=16, seed=1), candidates=cands)
+    assert best["path"] == "tiled"
