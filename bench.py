@@ -250,6 +250,7 @@ def bench_rotbox(args):
         prob, ch = _make(p, "bf16x3")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        align = None
         if mode == "learned":
             ch.precond_create(args.rank)
             ch.precond_train(args.burnin, 0.05)
@@ -258,6 +259,13 @@ def bench_rotbox(args):
             ch.step(args.burnin)
         torch.cuda.synchronize()
         burn = time.perf_counter() - t0
+        if mode == "learned":
+            # what the fit learned: share of the trace of Sigma along the true
+            # longest `rank` axes (isotropic directions give rank / n)
+            U, ls = (v.cpu().numpy() for v in ch.precond_get())
+            Sig = U @ U.T + np.diag(np.exp(2.0 * ls))
+            top = Q[:, np.argsort(sides)[::-1][:args.rank]]
+            align = float(np.trace(top.T @ Sig @ top) / np.trace(Sig))
         start, _ = ch.state()
         sec = _timed_steps(ch, steps)
         Xend, _ = ch.state()
@@ -274,6 +282,9 @@ def bench_rotbox(args):
                      "burnin_s": burn, "max_marginal_ks_vs_exact": ks,
                      "replay_bitwise_identical": bool(torch.equal(Xrep, Xend)),
                      "flags": ch.sync()}
+        if align is not None:
+            out[mode]["sigma_share_on_true_top_axes"] = align
+            out[mode]["isotropic_share"] = args.rank / p.n
         ch.close()
         prob.close()
     line = _base_line(out["learned"]["chain_steps_per_sec"], steps, args.burnin,
