@@ -140,7 +140,7 @@ def cpu_baseline(p, seconds):
     t0 = time.perf_counter()
     X, _, _ = orc.run(p.A, p.b, p.X0, 1, seed=0, threads=threads)
     one = time.perf_counter() - t0
-    k = int(max(1, min(200, seconds / max(one, 1e-6))))
+    k = int(max(1, min(5000, seconds / max(one, 1e-6))))
     t0 = time.perf_counter()
     orc.run(p.A, p.b, X, k, seed=0, step0=1, threads=threads)
     dt = time.perf_counter() - t0
