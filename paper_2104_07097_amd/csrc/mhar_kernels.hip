@@ -950,7 +950,7 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     // K-steps are fetched kDepth ahead into a ring of register buffers (K-step
     // k in slot k % kDepth) and deposited into the LDS stage the next K-step
     // reads from, so about kDepth K-steps of compute cover the load latency.
-    constexpr int kDepth = 3;
+    constexpr int kDepth = 1;
     uint4 ring[kDepth][kPer];
     auto fetch = [&](uint4* dst, int k) __attribute__((always_inline)) {
         const bool live = k < nk;
@@ -1027,6 +1027,32 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
         }
     };
 
+    // slack and last product of this wave's entries, two walk tiles (a half)
+    // at a time; the first half is loaded before the main loop so that its
+    // latency is hidden behind the GEMM (only this tile writes these entries)
+    const float* S = (const float*)a.S;
+    const float* Gb = (const float*)a.G;
+    const int Q = a.m_pad >> 4;
+    auto load_half = [&](int half, float (*sv)[4][4], float (*gp)[4][4]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int cbase = C0 + wc * 64 + (2 * half + h) * 16;
+            const int tile = min(cbase, a.z_pad - kChainTile) / kChainTile;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const int q = ((R0 + wr * 64) >> 4) + rt;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
+                    sv[h][rt][r] = wave_rows ? S[idx] : 0.0f;
+                    gp[h][rt][r] = (wave_rows && pending) ? Gb[idx] : 0.0f;
+                }
+            }
+        }
+    };
+    float sv0[2][4][4], gp0[2][4][4];
+    load_half(0, sv0, gp0);
+
 #pragma unroll
     for (int u = 0; u < kDepth; ++u) fetch(ring[u], u);
     deposit(ring[0], 0);
@@ -1047,31 +1073,17 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     if (!wave_rows) return;
 
     // fused epilogue: deferred slack update, new product, interval bounds
-    float* S = (float*)a.S;
-    float* Gb = (float*)a.G;
-    const int Q = a.m_pad >> 4, ngroups = a.m_pad / kRowGroup;
+    float* Sw = (float*)a.S;
+    float* Gw = (float*)a.G;
+    const int ngroups = a.m_pad / kRowGroup;
     const int grp = (R0 + wr * 64) / kRowGroup;
     const float bscale = a.u_s * (float)T * kHighGrow;
-    // two halves of two walk tiles each: all slack and product loads of a half
-    // are issued before its arithmetic, so their latency is paid once
+    float sv1[2][4][4], gp1[2][4][4];
+    load_half(1, sv1, gp1);   // all loads of the second half issued before the arithmetic
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-        float sv[2][4][4], gp[2][4][4];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int cbase = C0 + wc * 64 + (2 * half + h) * 16;
-            const int tile = min(cbase, a.z_pad - kChainTile) / kChainTile;
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                const int q = ((R0 + wr * 64) >> 4) + rt;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
-                    sv[h][rt][r] = S[idx];
-                    gp[h][rt][r] = pending ? Gb[idx] : 0.0f;
-                }
-            }
-        }
+        float (*sv)[4][4] = half ? sv1 : sv0;
+        float (*gp)[4][4] = half ? gp1 : gp0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int ct = 2 * half + h;
@@ -1094,9 +1106,9 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
                     float s_ = sv[h][rt][r];
                     if (pending) {
                         s_ = fmaf(-th, gp[h][rt][r], s_);
-                        S[idx] = s_;
+                        Sw[idx] = s_;
                     }
-                    Gb[idx] = gv;
+                    Gw[idx] = gv;
                     const float na = a.rownorm[row];
                     const float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
                     const float e = na * ed;
@@ -1145,7 +1157,7 @@ __global__ __launch_bounds__(kThreads) void grouped_screen_kernel(const StepArgs
     extern __shared__ __align__(16) unsigned char smem[];
     if ((int)blockIdx.x >= ntiles) return;
     const int4 e = tiles[blockIdx.x];
-    const StepArgs& a = descs[e.x];
+    const StepArgs a = descs[e.x];   // a private copy: no aliasing with the stores
     int pending, T;
     bool due;
     sched_at(a, s, pending, T, due);
@@ -1250,7 +1262,7 @@ __global__ __launch_bounds__(kThreads) void grouped_chords_kernel(const StepArgs
 {
     if ((int)blockIdx.x >= nunits) return;
     const int2 u = units[blockIdx.x];
-    const StepArgs& a = descs[u.x];
+    const StepArgs a = descs[u.x];   // a private copy: no aliasing with the stores
     int pending, T;
     bool due;
     sched_at(a, s, pending, T, due);
@@ -1413,7 +1425,7 @@ __global__ __launch_bounds__(kThreads) void grouped_recompute_kernel(const StepA
     extern __shared__ __align__(16) unsigned char smem[];
     if ((int)blockIdx.x >= ntiles) return;
     const int4 e = tiles[blockIdx.x];
-    const StepArgs& a = descs[e.x];
+    const StepArgs a = descs[e.x];   // a private copy: no aliasing with the stores
     bool run;
     if (first) {
         run = a.recompute_first != 0;
