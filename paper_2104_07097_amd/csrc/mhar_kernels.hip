@@ -826,7 +826,8 @@ __global__ __launch_bounds__(kThreads) void mhar_batch_kernel(const StepArgs* __
         __syncthreads();
         if (u >= nunits) break;
         const int2 w = units[u];
-        run_tile<P>(descs[w.x], smem, w.y);
+        const StepArgs a = descs[w.x];   // a private copy: no aliasing with the stores
+        run_tile<P>(a, smem, w.y);
     }
 }
 
