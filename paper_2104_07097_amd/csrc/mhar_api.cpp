@@ -20,6 +20,7 @@ struct mhar_problem {
     double *A64, *b64, *Aeq, *beq, *WT;
     float *A32, *rownorm, *absb;
     __bf16 *Ahi, *Alo;
+    void* Apk;   // operand in the resident kernel's load order (nullptr if unused)
     int* status;
     int live_chains;
 };
@@ -167,6 +168,7 @@ size_t carve_problem(const ProblemDims& d, int prec, void* ws, mhar_problem* p)
     q->A32 = prec == MHAR_FP32 ? c.take<float>(mat) : nullptr;
     q->Ahi = prec == MHAR_BF16X3 ? c.take<__bf16>(mat) : nullptr;
     q->Alo = prec == MHAR_BF16X3 ? c.take<__bf16>(mat) : nullptr;
+    q->Apk = prec != MHAR_FP64 && d.lda <= kMaxNResident ? (void*)c.take<float>(mat) : nullptr;
     q->b64 = c.take<double>(d.m_pad);
     q->rownorm = c.take<float>(d.m_pad);
     q->absb = c.take<float>(d.m_pad);
@@ -246,6 +248,7 @@ StepArgs make_args(const mhar_chains* c)
     a.A32 = p->A32;
     a.Ahi = p->Ahi;
     a.Alo = p->Alo;
+    a.Apk = p->Apk;
     a.b64 = p->b64;
     a.rownorm = p->rownorm;
     a.absb = p->absb;
@@ -445,6 +448,8 @@ mhar_status_t mhar_problem_create(int64_t n, int64_t m, const double* A, const d
     hipError_t e = launch_convert_problem(p->prec, p->n, p->m, p->m_pad, p->lda, A, b, p->A64,
                                           p->A32, p->Ahi, p->Alo, p->b64, p->rownorm, p->absb,
                                           stream);
+    if (e == hipSuccess && p->Apk)
+        e = launch_pack_operand(p->prec, p->m_pad, p->lda, p->A32, p->Ahi, p->Alo, p->Apk, stream);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(e, "problem conversion");

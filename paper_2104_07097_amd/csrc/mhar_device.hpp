@@ -134,6 +134,8 @@ constexpr float kInf = __builtin_huge_valf();
 constexpr double kInfD = __builtin_huge_val();
 constexpr float kLowShrink = 1.0f - 0x1.0p-20f;  // turns rounded lower bounds into safe ones
 constexpr float kHighGrow = 1.0f + 0x1.0p-20f;
+constexpr float kScreenSlack = 1.0f + 0x1.0p-18f;  // product form of the candidate test
+constexpr float kTinySlack = 0x1.0p-100f;         // slack lower bounds below this are always candidates
 
 // Interval bounds of the two chord-end ratios of one (row, walk) entry.
 //   s, g   : approximate slack and directional derivative

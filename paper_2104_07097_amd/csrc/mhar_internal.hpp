@@ -14,6 +14,7 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kRowGroup = 64;    // rows one wave handles per pass (4 MFMA row blocks)
 constexpr int kKAlign = 32;      // padded row length (K) granularity
 constexpr int kMaxN = 1152;      // LDS holds 16 padded FP64 rows of length <= kMaxN
+constexpr int kMaxNResident = 256;  // longest padded row of the register-resident kernel
 constexpr int kMaxNTiled = 8192; // the tiled path keeps no row of length n in LDS
 constexpr int kScreenRows = 256; // tiled path: rows x walks of a screening tile
 constexpr int kScreenWalks = 128;
@@ -45,6 +46,12 @@ struct StepArgs {
     const float* A32;       // m_pad x lda (FP32 mode)
     const __bf16* Ahi;      // m_pad x lda (BF16X3 mode)
     const __bf16* Alo;
+    // the same operand in the load order of the register-resident kernel
+    // (lda <= kMaxNResident): for each 16-row block R and 32-column chunk kc,
+    // two 1 KB units of 64 lanes x 16 B; lane 16 g + c of unit u holds row
+    // 16 R + c, FP32 columns 32 kc + 8 g + 4 u + (0..3), or the BF16 hi (u = 0)
+    // or lo (u = 1) parts of columns 32 kc + 8 g + (0..7)
+    const void* Apk;
     const double* b64;      // m_pad (padding rows: 1)
     const float* rownorm;   // m_pad, ||a_i|| rounded up (padding rows: 0)
     const float* absb;      // m_pad, |b_i| rounded up
@@ -119,6 +126,8 @@ hipError_t launch_convert_problem(int prec, int n, int m, int m_pad, int lda, co
                                   const double* b, double* A64, float* A32, __bf16* Ahi,
                                   __bf16* Alo, double* b64, float* rownorm, float* absb,
                                   hipStream_t stream);
+hipError_t launch_pack_operand(int prec, int m_pad, int lda, const float* A32, const __bf16* Ahi,
+                               const __bf16* Alo, void* Apk, hipStream_t stream);
 hipError_t launch_eq_setup(int n, int lda, int m_eq, const double* Aeq_in, const double* beq_in,
                            double* Aeq, double* beq, double* WT, int* status,
                            hipStream_t stream);

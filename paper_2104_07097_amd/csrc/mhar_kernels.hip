@@ -1803,6 +1803,35 @@ hipError_t launch_convert_problem(int prec, int n, int m, int m_pad, int lda, co
     return hipGetLastError();
 }
 
+// Operand copy in the load order of the register-resident kernel: one
+// thread per 16-byte lane unit (layout at StepArgs::Apk).
+__global__ void pack_operand_kernel(int prec, int m_pad, int lda, const float* __restrict__ A32,
+                                    const __bf16* __restrict__ Ahi, const __bf16* __restrict__ Alo,
+                                    uint4* __restrict__ Apk)
+{
+    const int nk = lda / 32;
+    const size_t units = (size_t)(m_pad / 16) * nk * 128;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= units) return;
+    const int l = (int)(i & 63), u = (int)((i >> 6) & 1);
+    const size_t blk = i >> 7;   // R * nk + kc
+    const int kc = (int)(blk % nk), R = (int)(blk / nk);
+    const int g = l >> 4, c = l & 15;
+    const size_t row = (size_t)16 * R + c;
+    if (prec == kFP32) Apk[i] = *(const uint4*)(A32 + row * lda + 32 * kc + 8 * g + 4 * u);
+    else Apk[i] = *(const uint4*)((u ? Alo : Ahi) + row * lda + 32 * kc + 8 * g);
+}
+
+hipError_t launch_pack_operand(int prec, int m_pad, int lda, const float* A32, const __bf16* Ahi,
+                               const __bf16* Alo, void* Apk, hipStream_t stream)
+{
+    if ((prec != kFP32 && prec != kBF16X3) || lda % 32 || m_pad % 16) return hipErrorInvalidValue;
+    const size_t units = (size_t)(m_pad / 16) * (lda / 32) * 128;
+    hipLaunchKernelGGL(pack_operand_kernel, dim3((unsigned)((units + 255) / 256)), dim3(256), 0, stream,
+                       prec, m_pad, lda, A32, Ahi, Alo, (uint4*)Apk);
+    return hipGetLastError();
+}
+
 hipError_t launch_eq_setup(int n, int lda, int m_eq, const double* Aeq_in, const double* beq_in,
                            double* Aeq, double* beq, double* WT, int* status, hipStream_t stream)
 {

@@ -47,9 +47,8 @@ struct ResLds {
     int flags[kChainTile];
     int cand_row[kWaves][kCandBatch];
     int cand_chain[kWaves][kCandBatch];
-    unsigned long long mask[kWaves][16];   // candidate ballots of each wave's 16 output slots
-    float rownorm[kRowsPerWg];
-    float absb[kRowsPerWg];
+    alignas(16) float rownorm[kRowsPerWg];
+    alignas(16) float absb[kRowsPerWg];
     unsigned long long exact;
     int ok;
 };
@@ -76,7 +75,7 @@ __host__ __device__ inline ResLayout res_layout(int prec, int lda)
     const size_t st = al16(sizeof(ResLds));
     const size_t budget = 163840;
     const size_t used = L.cb_off + st;
-    const size_t per_row = (size_t)kWaves * lda * 8;
+    const size_t per_row = (size_t)kWaves * (lda + 2) * 8;   // rows padded by two doubles
     int rows = used < budget ? (int)((budget - used) / per_row) : 0;
     if (rows > kCandBatch) rows = kCandBatch;
     L.cb_rows = rows;
@@ -121,6 +120,32 @@ __device__ bool group_wait(unsigned* cnt, unsigned target, int* err, int* ok_lds
     __syncthreads();
     return *ok_lds != 0;
 }
+
+// Wave sums of two and four values, exchanged together so that the
+// exchange latencies of the values overlap.
+__device__ __forceinline__ void wave_sum2(double& u, double& v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double pu = __shfl_xor(u, o, 64), pv = __shfl_xor(v, o, 64);
+        u += pu;
+        v += pv;
+    }
+}
+
+__device__ __forceinline__ void wave_sum4(double* q)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double p[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p[i] = __shfl_xor(q[i], o, 64);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[i] += p[i];
+    }
+}
+
+static_assert(kChainTile == 2 * kWaves, "each wave owns two walks of the tile");
 
 template <int P, int NK>
 __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
@@ -220,11 +245,18 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             }
             __syncthreads();
         }
-        for (int cl = wave; cl < kChainTile; cl += kWaves) {
-            double v = 0.0;
-            for (int j = lane; j < n; j += 64) v = fma(Dt[cl * xld + j], Dt[cl * xld + j], v);
-            v = wave_sum(v);
-            if (lane == 0) cs->dnorm[buf][cl] = sqrt(v);
+        {
+            const int cl0 = wave, cl1 = wave + kWaves;
+            double v0 = 0.0, v1 = 0.0;
+            for (int j = lane; j < n; j += 64) {
+                v0 = fma(Dt[cl0 * xld + j], Dt[cl0 * xld + j], v0);
+                v1 = fma(Dt[cl1 * xld + j], Dt[cl1 * xld + j], v1);
+            }
+            wave_sum2(v0, v1);
+            if (lane == 0) {
+                cs->dnorm[buf][cl0] = sqrt(v0);
+                cs->dnorm[buf][cl1] = sqrt(v1);
+            }
         }
         if (P == kFP32) {
             float* Ot = (float*)op;
@@ -255,12 +287,19 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
     for (int s = 0;; ++s) {
         if (recompute_now) {
             // exact FP64 slack b - A x of this wave's rows (FP64 matrix cores)
-            for (int cl = wave; cl < kChainTile; cl += kWaves) {
-                double v = 0.0;
-                for (int j = lane; j < n; j += 64) v = fma(Xt[cl * xld + j], Xt[cl * xld + j], v);
-                v = wave_sum(v);
-                if (lane == 0)
-                    cs->E[cl] = ((double)a.u_s * (1.0 + 0x1.0p-20) + (2.0 * n + 4.0) * u64) * sqrt(v);
+            {
+                const int cl0 = wave, cl1 = wave + kWaves;
+                double v0 = 0.0, v1 = 0.0;
+                for (int j = lane; j < n; j += 64) {
+                    v0 = fma(Xt[cl0 * xld + j], Xt[cl0 * xld + j], v0);
+                    v1 = fma(Xt[cl1 * xld + j], Xt[cl1 * xld + j], v1);
+                }
+                wave_sum2(v0, v1);
+                if (lane == 0) {
+                    const double f = (double)a.u_s * (1.0 + 0x1.0p-20) + (2.0 * n + 4.0) * u64;
+                    cs->E[cl0] = f * sqrt(v0);
+                    cs->E[cl1] = f * sqrt(v1);
+                }
             }
             int fl = 0;
             if (rows_live) {
@@ -329,12 +368,16 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                 const float* Ot = (const float*)op;
                 constexpr int fld = lda + 4;
                 float4 bufa[2][8];
+                // packed operand: each load is one contiguous 1 KB unit
+                // (wave-uniform base + the lane's 16-byte slot)
+                const char* Ab = (const char*)a.Apk + (size_t)(__builtin_amdgcn_readfirstlane(row0) >> 4) * NK * 2048;
+                const unsigned loff = 16u * lane;
                 auto load = [&](float4* dst, int kc) __attribute__((always_inline)) {
 #pragma unroll
                     for (int rb = 0; rb < 4; ++rb) {
-                        const float4* ap = (const float4*)(a.A32 + (size_t)(row0 + 16 * rb + c) * a.lda + kc * 32 + 8 * g);
-                        dst[2 * rb] = ap[0];
-                        dst[2 * rb + 1] = ap[1];
+                        const char* ap = Ab + (size_t)(rb * NK + kc) * 2048 + loff;
+                        dst[2 * rb] = *(const float4*)ap;
+                        dst[2 * rb + 1] = *(const float4*)(ap + 1024);
                     }
                 };
                 load(bufa[0], 0);
@@ -359,12 +402,15 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                 constexpr int bld = lda + 8;
                 const __bf16* Ol = Oh + kChainTile * bld;
                 bf16x8 bufa[2][8];
+                // packed operand: hi and lo parts, each one contiguous 1 KB unit
+                const char* Ab = (const char*)a.Apk + (size_t)(__builtin_amdgcn_readfirstlane(row0) >> 4) * NK * 2048;
+                const unsigned loff = 16u * lane;
                 auto load = [&](bf16x8* dst, int kc) __attribute__((always_inline)) {
 #pragma unroll
                     for (int rb = 0; rb < 4; ++rb) {
-                        const size_t off = (size_t)(row0 + 16 * rb + c) * a.lda + kc * 32 + 8 * g;
-                        dst[2 * rb] = *(const bf16x8*)(a.Ahi + off);
-                        dst[2 * rb + 1] = *(const bf16x8*)(a.Alo + off);
+                        const char* ap = Ab + (size_t)(rb * NK + kc) * 2048 + loff;
+                        dst[2 * rb] = *(const bf16x8*)ap;
+                        dst[2 * rb + 1] = *(const bf16x8*)(ap + 1024);
                     }
                 };
                 load(bufa[0], 0);
@@ -384,32 +430,39 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             }
         }
 
-        // ---------------- screening: certified bounds, candidate masks ----------------
+        // ---------------- screening: certified bounds, candidate list ----------------
         // Every workgroup screens its rows with its own upper bounds of the
         // chord ends; they can only exceed the bounds over all rows, so the
         // candidate set is a superset of the one the global bound would give.
+        // Pass 1 takes the upper bound of each entry's ratio, (s + dl) / (|g| - e)
+        // where |g| > e surely, and the minimum per walk and side.  Pass 2
+        // keeps the entries whose lower bound max(s - dl, 0) / (|g| + e) can
+        // reach that minimum, tested as a product so that no second
+        // reciprocal is needed; the same for the other side where |g| < e.
         const float ed = active_c ? (float)(cs->dnorm[buf][c] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
         const float Ek = (float)cs->E[c] * kHighGrow;
         const float bscale = a.u_s * (float)T * kHighGrow;
-        float lo_p[4][4], lo_m[4][4];
+        float dls[4][4];
         {
             float up = kInf, um = kInf;
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int rb = 0; rb < 4; ++rb) {
+                const int li0 = wave * kRowGroup + 16 * rb + 4 * g;   // rows li0 .. li0 + 3
+                const float4 na4 = *(const float4*)&cs->rownorm[li0];
+                const float4 ab4 = *(const float4*)&cs->absb[li0];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int li = wave * kRowGroup + 16 * rb + 4 * g + r;   // row within the workgroup
-                    float hp = kInf, hm = kInf;
-                    lo_p[rb][r] = kInf;
-                    lo_m[rb][r] = kInf;
-                    if (rows_live && rbase + li < m) {
-                        const float na = cs->rownorm[li];
-                        const float dl = fmaf(na, Ek, fmaf(bscale, cs->absb[li], 1e-30f));
-                        ratio_bounds(S[rb][r], acc[rb][r], dl, na * ed, lo_p[rb][r], hp, lo_m[rb][r], hm);
-                    }
-                    up = fminf(up, hp);
-                    um = fminf(um, hm);
+                    const float na = (&na4.x)[r], ab = (&ab4.x)[r];
+                    const float dl = fmaf(na, Ek, fmaf(bscale, ab, 1e-30f));
+                    dls[rb][r] = dl;
+                    const float gv = acc[rb][r];
+                    const float den = fabsf(gv) - na * ed;
+                    float h = (S[rb][r] + dl) * __builtin_amdgcn_rcpf(den);
+                    h = den > 0.0f ? h : kInf;
+                    up = fminf(up, gv > 0.0f ? h : kInf);
+                    um = fminf(um, gv < 0.0f ? h : kInf);
                 }
+            }
             up = fminf(up, __shfl_xor(up, 16, 64));
             up = fminf(up, __shfl_xor(up, 32, 64));
             um = fminf(um, __shfl_xor(um, 16, 64));
@@ -421,80 +474,136 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             }
         }
         __syncthreads();
+        // candidate bits of this lane's 16 entries (slot 4 rb + r)
+        unsigned cbits = 0;
         {
-            const float Up = __uint_as_float(cs->up[c]), Um = __uint_as_float(cs->um[c]);
+            // kScreenSlack covers the roundings of both ratio bounds and of
+            // the products below
+            const float Up = __uint_as_float(cs->up[c]) * kScreenSlack;
+            const float Um = __uint_as_float(cs->um[c]) * kScreenSlack;
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+            for (int rb = 0; rb < 4; ++rb) {
+                const int li0 = wave * kRowGroup + 16 * rb + 4 * g;
+                const float4 na4 = *(const float4*)&cs->rownorm[li0];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int row = row0 + 16 * rb + 4 * g + r;
-                    const bool cand = active_c && row < m && ((lo_p[rb][r] <= Up) || (lo_m[rb][r] <= Um));
-                    const unsigned long long mk = __ballot(cand);
-                    if (lane == 0) cs->mask[wave][rb * 4 + r] = mk;
+                    const float e = (&na4.x)[r] * ed;
+                    const float gv = acc[rb][r], ag = fabsf(gv);
+                    const float slo = fmaxf(S[rb][r] - dls[rb][r], 0.0f);
+                    const bool pos = gv >= 0.0f;
+                    const float us = pos ? Up : Um, uo = pos ? Um : Up;
+                    const float go = e - ag;
+                    const bool cand = slo <= us * (ag + e) || (go > 0.0f && slo <= uo * go) || slo <= kTinySlack;
+                    if (active_c && row < m && cand) cbits |= 1u << (4 * rb + r);
                 }
+            }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
 
         // ---------------- C: exact chords of the candidate rows ----------------
         {
-            double* cb = Cb + (size_t)wave * CB * lda;
-            int slot = 0;
-            unsigned long long mk = cs->mask[wave][0];
-            unsigned long long nex = 0;
-            while (true) {
-                int cnt = 0;
-                while (cnt < CB) {
-                    while (mk == 0 && slot < 15) mk = cs->mask[wave][++slot];
-                    if (mk == 0) break;
-                    const int bit = __ffsll((long long)mk) - 1;
-                    mk &= mk - 1;
-                    if (lane == 0) {
-                        cs->cand_row[wave][cnt] = row0 + 16 * (slot >> 2) + 4 * (bit >> 4) + (slot & 3);
-                        cs->cand_chain[wave][cnt] = bit & 15;
-                    }
-                    ++cnt;
-                }
-                if (cnt == 0) break;
-                nex += cnt;
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                for (int q = 0; q < cnt; ++q) {
-                    const double* ar = a.A64 + (size_t)cs->cand_row[wave][q] * a.lda;
+            constexpr int cld = lda + 2;          // padded: candidate rows on distinct banks
+            constexpr int kPer = (lda + 127) / 128;
+            double* cb = Cb + (size_t)wave * CB * cld;
+            int total = 0;
 #pragma unroll
-                    for (int j = 2 * lane; j < lda; j += 128) *(double2*)(cb + q * lda + j) = *(const double2*)(ar + j);
+            for (int k = 0; k < 16; ++k) total += __popcll(__ballot((cbits >> k) & 1u));
+            for (int base = 0; base < total; base += CB) {
+                const int cnt = min(CB, total - base);
+                // list: position of an entry = its rank in (slot, lane) order
+                int off = 0;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const bool f = (cbits >> k) & 1u;
+                    const unsigned long long bk = __ballot(f);
+                    const int pos = off - base +
+                                    (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bk >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)bk, 0u));
+                    if (f && pos >= 0 && pos < cnt) {
+                        cs->cand_row[wave][pos] = row0 + 16 * (k >> 2) + 4 * g + (k & 3);
+                        cs->cand_chain[wave][pos] = c;
+                    }
+                    off += __popcll(bk);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
+                // each lane < cnt evaluates one candidate
+                int rr = 0, cc = 0;
+                double bi = 0.0;
                 if (lane < cnt) {
-                    // the line-set formula of S4.4 in the operation order of a
-                    // sequential FP64 evaluation
-                    const int rr = cs->cand_row[wave][lane];
-                    const int cc = cs->cand_chain[wave][lane];
-                    const double* av = cb + lane * lda;
-                    const double* xv = Xt + cc * xld;
-                    const double* dv = Dt + cc * xld;
-                    const double bi = a.b64[rr];
-                    double sx = bi, gx = 0.0;
+                    rr = cs->cand_row[wave][lane];
+                    cc = cs->cand_chain[wave][lane];
+                    bi = a.b64[rr];
+                }
+                // stage the rows, four at a time: the four loads are issued
+                // before the first store (a missing candidate repeats the
+                // last one, so the loads need no branch)
+#pragma unroll
+                for (int q0 = 0; q0 < kCandBatch; q0 += 4) {
+                    if (q0 < cnt) {
+                        double2 rv[4][kPer];
+#pragma unroll
+                        for (int qq = 0; qq < 4; ++qq) {
+                            const int q = min(q0 + qq, cnt - 1);
+                            const double* ar = a.A64 + (size_t)cs->cand_row[wave][q] * a.lda;
+#pragma unroll
+                            for (int t = 0; t < kPer; ++t) {
+                                const int j = min(2 * lane + 128 * t, lda - 2);
+                                rv[qq][t] = *(const double2*)(ar + j);
+                            }
+                        }
+#pragma unroll
+                        for (int qq = 0; qq < 4; ++qq) {
+                            if (q0 + qq < cnt) {
+#pragma unroll
+                                for (int t = 0; t < kPer; ++t) {
+                                    const int j = 2 * lane + 128 * t;
+                                    if (j < lda) *(double2*)(cb + (q0 + qq) * cld + j) = rv[qq][t];
+                                }
+                            }
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                // the line-set formula of S4.4 in the operation order of a
+                // sequential FP64 evaluation: lane q < cnt sums the slack
+                // b - a.x of candidate q, lane 32 + q its a.d (a - b is
+                // summed as a + (-b), which rounds the same)
+                const int qh = lane & 31;
+                const int cq = __shfl(cc, qh, 64);   // all lanes take part in the exchange
+                double sum = 0.0;
+                if (qh < cnt) {
+                    const bool slack = lane < 32;
+                    const double* av = cb + qh * cld;
+                    const double* vv = (slack ? Xt : Dt) + cq * xld;
+                    const unsigned flip = slack ? 0x80000000u : 0u;
+                    sum = slack ? bi : 0.0;
                     int j = 0;
                     for (; j + 8 <= n; j += 8) {
-                        double av8[8], xv8[8], dv8[8];
+                        double a8[8], v8[8];
 #pragma unroll
                         for (int e = 0; e < 8; ++e) {
-                            av8[e] = av[j + e];
-                            xv8[e] = xv[j + e];
-                            dv8[e] = dv[j + e];
+                            a8[e] = av[j + e];
+                            v8[e] = vv[j + e];
                         }
 #pragma unroll
                         for (int e = 0; e < 8; ++e) {
-                            sx = __dsub_rn(sx, __dmul_rn(av8[e], xv8[e]));
-                            gx = __dadd_rn(gx, __dmul_rn(av8[e], dv8[e]));
+                            double t = __dmul_rn(a8[e], v8[e]);
+                            t = __hiloint2double(__double2hiint(t) ^ (int)flip, __double2loint(t));
+                            sum = __dadd_rn(sum, t);
                         }
                     }
                     for (; j < n; ++j) {
-                        sx = __dsub_rn(sx, __dmul_rn(av[j], xv[j]));
-                        gx = __dadd_rn(gx, __dmul_rn(av[j], dv[j]));
+                        double t = __dmul_rn(av[j], vv[j]);
+                        t = __hiloint2double(__double2hiint(t) ^ (int)flip, __double2loint(t));
+                        sum = __dadd_rn(sum, t);
                     }
+                }
+                const double gsum = __shfl(sum, qh + 32, 64);
+                if (lane < cnt) {
+                    double sx = sum;
+                    const double gx = gsum;
                     int fl = 0;
                     if (sx < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
                     if (sx < 0.0) sx = 0.0;
@@ -507,7 +616,7 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
-            if (lane == 0 && nex) atomicAdd(&cs->exact, nex);
+            if (lane == 0 && total) atomicAdd(&cs->exact, (unsigned long long)total);
         }
         __syncthreads();
 
@@ -581,38 +690,56 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             cs->theta[lane] = th_l;
             if (fl_l) cs->flags[lane] |= fl_l;
         }
-        for (int cl = wave; cl < kChainTile; cl += kWaves) {
-            const int chain = c0 + cl;
-            if (chain >= a.z) continue;
-            const double th = __shfl(th_l, cl, 64);
-            double xo = 0.0, xn2 = 0.0;
-            bool finite = isfinite(th);
-            const bool rec = slice == 0 && a.rec_stride > 0 && chain < a.rec_chains &&
-                             ((a.rec_s_base + s + 1) % a.rec_stride) == 0;
-            double* rp = rec ? a.rec_out + ((size_t)((a.rec_s_base + s + 1) / a.rec_stride - 1) *
-                                                a.rec_chains + chain) * n
-                             : nullptr;
+        {
+            // the two walks of this wave, updated together
+            const int cl0 = wave, cl1 = wave + kWaves;
+            const bool v0 = c0 + cl0 < a.z, v1 = c0 + cl1 < a.z;
+            const double th0 = __shfl(th_l, cl0, 64), th1 = __shfl(th_l, cl1, 64);
+            const int64_t rs = a.rec_s_base + s + 1;
+            const bool recs = slice == 0 && a.rec_stride > 0 && (rs % a.rec_stride) == 0;
+            const bool rec0 = recs && v0 && c0 + cl0 < a.rec_chains;
+            const bool rec1 = recs && v1 && c0 + cl1 < a.rec_chains;
+            double* rp0 = rec0 ? a.rec_out + ((size_t)(rs / a.rec_stride - 1) * a.rec_chains + c0 + cl0) * n : nullptr;
+            double* rp1 = rec1 ? a.rec_out + ((size_t)(rs / a.rec_stride - 1) * a.rec_chains + c0 + cl1) * n : nullptr;
+            double q[4] = {0.0, 0.0, 0.0, 0.0};   // |x|^2, |x'|^2 of both walks
+            bool fin0 = isfinite(th0), fin1 = isfinite(th1);
             for (int j = lane; j < n; j += 64) {
-                const double xv = Xt[cl * xld + j];
-                const double xnew = __dadd_rn(xv, __dmul_rn(th, Dt[cl * xld + j]));
-                Xt[cl * xld + j] = xnew;
-                if (rec) rp[j] = xnew;
-                xo = fma(xv, xv, xo);
-                xn2 = fma(xnew, xnew, xn2);
-                finite = finite && isfinite(xnew);
+                if (v0) {
+                    const double xv = Xt[cl0 * xld + j];
+                    const double xnew = __dadd_rn(xv, __dmul_rn(th0, Dt[cl0 * xld + j]));
+                    Xt[cl0 * xld + j] = xnew;
+                    if (rec0) rp0[j] = xnew;
+                    q[0] = fma(xv, xv, q[0]);
+                    q[1] = fma(xnew, xnew, q[1]);
+                    fin0 = fin0 && isfinite(xnew);
+                }
+                if (v1) {
+                    const double xv = Xt[cl1 * xld + j];
+                    const double xnew = __dadd_rn(xv, __dmul_rn(th1, Dt[cl1 * xld + j]));
+                    Xt[cl1 * xld + j] = xnew;
+                    if (rec1) rp1[j] = xnew;
+                    q[2] = fma(xv, xv, q[2]);
+                    q[3] = fma(xnew, xnew, q[3]);
+                    fin1 = fin1 && isfinite(xnew);
+                }
             }
-            xo = wave_sum(xo);
-            xn2 = wave_sum(xn2);
-            finite = __all(finite);
+            wave_sum4(q);
+            fin0 = __all(fin0);
+            fin1 = __all(fin1);
             if (lane == 0) {
-                const double dn = cs->dnorm[buf][cl], at = fabs(th);
-                const double us = (double)a.u_s;
-                double E = cs->E[cl];
-                E += at * dn * ((double)a.eps_g + 2.0 * us);
-                E += 2.0 * u64 * (sqrt(xo) + at * dn);
-                E += us * (1.0 + 0x1.0p-20) * sqrt(xn2);
-                cs->E[cl] = E;
-                if (!finite) cs->flags[cl] |= kNonFinite;
+                // bound on the slack error carried into the next step
+                auto grow_E = [&](int cl, double th, double xo, double xn2, bool finite) {
+                    const double dn = cs->dnorm[buf][cl], at = fabs(th);
+                    const double us = (double)a.u_s;
+                    double E = cs->E[cl];
+                    E += at * dn * ((double)a.eps_g + 2.0 * us);
+                    E += 2.0 * u64 * (sqrt(xo) + at * dn);
+                    E += us * (1.0 + 0x1.0p-20) * sqrt(xn2);
+                    cs->E[cl] = E;
+                    if (!finite) cs->flags[cl] |= kNonFinite;
+                };
+                if (v0) grow_E(cl0, th0, q[0], q[1], fin0);
+                if (v1) grow_E(cl1, th1, q[2], q[3], fin1);
             }
         }
         __syncthreads();
@@ -708,7 +835,7 @@ int res_occupancy(int lda)
 int resident_split(int prec, int lda, int m_pad, int z_pad)
 {
     if (prec != kFP32 && prec != kBF16X3) return 0;
-    if (lda > 256 || res_layout(prec, lda).cb_rows < 1) return 0;
+    if (lda > kMaxNResident || res_layout(prec, lda).cb_rows < 1) return 0;
     const int rows = kWaves * kRowGroup;
     const int split = (m_pad + rows - 1) / rows;
     if (split > 16) return 0;
