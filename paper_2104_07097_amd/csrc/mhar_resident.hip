@@ -123,27 +123,49 @@ __device__ bool group_wait(unsigned* cnt, unsigned target, int* err, int* ok_lds
 
 // Wave sums of two and four values, exchanged together so that the
 // exchange latencies of the values overlap.
-__device__ __forceinline__ void wave_sum2(double& u, double& v)
+// One data-parallel-primitive move of a double (both halves); lanes of rows
+// outside row_mask receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double x)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double pu = __shfl_xor(u, o, 64), pv = __shfl_xor(v, o, 64);
-        u += pu;
-        v += pv;
-    }
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xf, false);
+    return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ void wave_sum4(double* q)
+// Sums of K values over the wave, all lanes get the totals: quad swaps,
+// half-row and row mirrors, then the row broadcasts of lanes 15 and 31
+// leave the total in lane 63.
+template <int K>
+__device__ __forceinline__ void wave_sums(double* q)
 {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double p[4];
+    for (int i = 0; i < K; ++i) q[i] += dpp_move<0xB1, 0xf>(q[i]);    // quad_perm 1,0,3,2
 #pragma unroll
-        for (int i = 0; i < 4; ++i) p[i] = __shfl_xor(q[i], o, 64);
+    for (int i = 0; i < K; ++i) q[i] += dpp_move<0x4E, 0xf>(q[i]);    // quad_perm 2,3,0,1
 #pragma unroll
-        for (int i = 0; i < 4; ++i) q[i] += p[i];
-    }
+    for (int i = 0; i < K; ++i) q[i] += dpp_move<0x141, 0xf>(q[i]);   // row_half_mirror
+#pragma unroll
+    for (int i = 0; i < K; ++i) q[i] += dpp_move<0x140, 0xf>(q[i]);   // row_mirror
+#pragma unroll
+    for (int i = 0; i < K; ++i) q[i] += dpp_move<0x142, 0xa>(q[i]);   // row_bcast15 into rows 1, 3
+#pragma unroll
+    for (int i = 0; i < K; ++i) q[i] += dpp_move<0x143, 0xc>(q[i]);   // row_bcast31 into rows 2, 3
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        q[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(q[i]), 63),
+                                __builtin_amdgcn_readlane(__double2loint(q[i]), 63));
 }
+
+__device__ __forceinline__ void wave_sum2(double& u, double& v)
+{
+    double q[2] = {u, v};
+    wave_sums<2>(q);
+    u = q[0];
+    v = q[1];
+}
+
+__device__ __forceinline__ void wave_sum4(double* q) { wave_sums<4>(q); }
 
 static_assert(kChainTile == 2 * kWaves, "each wave owns two walks of the tile");
 
