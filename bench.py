@@ -34,10 +34,10 @@ MFMA_PER_FLOP = {"fp32": 1, "bf16x3": 3, "fp64": 1}   # matrix-core products per
 # for a plain 256 MiB device copy in the same run.  Valid only for the kernel sources it
 # was measured on: reported as null once any of them differs.
 TRAFFIC = {
-    "precision": "fp32", "steps_per_launch": 500,
-    "sources_sha256": "7b180db60e0bec0682662c90375c9a8d560ef6db2e06ed972bafda5b05ad9ca4",
-    "fetch_kib": 25086.78125, "fetch_scale": 262144.0 / 131095.1875,
-    "write_kib": 45848.0, "write_scale": 262144.0 / 262144.0,
+    "precision": "bf16x3", "steps_per_launch": 500,
+    "sources_sha256": "66152bcc5612981b2712a440e2c63c0fa799aee28bc2e9574cf37a1434006b0e",
+    "fetch_kib": 25584.9375, "fetch_scale": 262144.0 / 131094.0625,
+    "write_kib": 45336.0, "write_scale": 262144.0 / 262144.0,
 }
 
 
