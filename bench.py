@@ -41,8 +41,8 @@ TRAFFIC = {
 }
 
 
-KERNEL_PATHS = {1: "general", 2: "resident", 3: "tiled"}
-KERNEL_NAMES = {1: "mhar_steps_kernel", 2: "resident_kernel", 3: "tiled_screen_kernel"}
+KERNEL_PATHS = {1: "general", 2: "resident", 3: "tiled", 4: "lane"}
+KERNEL_NAMES = {1: "mhar_steps_kernel", 2: "resident_kernel", 3: "tiled_screen_kernel", 4: "lane_kernel"}
 
 
 # the files that define the timed (register-resident) kernel and how it is built

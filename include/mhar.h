@@ -95,8 +95,14 @@ typedef enum {
     MHAR_PATH_GENERAL = 1,   /* one workgroup per 16 walks over all rows, slack in HBM */
     MHAR_PATH_RESIDENT = 2,  /* slack in registers, rows split over co-resident workgroups;
                                 FP32/BF16X3, n <= 256, m <= 8192 (else MHAR_E_UNSUPPORTED) */
-    MHAR_PATH_TILED = 3      /* per step a screening GEMM over 256-row x 128-walk tiles and a
+    MHAR_PATH_TILED = 3,     /* per step a screening GEMM over 256-row x 128-walk tiles and a
                                 chords kernel; FP32/BF16X3 (else MHAR_E_UNSUPPORTED) */
+    MHAR_PATH_LANE = 4       /* one walk per lane, every row evaluated exactly in FP64 each
+                                step (no screening product, so any precision); n <= 32 (else
+                                MHAR_E_UNSUPPORTED).  With a learned covariance attached the
+                                handle steps on the general kernel.  AUTO takes it for
+                                n <= 16, m n <= 512 and enough walks that it
+                                beats the screened kernels' step latency. */
 } mhar_path_t;
 
 typedef struct {
@@ -115,9 +121,11 @@ typedef struct mhar_batch* mhar_batch_t;
 typedef struct {
     uint64_t steps;             /* steps taken by every walk */
     uint64_t chain_steps;       /* walks x steps */
-    uint64_t exact_rows;        /* rows evaluated exactly in FP64 (candidates of the screening) */
+    uint64_t exact_rows;        /* rows evaluated exactly in FP64 (candidates of the screening;
+                                   every row on the lane path) */
     uint64_t recomputes;        /* exact slack recomputes */
-    int32_t kernel;             /* mhar_path_t of the last step: MHAR_PATH_GENERAL, _RESIDENT or _TILED */
+    int32_t kernel;             /* mhar_path_t of the last step: MHAR_PATH_GENERAL, _RESIDENT,
+                                   _TILED or _LANE */
     int32_t split;              /* workgroups per 16-walk tile (resident kernel), else 1 */
 } mhar_stats_t;
 

@@ -25,6 +25,7 @@ DEFAULT_CANDIDATES = (
      for p in ("fp32", "bf16x3") for r in (25, 50, 100)]
     + [{"precision": p, "recompute_every": 50, "steps_per_launch": 0, "path": path}
        for p in ("fp32", "bf16x3") for path in ("tiled", "general")]
+    + [{"precision": "fp64", "recompute_every": 50, "steps_per_launch": 0, "path": "lane"}]
 )
 
 

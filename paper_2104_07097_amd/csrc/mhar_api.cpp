@@ -14,6 +14,12 @@
 
 using namespace mhar;
 
+namespace mhar {
+// one walk per lane, every row exact (mhar_lane.hip)
+bool lane_fits(int n);
+hipError_t launch_lane(const StepArgs& a, hipStream_t stream);
+}  // namespace mhar
+
 struct mhar_problem {
     int n, m, m_pad, lda, m_eq, prec, R, steps_per_launch, path;
     float eps_g, u_s;
@@ -30,6 +36,9 @@ struct mhar_chains {
     int z, z_pad;
     int split;  // > 0: register-resident kernel with this many workgroups per walk tile
     int tiled;  // 1: tiled path (screening GEMM + chords kernel per step)
+    int lane;   // 1: one walk per lane, every row exact (isotropic directions only)
+    int slack_stale;  // the lane path ran since the last slack recompute
+    int last_kernel;  // mhar_path_t of the last launch
     uint64_t seed;
     uint32_t chain_offset;
     uint64_t step;
@@ -128,7 +137,7 @@ mhar_status_t check_options(const mhar_options_t* opt, mhar_options_t* out)
         return fail(MHAR_E_INVALID_ARG, "options.recompute_every must be <= 100000");
     if (opt->steps_per_launch < 0)
         return fail(MHAR_E_INVALID_ARG, "options.steps_per_launch must be >= 0");
-    if (opt->path < MHAR_PATH_AUTO || opt->path > MHAR_PATH_TILED)
+    if (opt->path < MHAR_PATH_AUTO || opt->path > MHAR_PATH_LANE)
         return fail(MHAR_E_INVALID_ARG, "options.path must be a mhar_path_t value");
     if (opt->path == MHAR_PATH_TILED && opt->precision == MHAR_FP64)
         return fail(MHAR_E_UNSUPPORTED, "the tiled path screens in FP32 or BF16X3 only");
@@ -305,8 +314,37 @@ int64_t auto_chunk(const mhar_problem* p)
     return std::min<int64_t>(std::max<int64_t>(chunk, 1), 100000);
 }
 
-hipError_t launch_any(const mhar_chains* c, const StepArgs& a, hipStream_t stream)
+// AUTO takes the lane path where its step takes less time than a screened
+// kernel's.  Step-time models fitted to measurements on one MI355X
+// (hypercube and simplex rows of the paper's Table 5, cube n = 10):
+//   lane:    about 3 + 0.08 m n us, whatever z up to ~10^5 walks (one wave
+//            per 64 walks, each latency-bound);
+//   general: about 19 us up to ~4096 walks, then growing with z as the
+//            16-walk workgroups queue for the CUs.
+// At 10^4 walks the lane path is 6-13x faster for n = 3..5, 1.2-2x for
+// n = 15 and slower from n = 25; at 16 walks and n = 10 it is 10 % slower.
+constexpr int kLaneAutoN = 16;
+constexpr int64_t kLaneAutoWork = 512;   // m n
+
+bool lane_preferred(const mhar_problem* p, int z_pad)
 {
+    if (!lane_fits(p->n) || p->n > kLaneAutoN) return false;
+    const int64_t work = (int64_t)p->m * p->n;
+    if (work > kLaneAutoWork) return false;
+    const double lane_us = 3.0 + 0.08 * (double)work;
+    const double general_us = 19.0 * std::max(1.0, (double)z_pad / 4096.0);
+    return lane_us < 0.9 * general_us;
+}
+
+hipError_t launch_any(mhar_chains* c, const StepArgs& a, hipStream_t stream)
+{
+    if (c->lane && c->pc_rank == 0) {
+        // the slack the other paths keep is not updated: they recompute it first
+        c->slack_stale = 1;
+        c->last_kernel = MHAR_PATH_LANE;
+        return launch_lane(a, stream);
+    }
+    c->last_kernel = c->tiled ? MHAR_PATH_TILED : c->split > 0 ? MHAR_PATH_RESIDENT : MHAR_PATH_GENERAL;
     if (c->tiled) return launch_tiled(c->p->prec, a, stream);
     if (c->split <= 0) return launch_steps(c->p->prec, a, stream);
     if (c->split > 1) {
@@ -332,6 +370,10 @@ mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, doub
     if (c->force_recompute) {
         recompute_first = 1;
         c->force_recompute = 0;
+    }
+    if (c->slack_stale && !(c->lane && c->pc_rank == 0)) {
+        recompute_first = 1;
+        c->slack_stale = 0;
     }
     if (recompute_first) {
         StepArgs a = make_args(c);
@@ -532,13 +574,18 @@ mhar_status_t mhar_chains_create(mhar_problem_t p, int64_t z, const double* X0, 
     const int rs = resident_split(p->prec, p->lda, p->m_pad, z_pad);
     c->split = 0;
     c->tiled = 0;
-    if (p->path == MHAR_PATH_RESIDENT) {
+    c->lane = 0;
+    if (p->path == MHAR_PATH_LANE) {
+        if (!lane_fits(p->n)) return cleanup(fail(MHAR_E_UNSUPPORTED, "the lane path needs n <= 32"));
+        c->lane = 1;
+    } else if (p->path == MHAR_PATH_RESIDENT) {
         if (rs <= 0) return cleanup(fail(MHAR_E_UNSUPPORTED, "the resident path does not fit this shape"));
         c->split = rs;
     } else if (p->path == MHAR_PATH_TILED) {
         c->tiled = 1;
     } else if (p->path == MHAR_PATH_AUTO) {
-        if (rs > 0) c->split = rs;
+        if (lane_preferred(p, z_pad)) c->lane = 1;
+        else if (rs > 0) c->split = rs;
         else c->tiled = p->lda > kMaxN || use_tiled(p, z_pad);
     }
     hipError_t e = launch_fill_i32((int*)c->theta, (int64_t)z_pad * 2, 0, stream);
@@ -641,7 +688,10 @@ mhar_status_t mhar_get_stats(mhar_chains_t c, void* stream, mhar_stats_t* stats)
     stats->chain_steps = c->step * (uint64_t)c->z;
     stats->exact_rows = cnt[0];
     stats->recomputes = c->recomputes;
-    stats->kernel = c->tiled ? MHAR_PATH_TILED : c->split > 0 ? MHAR_PATH_RESIDENT : MHAR_PATH_GENERAL;
+    stats->kernel = c->last_kernel ? c->last_kernel
+                                   : c->lane ? MHAR_PATH_LANE
+                                   : c->tiled ? MHAR_PATH_TILED
+                                   : c->split > 0 ? MHAR_PATH_RESIDENT : MHAR_PATH_GENERAL;
     stats->split = c->split > 0 ? c->split : 1;
     return MHAR_OK;
 }
@@ -888,13 +938,19 @@ mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return cleanup(hip_fail(e, "device query"));
     b->grid = b->nunits ? std::min(b->nunits, cus * batch_blocks_per_cu(b->prec, b->max_lda)) : 0;
-    // resident handles switch to the tiled path or the general kernel
+    // resident handles switch to the tiled path or the general kernel; lane
+    // handles step on the general kernel, whose slack they have not kept
     for (mhar_chains* c : b->chains) {
+        if (c->slack_stale) {
+            c->force_recompute = 1;
+            c->slack_stale = 0;
+        }
         if (c->split > 0) {
             c->tiled = tiled_in_batch(c) ? 1 : 0;
             c->split = 0;
             c->force_recompute = 1;
         }
+        c->last_kernel = c->tiled ? MHAR_PATH_TILED : MHAR_PATH_GENERAL;   // the path inside the batch
     }
     *out = b;
     return MHAR_OK;
@@ -962,6 +1018,7 @@ mhar_status_t mhar_batch_destroy(mhar_batch_t b)
     if (b->copy_pending) hipEventSynchronize(b->copied);
     for (int i = 0; i < b->count; ++i) {
         mhar_chains* c = b->chains[i];
+        c->last_kernel = 0;   // the handle's own path again
         if (b->saved_split[i] > 0 && c->pc_rank == 0) {
             c->split = b->saved_split[i];
             c->tiled = b->saved_tiled[i];

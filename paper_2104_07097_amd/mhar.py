@@ -141,7 +141,7 @@ def _make_module_functions():
 globals().update(_make_module_functions())
 
 
-PATHS = {"auto": 0, "general": 1, "resident": 2, "tiled": 3}
+PATHS = {"auto": 0, "general": 1, "resident": 2, "tiled": 3, "lane": 4}
 
 
 def options(precision="fp32", recompute_every=50, steps_per_launch=0, path="auto") -> Options:

@@ -74,9 +74,10 @@ def test_create_rejects_null_and_misaligned():
     assert lib.mhar_chains_destroy(None) == mhar.OK
 
 
-@pytest.mark.parametrize("prec,path,code", [("fp32", 4, mhar.E_INVALID_ARG), ("fp32", -1, mhar.E_INVALID_ARG),
+@pytest.mark.parametrize("prec,path,code", [("fp32", 5, mhar.E_INVALID_ARG), ("fp32", -1, mhar.E_INVALID_ARG),
                                             ("fp64", "tiled", mhar.E_UNSUPPORTED),
-                                            ("bf16x3", "tiled", mhar.OK), ("fp64", "general", mhar.OK)])
+                                            ("bf16x3", "tiled", mhar.OK), ("fp64", "general", mhar.OK),
+                                            ("fp64", "lane", mhar.OK), ("bf16x3", "lane", mhar.OK)])
 def test_path_option_checked(prec, path, code):
     lib = mhar.load()
     o = mhar.options(prec, path=path)

@@ -129,7 +129,7 @@ def test_largest_n():
         assert gu.rel_err(got, want) <= 1e-9, prec
 
 
-@pytest.mark.parametrize("path", ["auto", "general", "tiled"])
+@pytest.mark.parametrize("path", ["auto", "general", "tiled", "lane"])
 def test_nan_inputs_rejected(path):
     """A NaN in A, b or a start point makes that walk's start slack NaN, which
     the interior check rejects on every kernel path."""

@@ -1,0 +1,118 @@
+"""The lane path (one walk per lane, every row evaluated exactly each step)
+against the general kernel and the oracle.
+
+It draws the same directions (the projection's A_eq h summed in the order of
+the other paths' wave reduction) and evaluates every row with the same
+sequential FP64 formula the other paths use for their candidate rows, so
+its trajectories must be bitwise those of the general kernel.  Shapes cover
+each register template (n <= 8, 16, 32), equality constraints, and walk
+counts that leave a partial last wave."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import Oracle
+from paper_2104_07097_amd import instances as inst
+from paper_2104_07097_amd import mhar
+
+from . import gpu_util as gu
+
+pytestmark = pytest.mark.gpu
+
+
+def cases():
+    rng = np.random.default_rng(77)
+    cube_start = rng.uniform(-0.5, 0.5, size=(70, 15))
+    return {
+        "cube3": inst.hypercube(3, 70),
+        "cube15": inst.hypercube(15, 70, cube_start),
+        "simplex5": inst.simplex(5, 70),
+        "simplex15": inst.simplex(15, 130),
+        "randpoly20": inst.randpoly(n=20, m=45, z=70, seed=71),
+        "simplex_cut30": inst.simplex_cut(n=30, m_extra=12, m_eq_extra=2, z=70, seed=72),
+    }
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return Oracle()
+
+
+@pytest.mark.parametrize("case", list(cases()))
+def test_lane_equals_general_bitwise(case):
+    p = cases()[case]
+    gu.announce("lane vs general", case)
+    _, a = gu.make(p, "fp64", recompute_every=9, path="lane")
+    _, b = gu.make(p, "fp64", recompute_every=9, path="general")
+    for k in (1, 12, 40):
+        a.step(k)
+        b.step(k)
+    Xa, sa = gu.state(a)
+    Xb, sb = gu.state(b)
+    assert a.stats()["kernel"] == 4 and b.stats()["kernel"] == 1
+    assert not sa.any() and not sb.any()
+    assert np.array_equal(Xa, Xb)
+    ra = a.record(20, 3, 16).cpu().numpy()
+    rb = b.record(20, 3, 16).cpu().numpy()
+    assert np.array_equal(ra, rb)
+    assert gu.feasible(p, Xa)
+
+
+@pytest.mark.parametrize("case", ["cube15", "simplex15", "simplex_cut30"])
+def test_lane_short_horizon_parity(orc, case):
+    p = cases()[case]
+    P = gu.oracle_projection(orc, p)
+    gu.announce("lane 30-step", case)
+    _, ch = gu.make(p, "fp32", path="lane")
+    ch.step(30)
+    got, gst = gu.state(ch)
+    want, st, _ = orc.run(p.A, p.b, p.X0, 30, seed=0, P=P)
+    err = gu.rel_err(got, want)
+    print(f"  rel err after 30 steps {err:.2e}", flush=True)
+    assert not gst.any() and not st.any()
+    assert err <= 1e-8, (case, err)
+
+
+def test_lane_stats_and_auto_choice():
+    p = cases()["cube3"]
+    gu.announce("lane stats")
+    _, ch = gu.make(p, "fp32")            # AUTO: n = 3, m = 6 takes the lane path
+    ch.step(25)
+    s = ch.stats()
+    assert s["kernel"] == 4
+    assert s["exact_rows"] == 6 * 70 * 25
+    big = inst.randpoly(n=40, m=300, z=20, seed=73)
+    _, ch2 = gu.make(big, "fp32")         # n > 32: not the lane path
+    ch2.step(2)
+    assert ch2.stats()["kernel"] != 4
+
+
+def test_lane_rejects_large_n():
+    p = inst.randpoly(n=33, m=80, z=4, seed=74)
+    gu.announce("lane n=33")
+    with pytest.raises(mhar.MharError) as ei:
+        gu.make(p, "fp32", path="lane")
+    assert ei.value.code == mhar.E_UNSUPPORTED
+
+
+def test_lane_handle_in_batch_and_after():
+    """A lane handle stepped inside a batch (general kernel, whose slack it
+    must first recompute) and then alone again follows the trajectory of a
+    handle that only ever ran the general kernel."""
+    p = cases()["simplex15"]
+    gu.announce("lane handle in a batch")
+    _, a = gu.make(p, "fp32", path="lane")
+    _, b = gu.make(p, "fp32", path="general")
+    a.step(7)
+    b.step(7)
+    bat = mhar.Batch([a])
+    bat.step(11)
+    bat.close()
+    b.step(11)
+    a.step(5)
+    b.step(5)
+    Xa, sa = gu.state(a)
+    Xb, sb = gu.state(b)
+    assert not sa.any() and not sb.any()
+    assert np.array_equal(Xa, Xb)
+    assert a.stats()["kernel"] == 4
