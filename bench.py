@@ -35,8 +35,8 @@ MFMA_PER_FLOP = {"fp32": 1, "bf16x3": 3, "fp64": 1}   # matrix-core products per
 # was measured on: reported as null once any of them differs.
 TRAFFIC = {
     "precision": "bf16x3", "steps_per_launch": 500,
-    "sources_sha256": "66152bcc5612981b2712a440e2c63c0fa799aee28bc2e9574cf37a1434006b0e",
-    "fetch_kib": 25584.9375, "fetch_scale": 262144.0 / 131094.0625,
+    "sources_sha256": "f5e6d9700b0238a4c09ba5f1cea6bc82bd8a3c2b8443fd205e2a36bffc342d39",
+    "fetch_kib": 25434.28125, "fetch_scale": 262144.0 / 131094.5,
     "write_kib": 45336.0, "write_scale": 262144.0 / 262144.0,
 }
 
