@@ -97,12 +97,12 @@ typedef enum {
                                 FP32/BF16X3, n <= 256, m <= 8192 (else MHAR_E_UNSUPPORTED) */
     MHAR_PATH_TILED = 3,     /* per step a screening GEMM over 256-row x 128-walk tiles and a
                                 chords kernel; FP32/BF16X3 (else MHAR_E_UNSUPPORTED) */
-    MHAR_PATH_LANE = 4       /* one walk per lane, every row evaluated exactly in FP64 each
+    MHAR_PATH_LANE = 4       /* a few lanes per walk, every row evaluated exactly in FP64 each
                                 step (no screening product, so any precision); n <= 32 (else
                                 MHAR_E_UNSUPPORTED).  With a learned covariance attached the
                                 handle steps on the general kernel.  AUTO takes it for
-                                n <= 16, m n <= 512 and enough walks that it
-                                beats the screened kernels' step latency. */
+                                n <= 32 where its modelled step time (about
+                                2.5 + 0.013 m n us) beats the screened kernels'. */
 } mhar_path_t;
 
 typedef struct {

@@ -316,23 +316,21 @@ int64_t auto_chunk(const mhar_problem* p)
 
 // AUTO takes the lane path where its step takes less time than a screened
 // kernel's.  Step-time models fitted to measurements on one MI355X
-// (hypercube and simplex rows of the paper's Table 5, cube n = 10):
-//   lane:    about 3 + 0.08 m n us, whatever z up to ~10^5 walks (one wave
-//            per 64 walks, each latency-bound);
-//   general: about 19 us up to ~4096 walks, then growing with z as the
+// (hypercube and simplex rows of the paper's Table 5 with n <= 32, cube
+// n = 10 with 16 and 256 walks):
+//   lane:    about 2.5 + 0.013 m n us while z times its lanes per walk stays
+//            below ~10^5 (each group of lanes is latency-bound);
+//   general: about 16 us up to ~2048 walks, then growing with z as the
 //            16-walk workgroups queue for the CUs.
-// At 10^4 walks the lane path is 6-13x faster for n = 3..5, 1.2-2x for
-// n = 15 and slower from n = 25; at 16 walks and n = 10 it is 10 % slower.
-constexpr int kLaneAutoN = 16;
-constexpr int64_t kLaneAutoWork = 512;   // m n
-
+// Measured: 12-17x the general kernel at n = 3..5 and 10^4 walks, 5-6x at
+// n = 15, 1.5-2x at n = 25, 3x for n = 10 with 16 walks; the general kernel
+// wins for the cube at n = 32 with 2500 walks.
 bool lane_preferred(const mhar_problem* p, int z_pad)
 {
-    if (!lane_fits(p->n) || p->n > kLaneAutoN) return false;
-    const int64_t work = (int64_t)p->m * p->n;
-    if (work > kLaneAutoWork) return false;
-    const double lane_us = 3.0 + 0.08 * (double)work;
-    const double general_us = 19.0 * std::max(1.0, (double)z_pad / 4096.0);
+    if (!lane_fits(p->n)) return false;
+    const double work = (double)p->m * p->n;
+    const double lane_us = 2.5 + 0.013 * work;
+    const double general_us = 16.0 * std::max(1.0, (double)z_pad / 2048.0);
     return lane_us < 0.9 * general_us;
 }
 

@@ -2,14 +2,16 @@
 // small problems (n <= 32) on gfx950.
 //
 // Same method as the other kernels (paper Alg. 2, S4.3-S4.5), without the
-// screening product: each lane holds the state x and direction d of its own
-// walk in registers and evaluates the line-set formula of S4.4 for every
-// row in FP64, s_i = b_i - a_i x and g_i = a_i d as sequential sums (the
-// order of the other paths' exact rows), then theta and the update.  For
-// small m n this costs less than the product tile, the screening and the
-// workgroup barriers it replaces.  A and the equality data are read at
-// wave-uniform addresses (scalar loads); the walks are independent, so
-// there is no barrier and no LDS.
+// screening product: a group of G lanes (1 to 8) holds the state x and
+// direction d of one walk in registers and evaluates the line-set formula
+// of S4.4 for every row in FP64, s_i = b_i - a_i x and g_i = a_i d as
+// sequential sums (the order of the other paths' exact rows), then theta
+// and the update.  Lane q of a group draws the Box-Muller pairs p = q (mod G)
+// and evaluates the rows i = q (mod G); the draws are gathered and the chord
+// ends combined (an exact minimum, so in any order) by lane swizzles within
+// the group.  For small m n this costs less than the product tile, the
+// screening and the workgroup barriers it replaces; the walks are
+// independent, so there is no barrier and no LDS.
 //
 // The directions are bitwise those of the other paths: the draws come from
 // the same counter streams, and A_eq h is summed in the order of their
@@ -27,12 +29,72 @@ namespace {
 constexpr int kLaneThreads = 64;
 constexpr int kLaneMaxN = 32;   // x and d of a walk in registers
 
-template <int NM>   // compile-time bound on n (power of two, <= 32)
+// Lane moves within 32-lane halves by ds_swizzle in bit mode: lane i reads
+// lane ((i & and_mask) | or_mask) ^ xor_mask.
+constexpr int swz_pattern(int and_mask, int or_mask, int xor_mask)
+{
+    return (and_mask & 31) | ((or_mask & 31) << 5) | ((xor_mask & 31) << 10);
+}
+
+template <int PAT>
+__device__ __forceinline__ double swz(double v)
+{
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), PAT);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), PAT);
+    return __hiloint2double(hi, lo);
+}
+
+template <int PAT>
+__device__ __forceinline__ unsigned long long swz_u64(unsigned long long v)
+{
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)v, PAT);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(v >> 32), PAT);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+
+// value v of lane OWNER of this lane's group of G
+template <int G, int OWNER>
+__device__ __forceinline__ double group_bcast(double v)
+{
+    if constexpr (G == 1) return v;
+    else return swz<swz_pattern(31 & ~(G - 1), OWNER, 0)>(v);
+}
+
+// minimum (as unsigned) and OR over the lanes of a group of G
+template <int G>
+__device__ __forceinline__ void group_min_or(unsigned long long& a, unsigned long long& b, int& f)
+{
+    if constexpr (G > 1) {
+#pragma unroll
+        for (int s = 1; s < G; s <<= 1) {
+            // s is a compile-time constant after unrolling; the pattern is
+            // selected among the few group sizes
+            unsigned long long oa, ob;
+            int of;
+            if (s == 1) { oa = swz_u64<swz_pattern(31, 0, 1)>(a); ob = swz_u64<swz_pattern(31, 0, 1)>(b); of = __builtin_amdgcn_ds_swizzle(f, swz_pattern(31, 0, 1)); }
+            else if (s == 2) { oa = swz_u64<swz_pattern(31, 0, 2)>(a); ob = swz_u64<swz_pattern(31, 0, 2)>(b); of = __builtin_amdgcn_ds_swizzle(f, swz_pattern(31, 0, 2)); }
+            else { oa = swz_u64<swz_pattern(31, 0, 4)>(a); ob = swz_u64<swz_pattern(31, 0, 4)>(b); of = __builtin_amdgcn_ds_swizzle(f, swz_pattern(31, 0, 4)); }
+            a = oa < a ? oa : a;
+            b = ob < b ? ob : b;
+            f |= of;
+        }
+    }
+}
+
+// NM: compile-time bound on n (power of two, <= 32).  G: lanes per walk
+// (1, 2, 4 or 8); lane q of a walk's group draws the pairs p = q (mod G) and
+// evaluates the rows i = q (mod G); the draws are gathered within the group,
+// the chord ends combined by an exact minimum, and every lane of the group
+// then holds the same theta, direction and state.
+template <int NM, int G>
 __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
 {
     static_assert(NM <= 32 && (NM & (NM - 1)) == 0, "NM: power of two up to 32");
-    const int chain = blockIdx.x * kLaneThreads + threadIdx.x;
-    if (chain >= a.z) return;
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8, "G: 1, 2, 4 or 8 lanes per walk");
+    constexpr int PK = (NM / 2 + G - 1) / G;   // pairs drawn per lane
+    const int q = threadIdx.x & (G - 1);
+    const int chain = blockIdx.x * (kLaneThreads / G) + threadIdx.x / G;
+    if (chain >= a.z) return;   // whole groups leave together
     const int n = a.n, m = a.m, lda = a.lda;
     const double* __restrict__ A = a.A64;
     const double* __restrict__ b = a.b64;
@@ -43,10 +105,10 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
     int fl = 0;
     double theta = a.theta[chain];
 
-    // exact slack of every row at the launch's start and every R steps
-    // (where the other paths recompute it): start point strictly inside?
+    // exact slack of this lane's rows at the launch's start and every R
+    // steps (where the other paths recompute it): start point strictly inside?
     auto check_interior = [&]() __attribute__((always_inline)) {
-        for (int i = 0; i < m; ++i) {
+        for (int i = q; i < m; i += G) {
             const double* ar = A + (size_t)i * lda;
             const double bi = b[i];
             double s = bi;
@@ -63,19 +125,34 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
         const uint64_t step = a.step0 + (uint64_t)s;
         if (s > 0 && (a.since0 + s) % a.R == 0) check_interior();
 
-        // ---- directions: N(0, 1) pairs, then d = h - W (A_eq h) ----
-        double d[NM];
+        // ---- directions: N(0, 1) pairs (this lane's share), gathered ----
+        double2 hq[PK];
 #pragma unroll
-        for (int p = 0; p < NM / 2; ++p) {
-            d[2 * p] = 0.0;
-            d[2 * p + 1] = 0.0;
+        for (int k = 0; k < PK; ++k) {
+            const int p = q + G * k;
+            hq[k] = make_double2(0.0, 0.0);
             if (2 * p < n) {
                 Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step, (uint32_t)p);
-                double ev, od;
-                gauss_pair(w, ev, od);
-                d[2 * p] = ev;
-                if (2 * p + 1 < n) d[2 * p + 1] = od;
+                gauss_pair(w, hq[k].x, hq[k].y);
             }
+        }
+        double d[NM];
+#pragma unroll
+        for (int j = 0; j < NM; ++j) {
+            const int p = j >> 1;
+            const double v = (j & 1) ? hq[p / G].y : hq[p / G].x;
+            double g;
+            switch (p % G) {   // compile-time after unrolling
+            case 0: g = group_bcast<G, 0>(v); break;
+            case 1: g = group_bcast<G, (G > 1 ? 1 : 0)>(v); break;
+            case 2: g = group_bcast<G, (G > 2 ? 2 : 0)>(v); break;
+            case 3: g = group_bcast<G, (G > 3 ? 3 : 0)>(v); break;
+            case 4: g = group_bcast<G, (G > 4 ? 4 : 0)>(v); break;
+            case 5: g = group_bcast<G, (G > 5 ? 5 : 0)>(v); break;
+            case 6: g = group_bcast<G, (G > 6 ? 6 : 0)>(v); break;
+            default: g = group_bcast<G, (G > 7 ? 7 : 0)>(v); break;
+            }
+            d[j] = j < n ? g : 0.0;
         }
         if (a.m_eq > 0) {
             // y_p = A_eq h: one product per coordinate (an FMA onto +0, as a
@@ -102,12 +179,10 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
             }
         }
 
-        // ---- chord: every row exactly (S4.4, Lemma 4.2) ----
+        // ---- chord: every row exactly (S4.4, Lemma 4.2), rows split over the group ----
         unsigned long long lmax_b = (unsigned long long)__double_as_longlong(kInfD);
         unsigned long long nlmin_b = lmax_b;
-        // rows are independent: unrolled so that their dependent chains overlap
-#pragma unroll 4
-        for (int i = 0; i < m; ++i) {
+        for (int i = q; i < m; i += G) {
             const double* ar = A + (size_t)i * lda;
             const double bi = b[i];
             double sx = bi, gx = 0.0;
@@ -122,15 +197,18 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
             if (sx < 0.0) sx = 0.0;
             // chord ends compared as ordered bits (both >= 0; NaN never wins)
             if (gx > 0.0) {
-                const unsigned long long q = (unsigned long long)__double_as_longlong(sx / gx);
-                lmax_b = q < lmax_b ? q : lmax_b;
+                const unsigned long long c = (unsigned long long)__double_as_longlong(sx / gx);
+                lmax_b = c < lmax_b ? c : lmax_b;
             } else if (gx < 0.0) {
-                const unsigned long long q = (unsigned long long)__double_as_longlong(sx / -gx);
-                nlmin_b = q < nlmin_b ? q : nlmin_b;
+                const unsigned long long c = (unsigned long long)__double_as_longlong(sx / -gx);
+                nlmin_b = c < nlmin_b ? c : nlmin_b;
             }
         }
+        int fl_any = fl;
+        group_min_or<G>(lmax_b, nlmin_b, fl_any);
+        fl = fl_any;
 
-        // ---- theta and the update (S4.5, Lemma 4.3) ----
+        // ---- theta and the update (S4.5, Lemma 4.3), the same in every lane of the group ----
         const double lmax = __longlong_as_double((long long)lmax_b);
         const double lmin = -__longlong_as_double((long long)nlmin_b);
         double th = 0.0;
@@ -153,7 +231,7 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
             }
         }
         if (!finite) fl |= kNonFinite;
-        if (a.rec_stride > 0 && chain < a.rec_chains) {
+        if (q == 0 && a.rec_stride > 0 && chain < a.rec_chains) {
             const int64_t rs = a.rec_s_base + s + 1;
             if (rs % a.rec_stride == 0) {
                 double* rp = a.rec_out + ((size_t)(rs / a.rec_stride - 1) * a.rec_chains + chain) * n;
@@ -164,29 +242,55 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
         }
     }
 
+    // flags of the interior checks after the last step are combined too
+    unsigned long long u0 = 0, u1 = 0;
+    group_min_or<G>(u0, u1, fl);
+    // exact rows, one atomic per wave (lane 0 is live whenever any lane is)
+    const unsigned long long walks = __popcll(__ballot(q == 0));
+    if (threadIdx.x == 0 && a.steps > 0)
+        atomicAdd(&a.counters[0], walks * (unsigned long long)m * (unsigned long long)a.steps);
+    if (q != 0) return;
 #pragma unroll
     for (int j = 0; j < NM; ++j)
         if (j < n) a.X[(size_t)chain * lda + j] = x[j];
     a.theta[chain] = theta;
     if (fl) atomicOr(&a.flags[chain], fl);
-    // exact rows, one atomic per wave (lane 0 is live whenever any lane is)
-    const unsigned long long live = __popcll(__ballot(1));
-    if (threadIdx.x == 0 && a.steps > 0)
-        atomicAdd(&a.counters[0], live * (unsigned long long)m * (unsigned long long)a.steps);
 }
 
 }  // namespace
 
 bool lane_fits(int n) { return n >= 1 && n <= kLaneMaxN; }
 
+template <int G>
+hipError_t launch_lane_g(const StepArgs& a, hipStream_t stream)
+{
+    const dim3 grid((unsigned)(((int64_t)a.z * G + kLaneThreads - 1) / kLaneThreads)), block(kLaneThreads);
+    if (a.n <= 8) hipLaunchKernelGGL((lane_kernel<8, G>), grid, block, 0, stream, a);
+    else if (a.n <= 16) hipLaunchKernelGGL((lane_kernel<16, G>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL((lane_kernel<32, G>), grid, block, 0, stream, a);
+    return hipGetLastError();
+}
+
+// Lanes per walk, from timings on one MI355X (hypercube and simplex, 16 to
+// 10^4 walks): 4 for n <= 8; 8 up to n = 16 (the draws dominate); above, 8
+// without equalities and 4 with them, whose projection every lane of the
+// group repeats.
+int lane_group(const StepArgs& a)
+{
+    if (a.n <= 8) return 4;
+    if (a.n <= 16) return 8;
+    return a.m_eq > 0 ? 4 : 8;
+}
+
 hipError_t launch_lane(const StepArgs& a, hipStream_t stream)
 {
     if (!lane_fits(a.n) || a.r > 0 || a.m_eq > kMaxMeq) return hipErrorInvalidValue;
-    const dim3 grid((a.z + kLaneThreads - 1) / kLaneThreads), block(kLaneThreads);
-    if (a.n <= 8) hipLaunchKernelGGL(lane_kernel<8>, grid, block, 0, stream, a);
-    else if (a.n <= 16) hipLaunchKernelGGL(lane_kernel<16>, grid, block, 0, stream, a);
-    else hipLaunchKernelGGL(lane_kernel<32>, grid, block, 0, stream, a);
-    return hipGetLastError();
+    switch (lane_group(a)) {
+    case 1: return launch_lane_g<1>(a, stream);
+    case 2: return launch_lane_g<2>(a, stream);
+    case 4: return launch_lane_g<4>(a, stream);
+    default: return launch_lane_g<8>(a, stream);
+    }
 }
 
 }  // namespace mhar
