@@ -285,12 +285,7 @@ int lane_group(const StepArgs& a)
 hipError_t launch_lane(const StepArgs& a, hipStream_t stream)
 {
     if (!lane_fits(a.n) || a.r > 0 || a.m_eq > kMaxMeq) return hipErrorInvalidValue;
-    switch (lane_group(a)) {
-    case 1: return launch_lane_g<1>(a, stream);
-    case 2: return launch_lane_g<2>(a, stream);
-    case 4: return launch_lane_g<4>(a, stream);
-    default: return launch_lane_g<8>(a, stream);
-    }
+    return lane_group(a) == 4 ? launch_lane_g<4>(a, stream) : launch_lane_g<8>(a, stream);
 }
 
 }  // namespace mhar

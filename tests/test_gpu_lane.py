@@ -1,12 +1,14 @@
-"""The lane path (one walk per lane, every row evaluated exactly each step)
-against the general kernel and the oracle.
+"""The lane path (a group of lanes per walk, every row evaluated exactly
+each step) against the general kernel and the oracle.
 
 It draws the same directions (the projection's A_eq h summed in the order of
 the other paths' wave reduction) and evaluates every row with the same
-sequential FP64 formula the other paths use for their candidate rows, so
-its trajectories must be bitwise those of the general kernel.  Shapes cover
-each register template (n <= 8, 16, 32), equality constraints, and walk
-counts that leave a partial last wave."""
+sequential FP64 formula the other paths use for their candidate rows; the
+chord ends of a walk's lanes are combined by an exact minimum.  So its
+trajectories must be bitwise those of the general kernel.  Shapes cover each
+register template (n <= 8, 16, 32) and both group sizes (4 lanes per walk
+for n <= 8 and with equalities above 16, 8 otherwise), equality
+constraints, and walk counts that leave a partial last wave."""
 import numpy as np
 import pytest
 import torch
