@@ -289,6 +289,10 @@ mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void
 /* Enqueue `steps` steps of every handle in the batch. */
 mhar_status_t mhar_batch_step(mhar_batch_t batch, int64_t steps, void* stream);
 
+/* Release the batch; the handles return to their own kernel paths.  The
+ * batch is released even when the wait for its last descriptor copy or the
+ * release of its pinned buffer reports an error, which is then returned
+ * (MHAR_E_HIP). */
 mhar_status_t mhar_batch_destroy(mhar_batch_t batch);
 
 #ifdef __cplusplus

@@ -916,7 +916,7 @@ mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void
         b->saved_tiled.push_back(chains[i]->tiled);
     }
     auto cleanup = [&](mhar_status_t code) {
-        if (b->descs_host) hipHostFree(b->descs_host);
+        if (b->descs_host) (void)hipHostFree(b->descs_host);   // the first error is the one reported
         delete b;
         return code;
     };
@@ -1013,7 +1013,7 @@ mhar_status_t mhar_batch_step(mhar_batch_t b, int64_t steps, void* stream_)
 mhar_status_t mhar_batch_destroy(mhar_batch_t b)
 {
     if (!b) return MHAR_OK;
-    if (b->copy_pending) hipEventSynchronize(b->copied);
+    hipError_t e = b->copy_pending ? hipEventSynchronize(b->copied) : hipSuccess;
     for (int i = 0; i < b->count; ++i) {
         mhar_chains* c = b->chains[i];
         c->last_kernel = 0;   // the handle's own path again
@@ -1023,9 +1023,12 @@ mhar_status_t mhar_batch_destroy(mhar_batch_t b)
             c->force_recompute = 1;
         }
     }
-    hipEventDestroy(b->copied);
-    hipHostFree(b->descs_host);
+    hipError_t e2 = hipEventDestroy(b->copied);
+    if (e == hipSuccess) e = e2;
+    e2 = hipHostFree(b->descs_host);
+    if (e == hipSuccess) e = e2;
     delete b;
+    if (e != hipSuccess) return hip_fail(e, "batch teardown");
     return MHAR_OK;
 }
 
