@@ -208,32 +208,46 @@ def bench_simplex_cut(args):
 
 
 def bench_batched(args):
+    """The 256-problem batch in both screening precisions (each on its own
+    handles, one after the other); the faster one is the reported value."""
     import torch
     from paper_2104_07097_amd import instances as inst
     from paper_2104_07097_amd import mhar
     probs = inst.batched()
-    made = [_make(p, "fp32") for p in probs]
-    batch = mhar.Batch([ch for _, ch in made])
     steps = args.steps if args.steps != 5000 else 100
-    batch.step(min(args.warmup, 20))
+    z = sum(p.z for p in probs)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    batch.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3
-    z = sum(p.z for p in probs)
-    flags = 0
-    for _, ch in made:
-        flags |= ch.sync()
-    return _base_line(z * steps / sec, steps, min(args.warmup, 20), sec, "fp32",
+    variants, flags = {}, 0
+    for prec in ("fp32", "bf16x3"):
+        made = [_make(p, prec) for p in probs]
+        batch = mhar.Batch([ch for _, ch in made])
+        batch.step(min(args.warmup, 20))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        batch.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        for _, ch in made:
+            flags |= ch.sync()
+        variants[prec] = {"value": z * steps / sec, "ms_per_step": sec * 1e3 / steps}
+        batch.close()
+        for prob, ch in made:
+            ch.close()
+            prob.close()
+        del made, batch
+        torch.cuda.synchronize()
+    best = max(variants, key=lambda k: variants[k]["value"])
+    sec = variants[best]["ms_per_step"] * steps / 1e3
+    line = _base_line(z * steps / sec, steps, min(args.warmup, 20), sec, best,
                       {"workload": "256 Gaussian-halfspace polytopes, n log-uniform in [20,400], "
                                    "m=ceil(4 n^1.5), 256 walks each, one persistent launch per call",
                        "problems": len(probs), "z_total": z,
                        "sum_mn": int(sum(p.m * p.n for p in probs)), "flags": flags})
+    line["variants"] = variants
+    return line
 
 
 def bench_rotbox(args):
