@@ -118,3 +118,46 @@ def test_lane_handle_in_batch_and_after():
     assert not sa.any() and not sb.any()
     assert np.array_equal(Xa, Xb)
     assert a.stats()["kernel"] == 4
+
+
+def test_lane_handle_with_covariance_and_state_reset():
+    """A learned covariance on a lane handle moves it to the general kernel
+    (which first recomputes the slack the lane path does not keep); detached,
+    it returns to the lane path; a new state set on it is stepped like any
+    other.  At every stage the trajectory is bitwise that of a handle that
+    only ever ran the general kernel."""
+    p = cases()["randpoly20"]
+    dev = gu.device()
+    gu.announce("lane handle, covariance and state reset")
+    _, a = gu.make(p, "fp32", path="lane")
+    _, b = gu.make(p, "fp32", path="general")
+    for ch in (a, b):
+        ch.step(5)
+    rng = np.random.default_rng(3)
+    U = torch.tensor(0.05 * rng.standard_normal((p.A.shape[1], 2)), device=dev)
+    ls = torch.tensor(np.full(p.A.shape[1], np.log(0.9)), device=dev)
+    for ch in (a, b):
+        ch.precond_create(2)
+        ch.precond_set(U, ls)
+        ch.precond_freeze()
+        ch.step(9)
+    Xa, sa = gu.state(a)
+    Xb, sb = gu.state(b)
+    assert a.stats()["kernel"] == 1
+    assert not sa.any() and not sb.any()
+    assert np.array_equal(Xa, Xb)
+    for ch in (a, b):
+        ch.precond_destroy()
+        ch.step(6)
+    Xa, _ = gu.state(a)
+    Xb, _ = gu.state(b)
+    assert a.stats()["kernel"] == 4
+    assert np.array_equal(Xa, Xb)
+    X = torch.tensor(p.X0, device=dev)
+    for ch in (a, b):
+        ch.set_state(X, 100)
+        ch.step(4)
+    Xa, sa = gu.state(a)
+    Xb, sb = gu.state(b)
+    assert not sa.any() and not sb.any()
+    assert np.array_equal(Xa, Xb)
