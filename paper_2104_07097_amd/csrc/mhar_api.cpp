@@ -15,7 +15,7 @@
 using namespace mhar;
 
 namespace mhar {
-// one walk per lane, every row exact (mhar_lane.hip)
+// a few lanes per walk, every row exact (mhar_lane.hip)
 bool lane_fits(int n);
 hipError_t launch_lane(const StepArgs& a, hipStream_t stream);
 }  // namespace mhar
@@ -36,7 +36,7 @@ struct mhar_chains {
     int z, z_pad;
     int split;  // > 0: register-resident kernel with this many workgroups per walk tile
     int tiled;  // 1: tiled path (screening GEMM + chords kernel per step)
-    int lane;   // 1: one walk per lane, every row exact (isotropic directions only)
+    int lane;   // 1: lane path, every row exact (isotropic directions only)
     int slack_stale;  // the lane path ran since the last slack recompute
     int last_kernel;  // mhar_path_t of the last launch
     uint64_t seed;

@@ -1,4 +1,4 @@
-// mhar_lane.hip -- one walk per lane, every row exact: the MHAR step for
+// mhar_lane.hip -- a few lanes per walk, every row exact: the MHAR step for
 // small problems (n <= 32) on gfx950.
 //
 // Same method as the other kernels (paper Alg. 2, S4.3-S4.5), without the
