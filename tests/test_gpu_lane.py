@@ -31,6 +31,7 @@ def cases():
         "simplex5": inst.simplex(5, 70),
         "simplex15": inst.simplex(15, 130),
         "randpoly20": inst.randpoly(n=20, m=45, z=70, seed=71),
+        "cube32": inst.hypercube(32, 70),
         "simplex_cut30": inst.simplex_cut(n=30, m_extra=12, m_eq_extra=2, z=70, seed=72),
     }
 

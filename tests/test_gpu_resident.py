@@ -57,3 +57,24 @@ def test_resident_equals_general_with_equalities(prec):
     assert not sr.any() and not sg.any()
     assert np.array_equal(Xr, Xg)
     assert gu.feasible(p, Xr)
+
+
+def test_resident_at_its_largest_shape():
+    """n = 256 and m = 8192: the longest rows and the widest split (16
+    co-resident workgroups per walk tile) the resident kernel takes."""
+    p = inst.randpoly(n=256, m=8192, z=20, seed=130)
+    gu.announce("resident largest shape")
+    Xr, sr, stats = _run(p, "bf16x3", "resident", 12)
+    assert stats["kernel"] == 2 and stats["split"] == 16
+    Xg, sg, _ = _run(p, "bf16x3", "general", 12)
+    assert not sr.any() and not sg.any()
+    assert np.array_equal(Xr, Xg)
+
+
+def test_resident_rejects_more_rows():
+    from paper_2104_07097_amd import mhar
+    p = inst.randpoly(n=40, m=8193, z=4, seed=131)
+    gu.announce("resident m=8193")
+    with pytest.raises(mhar.MharError) as ei:
+        gu.make(p, "fp32", path="resident")
+    assert ei.value.code == mhar.E_UNSUPPORTED
