@@ -474,7 +474,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py measures one GPU only: this build has no multi-GPU path "
-            "(walks shard across GPUs with no communication; see DESIGN.md).")
+            "(walks shard across GPUs with no communication: each GPU takes a walk range "
+            "with chain_offset set to its first walk).")
         sys.exit(2)
 
     import numpy as np
