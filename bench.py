@@ -473,7 +473,7 @@ def main():
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        log("bench.py measures one GPU only: this build has no multi-GPU path "
+        log("bench.py measures one GPU only: the library has no multi-GPU path "
             "(walks shard across GPUs with no communication: each GPU takes a walk range "
             "with chain_offset set to its first walk).")
         sys.exit(2)
