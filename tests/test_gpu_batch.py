@@ -61,8 +61,8 @@ def test_batch_rejects_mixed_precision():
 
 def _mixed_problems():
     # the first runs the tiled path on its own, the next two the resident kernel
-    # (tiled inside a batch), the last two the resident kernel (general kernel
-    # inside a batch)
+    # (tiled inside a batch), the fourth the resident kernel and the last the
+    # lane path (both the general kernel inside a batch)
     return [inst.randpoly(n=300, m=1200, z=200, seed=51),
             inst.simplex_cut(n=150, m_extra=2000, m_eq_extra=3, z=150, seed=52),
             inst.rotbox(n=200, m_extra=1500, z=100, seed=53)[0],
