@@ -102,7 +102,8 @@ typedef enum {
                                 MHAR_E_UNSUPPORTED).  With a learned covariance attached the
                                 handle steps on the general kernel.  AUTO takes it for
                                 n <= 32 where its modelled step time (about
-                                2.5 + 0.013 m n us) beats the screened kernels'. */
+                                2.2 + 0.0065 m n + 0.4 n m_eq us) beats the
+                                screened kernels'. */
 } mhar_path_t;
 
 typedef struct {

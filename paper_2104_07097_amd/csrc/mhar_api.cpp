@@ -317,19 +317,19 @@ int64_t auto_chunk(const mhar_problem* p)
 // AUTO takes the lane path where its step takes less time than a screened
 // kernel's.  Step-time models fitted to measurements on one MI355X
 // (hypercube and simplex rows of the paper's Table 5 with n <= 32, cube
-// n = 10 with 16 and 256 walks):
-//   lane:    about 2.5 + 0.013 m n us while z times its lanes per walk stays
-//            below ~10^5 (each group of lanes is latency-bound);
+// n = 10 with 16 walks):
+//   lane:    about 2.2 + 0.0065 m n + 0.4 n m_eq us (every lane of a walk's
+//            group repeats the projection) while z times the lanes per walk
+//            stays below ~10^5;
 //   general: about 16 us up to ~2048 walks, then growing with z as the
 //            16-walk workgroups queue for the CUs.
-// Measured: 12-17x the general kernel at n = 3..5 and 10^4 walks, 5-6x at
-// n = 15, 1.5-2x at n = 25, 3x for n = 10 with 16 walks; the general kernel
-// wins for the cube at n = 32 with 2500 walks.
+// Measured: 15-20x the general kernel at n = 3..5 and 10^4 walks, 8x at
+// n = 15, 2.5-3x at n = 25, 4x for n = 10 with 16 walks; level with it for
+// the cube at n = 32 with 2500 walks.
 bool lane_preferred(const mhar_problem* p, int z_pad)
 {
     if (!lane_fits(p->n)) return false;
-    const double work = (double)p->m * p->n;
-    const double lane_us = 2.5 + 0.013 * work;
+    const double lane_us = 2.2 + 0.0065 * (double)p->m * p->n + 0.4 * (double)p->n * p->m_eq;
     const double general_us = 16.0 * std::max(1.0, (double)z_pad / 2048.0);
     return lane_us < 0.9 * general_us;
 }

@@ -10,8 +10,10 @@
 // and evaluates the rows i = q (mod G); the draws are gathered and the chord
 // ends combined (an exact minimum, so in any order) by lane swizzles within
 // the group.  For small m n this costs less than the product tile, the
-// screening and the workgroup barriers it replaces; the walks are
-// independent, so there is no barrier and no LDS.
+// screening and the workgroup barriers it replaces.  A and b are copied into
+// LDS once per launch when they fit (48 KB), since each lane of a group
+// reads a different row; the walks are independent, so that copy is the
+// only barrier.
 //
 // The directions are bitwise those of the other paths: the draws come from
 // the same counter streams, and A_eq h is summed in the order of their
@@ -86,7 +88,7 @@ __device__ __forceinline__ void group_min_or(unsigned long long& a, unsigned lon
 // evaluates the rows i = q (mod G); the draws are gathered within the group,
 // the chord ends combined by an exact minimum, and every lane of the group
 // then holds the same theta, direction and state.
-template <int NM, int G>
+template <int NM, int G, bool STAGED>
 __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
 {
     static_assert(NM <= 32 && (NM & (NM - 1)) == 0, "NM: power of two up to 32");
@@ -94,14 +96,27 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
     constexpr int PK = (NM / 2 + G - 1) / G;   // pairs drawn per lane
     const int q = threadIdx.x & (G - 1);
     const int chain = blockIdx.x * (kLaneThreads / G) + threadIdx.x / G;
+    const int n = a.n, m = a.m;
+    // A and b staged in LDS when the launch provides room (rows padded by one
+    // double, so the lanes of a group, which read different rows, hit
+    // different banks); otherwise read from global memory
+    extern __shared__ double lane_lds[];
+    const int lda = STAGED ? NM + 1 : a.lda;
+    const double* __restrict__ A = STAGED ? lane_lds : a.A64;
+    const double* __restrict__ b = STAGED ? lane_lds + (size_t)m * (NM + 1) : a.b64;
+    if (STAGED) {
+        for (int e = threadIdx.x; e < m * (NM + 1); e += kLaneThreads) {
+            const int i = e / (NM + 1), j = e - i * (NM + 1);
+            lane_lds[e] = j < n ? a.A64[(size_t)i * a.lda + j] : 0.0;
+        }
+        for (int i = threadIdx.x; i < m; i += kLaneThreads) lane_lds[(size_t)m * (NM + 1) + i] = a.b64[i];
+        __syncthreads();
+    }
     if (chain >= a.z) return;   // whole groups leave together
-    const int n = a.n, m = a.m, lda = a.lda;
-    const double* __restrict__ A = a.A64;
-    const double* __restrict__ b = a.b64;
 
     double x[NM];
 #pragma unroll
-    for (int j = 0; j < NM; ++j) x[j] = j < n ? a.X[(size_t)chain * lda + j] : 0.0;
+    for (int j = 0; j < NM; ++j) x[j] = j < n ? a.X[(size_t)chain * a.lda + j] : 0.0;
     int fl = 0;
     double theta = a.theta[chain];
 
@@ -163,7 +178,7 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
 #pragma unroll
             for (int j = 0; j < NM; ++j) h[j] = d[j];
             for (int p = 0; p < a.m_eq; ++p) {
-                const double* er = a.Aeq + (size_t)p * lda;
+                const double* er = a.Aeq + (size_t)p * a.lda;
                 double t[NM];
 #pragma unroll
                 for (int j = 0; j < NM; ++j) t[j] = j < n ? fma(er[j], h[j], 0.0) : 0.0;
@@ -172,7 +187,7 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
 #pragma unroll
                     for (int j = 0; j < half; ++j) t[j] = t[j] + t[j + half];
                 const double y = t[0];
-                const double* wr = a.WT + (size_t)p * lda;
+                const double* wr = a.WT + (size_t)p * a.lda;
 #pragma unroll
                 for (int j = 0; j < NM; ++j)
                     if (j < n) d[j] = fma(-wr[j], y, d[j]);
@@ -252,7 +267,7 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
     if (q != 0) return;
 #pragma unroll
     for (int j = 0; j < NM; ++j)
-        if (j < n) a.X[(size_t)chain * lda + j] = x[j];
+        if (j < n) a.X[(size_t)chain * a.lda + j] = x[j];
     a.theta[chain] = theta;
     if (fl) atomicOr(&a.flags[chain], fl);
 }
@@ -261,14 +276,24 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
 
 bool lane_fits(int n) { return n >= 1 && n <= kLaneMaxN; }
 
+constexpr size_t kLaneStageMax = 48 * 1024;   // LDS bytes for the staged A and b
+
+template <int NM, int G>
+hipError_t launch_lane_nm(const StepArgs& a, hipStream_t stream)
+{
+    const dim3 grid((unsigned)(((int64_t)a.z * G + kLaneThreads - 1) / kLaneThreads)), block(kLaneThreads);
+    const size_t bytes = ((size_t)a.m * (NM + 1) + a.m) * sizeof(double);
+    if (bytes <= kLaneStageMax) hipLaunchKernelGGL((lane_kernel<NM, G, true>), grid, block, bytes, stream, a);
+    else hipLaunchKernelGGL((lane_kernel<NM, G, false>), grid, block, 0, stream, a);
+    return hipGetLastError();
+}
+
 template <int G>
 hipError_t launch_lane_g(const StepArgs& a, hipStream_t stream)
 {
-    const dim3 grid((unsigned)(((int64_t)a.z * G + kLaneThreads - 1) / kLaneThreads)), block(kLaneThreads);
-    if (a.n <= 8) hipLaunchKernelGGL((lane_kernel<8, G>), grid, block, 0, stream, a);
-    else if (a.n <= 16) hipLaunchKernelGGL((lane_kernel<16, G>), grid, block, 0, stream, a);
-    else hipLaunchKernelGGL((lane_kernel<32, G>), grid, block, 0, stream, a);
-    return hipGetLastError();
+    if (a.n <= 8) return launch_lane_nm<8, G>(a, stream);
+    if (a.n <= 16) return launch_lane_nm<16, G>(a, stream);
+    return launch_lane_nm<32, G>(a, stream);
 }
 
 // Lanes per walk, from timings on one MI355X (hypercube and simplex, 16 to
