@@ -98,8 +98,8 @@ typedef enum {
     MHAR_PATH_TILED = 3,     /* per step a screening GEMM over 256-row x 128-walk tiles and a
                                 chords kernel; FP32/BF16X3 (else MHAR_E_UNSUPPORTED) */
     MHAR_PATH_LANE = 4       /* a few lanes per walk, every row evaluated exactly in FP64 each
-                                step (no screening product, so any precision); n <= 32 (else
-                                MHAR_E_UNSUPPORTED).  With a learned covariance attached the
+                                step (no screening product, so any precision); n <= 32, or
+                                n <= 64 when A fits in 96 KB of LDS (else MHAR_E_UNSUPPORTED).  With a learned covariance attached the
                                 handle steps on the general kernel.  AUTO takes it for
                                 n <= 32 where its modelled step time (about
                                 2.2 + 0.0065 m n + 0.4 n m_eq us) beats the

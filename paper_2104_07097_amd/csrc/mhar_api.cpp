@@ -16,7 +16,7 @@ using namespace mhar;
 
 namespace mhar {
 // a few lanes per walk, every row exact (mhar_lane.hip)
-bool lane_fits(int n);
+bool lane_fits(int n, int m);
 hipError_t launch_lane(const StepArgs& a, hipStream_t stream);
 }  // namespace mhar
 
@@ -326,9 +326,14 @@ int64_t auto_chunk(const mhar_problem* p)
 // Measured: 15-20x the general kernel at n = 3..5 and 10^4 walks, 8x at
 // n = 15, 2.5-3x at n = 25, 4x for n = 10 with 16 walks; level with it for
 // the cube at n = 32 with 2500 walks.
+// (The variant for 33..64 coordinates, x and d in LDS, is taken on request
+// only: measured it beat the screened kernels on none of the hypercube and
+// simplex rows at n = 40..64.)
+constexpr int kLaneAutoMaxN = 32;
+
 bool lane_preferred(const mhar_problem* p, int z_pad)
 {
-    if (!lane_fits(p->n)) return false;
+    if (p->n > kLaneAutoMaxN || !lane_fits(p->n, p->m)) return false;
     const double lane_us = 2.2 + 0.0065 * (double)p->m * p->n + 0.4 * (double)p->n * p->m_eq;
     const double general_us = 16.0 * std::max(1.0, (double)z_pad / 2048.0);
     return lane_us < 0.9 * general_us;
@@ -574,7 +579,8 @@ mhar_status_t mhar_chains_create(mhar_problem_t p, int64_t z, const double* X0, 
     c->tiled = 0;
     c->lane = 0;
     if (p->path == MHAR_PATH_LANE) {
-        if (!lane_fits(p->n)) return cleanup(fail(MHAR_E_UNSUPPORTED, "the lane path needs n <= 32"));
+        if (!lane_fits(p->n, p->m))
+            return cleanup(fail(MHAR_E_UNSUPPORTED, "the lane path needs n <= 32, or n <= 64 with A in 96 KB of LDS"));
         c->lane = 1;
     } else if (p->path == MHAR_PATH_RESIDENT) {
         if (rs <= 0) return cleanup(fail(MHAR_E_UNSUPPORTED, "the resident path does not fit this shape"));

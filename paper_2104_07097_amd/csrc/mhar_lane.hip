@@ -272,9 +272,185 @@ __global__ __launch_bounds__(kLaneThreads) void lane_kernel(StepArgs a)
     if (fl) atomicOr(&a.flags[chain], fl);
 }
 
+// Rows of length 33..64: the same step with x, d and the draws h of each
+// walk kept in LDS beside the staged A and b (a workgroup is one wave, so
+// LDS hand-offs between the lanes of a group need only a wave-level fence).
+// Lane q of a group draws the pairs p = q (mod G), updates the coordinates
+// j = q (mod G) and evaluates the rows i = q (mod G); every lane of the group
+// forms A_eq h in the order of the other paths' wave reduction (one FMA
+// product per coordinate onto +0; pairs of coordinates 32 apart, then
+// pairwise halving).
+constexpr int kWideN = 64;
+constexpr int kWideLd = kWideN + 2;   // LDS row stride (doubles): 16-byte aligned rows, shifted banks
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int G>
+__global__ __launch_bounds__(kLaneThreads) void lane_wide_kernel(StepArgs a)
+{
+    constexpr int W = kLaneThreads / G;   // walks per workgroup (one wave)
+    constexpr int LD = kWideLd;
+    const int q = threadIdx.x & (G - 1), wl = threadIdx.x / G;
+    const int chain = blockIdx.x * W + wl;
+    const int n = a.n, m = a.m;
+    extern __shared__ double lane_lds[];
+    double* As = lane_lds;                 // m x LD
+    double* bs = As + (size_t)m * LD;      // m (padded to even)
+    double* xs = bs + ((m + 1) & ~1);      // W x LD
+    double* ds = xs + W * LD;              // W x LD
+    double* hs = ds + W * LD;              // W x LD
+    for (int e = threadIdx.x; e < m * LD; e += kLaneThreads) {
+        const int i = e / LD, j = e - i * LD;
+        As[e] = j < n ? a.A64[(size_t)i * a.lda + j] : 0.0;
+    }
+    for (int i = threadIdx.x; i < m; i += kLaneThreads) bs[i] = a.b64[i];
+    const bool live = chain < a.z;
+    double* xw = xs + wl * LD;
+    double* dw = ds + wl * LD;
+    double* hw = hs + wl * LD;
+    for (int j = q; j < LD; j += G) {
+        xw[j] = (live && j < n) ? a.X[(size_t)chain * a.lda + j] : 0.0;
+        dw[j] = 0.0;
+        hw[j] = 0.0;
+    }
+    wave_sync_lds();
+    if (!live) return;   // whole groups leave together; no wave-wide sync follows for them
+    int fl = 0;
+    double theta = a.theta[chain];
+
+    auto check_interior = [&]() __attribute__((always_inline)) {
+        for (int i = q; i < m; i += G) {
+            const double* ar = As + (size_t)i * LD;
+            const double bi = bs[i];
+            double s = bi;
+            for (int j = 0; j < n; ++j) s = __dsub_rn(s, __dmul_rn(ar[j], xw[j]));
+            if (!(s > 0.0)) fl |= kNotInterior;
+            if (s < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
+        }
+    };
+    if (a.recompute_first || a.steps == 0 || a.since0 == 0) check_interior();
+
+    const int npairs = (n + 1) >> 1;
+    for (int s = 0; s < a.steps; ++s) {
+        const uint64_t step = a.step0 + (uint64_t)s;
+        if (s > 0 && (a.since0 + s) % a.R == 0) check_interior();
+
+        // ---- directions ----
+        double* hd = a.m_eq > 0 ? hw : dw;
+        for (int p = q; p < npairs; p += G) {
+            Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step, (uint32_t)p);
+            double ev, od;
+            gauss_pair(w, ev, od);
+            hd[2 * p] = ev;
+            if (2 * p + 1 < n) hd[2 * p + 1] = od;
+        }
+        wave_sync_lds();
+        if (a.m_eq > 0) {
+            for (int j = q; j < n; j += G) dw[j] = hw[j];
+            for (int p = 0; p < a.m_eq; ++p) {
+                const double* er = a.Aeq + (size_t)p * a.lda;
+                double t[32];
+#pragma unroll
+                for (int l = 0; l < 32; ++l) {
+                    const double lo = l < n ? fma(er[l], hw[l], 0.0) : 0.0;
+                    const double hi = l + 32 < n ? fma(er[l + 32], hw[l + 32], 0.0) : 0.0;
+                    t[l] = lo + hi;
+                }
+#pragma unroll
+                for (int half = 16; half > 0; half >>= 1)
+#pragma unroll
+                    for (int l = 0; l < half; ++l) t[l] = t[l] + t[l + half];
+                const double y = t[0];
+                const double* wr = a.WT + (size_t)p * a.lda;
+                for (int j = q; j < n; j += G) dw[j] = fma(-wr[j], y, dw[j]);
+            }
+            wave_sync_lds();
+        }
+
+        // ---- chord: every row exactly, rows split over the group ----
+        unsigned long long lmax_b = (unsigned long long)__double_as_longlong(kInfD);
+        unsigned long long nlmin_b = lmax_b;
+        for (int i = q; i < m; i += G) {
+            const double* ar = As + (size_t)i * LD;
+            const double bi = bs[i];
+            double sx = bi, gx = 0.0;
+            for (int j = 0; j < n; ++j) {
+                const double aij = ar[j];
+                sx = __dsub_rn(sx, __dmul_rn(aij, xw[j]));
+                gx = __dadd_rn(gx, __dmul_rn(aij, dw[j]));
+            }
+            if (sx < -1e-12 * fmax(1.0, fabs(bi))) fl |= kInfeasible;
+            if (sx < 0.0) sx = 0.0;
+            if (gx > 0.0) {
+                const unsigned long long c = (unsigned long long)__double_as_longlong(sx / gx);
+                lmax_b = c < lmax_b ? c : lmax_b;
+            } else if (gx < 0.0) {
+                const unsigned long long c = (unsigned long long)__double_as_longlong(sx / -gx);
+                nlmin_b = c < nlmin_b ? c : nlmin_b;
+            }
+        }
+        group_min_or<G>(lmax_b, nlmin_b, fl);
+
+        // ---- theta and the update ----
+        const double lmax = __longlong_as_double((long long)lmax_b);
+        const double lmin = -__longlong_as_double((long long)nlmin_b);
+        double th = 0.0;
+        if (lmax == kInfD || lmin == -kInfD) {
+            fl |= kUnbounded;
+        } else if (!(lmax > lmin)) {
+            fl |= kDegenerate;
+        } else {
+            Block4 w = stream_block(a.seed, kTagTheta, a.chain_offset + (uint32_t)chain, step, 0);
+            const double u = open_unit(w.w0, w.w1);
+            th = __dadd_rn(lmin, __dmul_rn(u, __dsub_rn(lmax, lmin)));
+        }
+        theta = th;
+        int nf = isfinite(th) ? 0 : kNonFinite;
+        const int64_t rs = a.rec_s_base + s + 1;
+        const bool rec = a.rec_stride > 0 && chain < a.rec_chains && rs % a.rec_stride == 0;
+        double* rp = rec ? a.rec_out + ((size_t)(rs / a.rec_stride - 1) * a.rec_chains + chain) * n : nullptr;
+        for (int j = q; j < n; j += G) {
+            const double xn = __dadd_rn(xw[j], __dmul_rn(th, dw[j]));
+            xw[j] = xn;
+            if (!isfinite(xn)) nf = kNonFinite;
+            if (rec) rp[j] = xn;
+        }
+        fl |= nf;
+        wave_sync_lds();
+    }
+
+    unsigned long long u0 = 0, u1 = 0;
+    group_min_or<G>(u0, u1, fl);
+    const unsigned long long walks = __popcll(__ballot(q == 0));
+    if (threadIdx.x == 0 && a.steps > 0)
+        atomicAdd(&a.counters[0], walks * (unsigned long long)m * (unsigned long long)a.steps);
+    for (int j = q; j < n; j += G) a.X[(size_t)chain * a.lda + j] = xw[j];
+    if (q != 0) return;
+    a.theta[chain] = theta;
+    if (fl) atomicOr(&a.flags[chain], fl);
+}
+
+size_t lane_wide_bytes(int m, int G)
+{
+    return ((size_t)m * kWideLd + (((size_t)m + 1) & ~(size_t)1) + 3 * (size_t)(kLaneThreads / G) * kWideLd) * sizeof(double);
+}
+
+constexpr size_t kLaneWideMax = 96 * 1024;   // LDS bytes of the wide variant
+constexpr int kLaneWideG = 8;
+
 }  // namespace
 
-bool lane_fits(int n) { return n >= 1 && n <= kLaneMaxN; }
+bool lane_fits(int n, int m)
+{
+    if (n < 1) return false;
+    if (n <= kLaneMaxN) return true;
+    return n <= kWideN && lane_wide_bytes(m, kLaneWideG) <= kLaneWideMax;
+}
 
 constexpr size_t kLaneStageMax = 48 * 1024;   // LDS bytes for the staged A and b
 
@@ -309,7 +485,16 @@ int lane_group(const StepArgs& a)
 
 hipError_t launch_lane(const StepArgs& a, hipStream_t stream)
 {
-    if (!lane_fits(a.n) || a.r > 0 || a.m_eq > kMaxMeq) return hipErrorInvalidValue;
+    if (!lane_fits(a.n, a.m) || a.r > 0 || a.m_eq > kMaxMeq) return hipErrorInvalidValue;
+    if (a.n > kLaneMaxN) {
+        const size_t bytes = lane_wide_bytes(a.m, kLaneWideG);
+        const void* fn = (const void*)lane_wide_kernel<kLaneWideG>;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+        const dim3 grid((unsigned)(((int64_t)a.z * kLaneWideG + kLaneThreads - 1) / kLaneThreads)), block(kLaneThreads);
+        hipLaunchKernelGGL((lane_wide_kernel<kLaneWideG>), grid, block, bytes, stream, a);
+        return hipGetLastError();
+    }
     return lane_group(a) == 4 ? launch_lane_g<4>(a, stream) : launch_lane_g<8>(a, stream);
 }
 

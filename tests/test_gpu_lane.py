@@ -6,9 +6,10 @@ the other paths' wave reduction) and evaluates every row with the same
 sequential FP64 formula the other paths use for their candidate rows; the
 chord ends of a walk's lanes are combined by an exact minimum.  So its
 trajectories must be bitwise those of the general kernel.  Shapes cover each
-register template (n <= 8, 16, 32) and both group sizes (4 lanes per walk
-for n <= 8 and with equalities above 16, 8 otherwise), equality
-constraints, and walk counts that leave a partial last wave."""
+register template (n <= 8, 16, 32), both group sizes (4 lanes per walk
+for n <= 8 and with equalities above 16, 8 otherwise), the variant for
+33..64 coordinates that keeps x and d in LDS, equality constraints, and walk
+counts that leave a partial last wave."""
 import numpy as np
 import pytest
 import torch
@@ -33,6 +34,10 @@ def cases():
         "randpoly20": inst.randpoly(n=20, m=45, z=70, seed=71),
         "cube32": inst.hypercube(32, 70),
         "simplex_cut30": inst.simplex_cut(n=30, m_extra=12, m_eq_extra=2, z=70, seed=72),
+        # rows of 33..64 coordinates: the variant with x, d and the draws in LDS
+        "cube40": inst.hypercube(40, 70, rng.uniform(-0.5, 0.5, size=(70, 40))),
+        "simplex50": inst.simplex(50, 45),
+        "simplex_cut64": inst.simplex_cut(n=64, m_extra=30, m_eq_extra=3, z=70, seed=75),
     }
 
 
@@ -90,9 +95,11 @@ def test_lane_stats_and_auto_choice():
     assert ch2.stats()["kernel"] != 4
 
 
-def test_lane_rejects_large_n():
-    p = inst.randpoly(n=33, m=80, z=4, seed=74)
-    gu.announce("lane n=33")
+@pytest.mark.parametrize("n,m", [(65, 80), (64, 400)])
+def test_lane_rejects_large_shapes(n, m):
+    """n above 64, or n above 32 with A too large for the LDS of the wide variant."""
+    p = inst.randpoly(n=n, m=m, z=4, seed=74)
+    gu.announce("lane", f"n={n}", f"m={m}")
     with pytest.raises(mhar.MharError) as ei:
         gu.make(p, "fp32", path="lane")
     assert ei.value.code == mhar.E_UNSUPPORTED
