@@ -1,5 +1,6 @@
 // mhar_lane.hip -- a few lanes per walk, every row exact: the MHAR step for
-// small problems (n <= 32) on gfx950.
+// small problems (n <= 32 in registers, n <= 64 with the walk state in LDS)
+// on gfx950.
 //
 // Same method as the other kernels (paper Alg. 2, S4.3-S4.5), without the
 // screening product: a group of G lanes (1 to 8) holds the state x and
@@ -18,7 +19,7 @@
 // The directions are bitwise those of the other paths: the draws come from
 // the same counter streams, and A_eq h is summed in the order of their
 // wave reduction (one product per lane, then pairwise halving), which a
-// single lane can replay because n <= 32.
+// single lane can replay because n <= 64 (one product per lane of the wave).
 #include <math.h>
 
 #include "mhar_device.hpp"
