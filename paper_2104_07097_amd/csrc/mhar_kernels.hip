@@ -1246,6 +1246,76 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
     }
 }
 
+// Directions of global step `step` for the tiled path, one workgroup per
+// walk (isotropic directions): draws, projection, norm and the operand row,
+// each in the operation order of make_directions (the projection's A_eq h
+// and the norm as lane-strided FMA chains and a wave reduction), so the
+// directions are bitwise those the chords kernel would make; with one
+// workgroup per walk instead of per 16 walks, small walk counts still fill
+// the device.
+template <int P>
+__global__ __launch_bounds__(kThreads) void tiled_dirs_kernel(StepArgs a, uint64_t step)
+{
+    __shared__ double y[kMaxMeq];
+    __shared__ double dn2;
+    const int chain = blockIdx.x;   // < z_pad
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = a.n, lda = a.lda;
+    const bool live = chain < a.z;
+    double* drow = a.D + (size_t)chain * lda;
+    if (live) {
+        const int npairs = (n + 1) >> 1;
+        for (int p = tid; p < npairs; p += kThreads) {
+            Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step, (uint32_t)p);
+            double ev, od;
+            gauss_pair(w, ev, od);
+            drow[2 * p] = ev;
+            if (2 * p + 1 < n) drow[2 * p + 1] = od;
+        }
+    }
+    if (live && a.m_eq > 0) {
+        __syncthreads();
+        for (int p = wave; p < a.m_eq; p += kWaves) {
+            const double* er = a.Aeq + (size_t)p * lda;
+            double v = 0.0;
+            for (int j = lane; j < n; j += 64) v = fma(er[j], drow[j], v);
+            v = wave_sum(v);
+            if (lane == 0) y[p] = v;
+        }
+        __syncthreads();
+        for (int j = tid; j < n; j += kThreads) {
+            double v = drow[j];
+            for (int p = 0; p < a.m_eq; ++p) v = fma(-a.WT[(size_t)p * lda + j], y[p], v);
+            drow[j] = v;
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double v = 0.0;
+        if (live)
+            for (int j = lane; j < n; j += 64) v = fma(drow[j], drow[j], v);
+        v = wave_sum(v);
+        if (lane == 0) dn2 = v;
+    }
+    const size_t o0 = (size_t)chain * lda;
+    if (P == kBF16X3) {
+        __bf16* Dh = (__bf16*)a.Dop;
+        __bf16* Dl = Dh + (size_t)a.z_pad * lda;
+        for (int j = tid; j < lda; j += kThreads) {
+            const float v = (live && j < n) ? (float)drow[j] : 0.0f;
+            __bf16 hi, lo;
+            split_bf16(v, hi, lo);
+            Dh[o0 + j] = hi;
+            Dl[o0 + j] = lo;
+        }
+    } else {
+        float* Df = (float*)a.Dop;
+        for (int j = tid; j < lda; j += kThreads) Df[o0 + j] = (live && j < n) ? (float)drow[j] : 0.0f;
+    }
+    __syncthreads();
+    if (tid == 0) a.dn[chain] = sqrt(dn2);
+}
+
 template <int P>
 __global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint64_t step,
                                                                 int s_rel, int T, int do_chords,
@@ -1701,15 +1771,26 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream)
         T = 2;
         since = 0;
     }
-    if (a.steps > 0)
-        hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a,
-                           (uint64_t)0, 0, T, 0, 1, a.step0);
+    // isotropic directions come from their own launch, one workgroup per walk;
+    // a learned covariance keeps them in the chords kernel
+    const bool own_dirs = a.r == 0;
+    const dim3 grid_d(a.z_pad);
+    if (a.steps > 0) {
+        if (own_dirs)
+            hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kThreads), 0, stream, a, a.step0);
+        else
+            hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a,
+                               (uint64_t)0, 0, T, 0, 1, a.step0);
+    }
     for (int s = 0; s < a.steps; ++s) {
         const uint64_t step = a.step0 + (uint64_t)s;
+        const bool more = s + 1 < a.steps;
         hipLaunchKernelGGL(tiled_screen_kernel<P>, grid_s, dim3(kThreads), lds_s, stream, a,
                            pending, T);
         hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a, step, s,
-                           T, 1, (int)(s + 1 < a.steps), step + 1);
+                           T, 1, (int)(more && !own_dirs), step + 1);
+        if (more && own_dirs)
+            hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kThreads), 0, stream, a, step + 1);
         pending = 1;
         T += 1;
         since += 1;
