@@ -35,9 +35,9 @@ MFMA_PER_FLOP = {"fp32": 1, "bf16x3": 3, "fp64": 1}   # matrix-core products per
 # was measured on: reported as null once any of them differs.
 TRAFFIC = {
     "precision": "bf16x3", "steps_per_launch": 500,
-    "sources_sha256": "f5e6d9700b0238a4c09ba5f1cea6bc82bd8a3c2b8443fd205e2a36bffc342d39",
-    "fetch_kib": 25434.28125, "fetch_scale": 262144.0 / 131094.5,
-    "write_kib": 45336.0, "write_scale": 262144.0 / 262144.0,
+    "sources_sha256": "6f5315e4df38bca4baa94c2b3697826b3c30a99e02da5887be119c81cd59dbe7",
+    "fetch_kib": 25597.44, "fetch_scale": 262144.0 / 131096.69,
+    "write_kib": 46360.0, "write_scale": 262144.0 / 262144.0,
 }
 
 

@@ -24,9 +24,11 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
-        uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
+        // one 32 x 32 -> 64 multiply (v_mad_u64_u32) per product instead
+        // of separate high and low multiplies
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         uint32_t n0 = hi1 ^ c1 ^ k0;
         uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;
@@ -61,9 +63,11 @@ __device__ __forceinline__ void gauss_pair(const Block4& w, double& even, double
     double ua = open_unit(w.w0, w.w1);
     double ub = open_unit(w.w2, w.w3);
     double radius = sqrt(__dmul_rn(-2.0, log(ua)));
-    double angle = __dmul_rn(6.283185307179586, ub);
+    // the angle 2 pi ub is taken as pi times the exact 2 ub: no rounded
+    // product with 2 pi, and sinpi/cospi reduce their argument exactly in
+    // about half the instructions of sin/cos of a general argument
     double sn, cs;
-    sincos(angle, &sn, &cs);
+    sincospi(__dmul_rn(2.0, ub), &sn, &cs);
     even = __dmul_rn(radius, cs);
     odd = __dmul_rn(radius, sn);
 }

@@ -748,7 +748,7 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
             wave_sum4(q);
             fin0 = __all(fin0);
             fin1 = __all(fin1);
-            if (lane == 0) {
+            if (lane < 2) {
                 // bound on the slack error carried into the next step
                 auto grow_E = [&](int cl, double th, double xo, double xn2, bool finite) {
                     const double dn = cs->dnorm[buf][cl], at = fabs(th);
@@ -760,8 +760,11 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                     cs->E[cl] = E;
                     if (!finite) cs->flags[cl] |= kNonFinite;
                 };
-                if (v0) grow_E(cl0, th0, q[0], q[1], fin0);
-                if (v1) grow_E(cl1, th1, q[2], q[3], fin1);
+                // lanes 0 and 1 grow the bounds of the two walks side by side
+                const bool second = lane == 1;
+                if (second ? v1 : v0)
+                    grow_E(second ? cl1 : cl0, second ? th1 : th0, second ? q[2] : q[0],
+                           second ? q[3] : q[1], second ? fin1 : fin0);
             }
         }
         __syncthreads();
