@@ -32,6 +32,7 @@ CHAIN_INFEASIBLE = 8
 TAG_DIR = 0
 TAG_THETA = 1
 TAG_LOWRANK = 2
+TAG_TRAIN = 4
 
 _lib = None
 
@@ -75,6 +76,13 @@ def _bind(lib):
     lib.mhar_ref_adam.argtypes = [i64, d, d, d, d, i64, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double]
     lib.mhar_ref_adam.restype = None
+    lib.mhar_ref_dikin_hessian.argtypes = [i64, i64, d, d, i64, d, d, d]
+    lib.mhar_ref_dikin_hessian.restype = ctypes.c_int
+    lib.mhar_ref_dikin_objective.argtypes = [i64, i64, d, d, d, d, d, d]
+    lib.mhar_ref_dikin_objective.restype = ctypes.c_int
+    lib.mhar_ref_dikin_train_step.argtypes = [i64, i64, d, d, i64, d, i64, d, d, d, ctypes.c_int,
+                                              ctypes.c_double, d]
+    lib.mhar_ref_dikin_train_step.restype = ctypes.c_int
     return lib
 
 
@@ -207,3 +215,45 @@ class Oracle:
         self.lib.mhar_ref_adam(param.size, _p(param), _p(grad), _p(m1), _p(m2), t, lr, beta1,
                                beta2, eps)
         return param, m1, m2
+
+    def dikin_hessian(self, A, b, X):
+        """(rc, xbar, H): the log-barrier Hessian at the mean of the states X."""
+        A, b, X = map(_f64, (A, b, X))
+        m, n = A.shape
+        X = X.reshape(-1, n)
+        xbar = np.empty(n)
+        H = np.empty((n, n))
+        rc = self.lib.mhar_ref_dikin_hessian(n, m, _p(A), _p(b), X.shape[0], _p(X), _p(xbar),
+                                             _p(H))
+        return rc, xbar, H
+
+    def dikin_objective(self, U, log_sigma, H):
+        """(K, grad_U, grad_log_sigma) of K = 1/2 tr(H Sigma) - 1/2 log det Sigma."""
+        U, log_sigma, H = map(_f64, (U, log_sigma, H))
+        n = log_sigma.shape[0]
+        r = 0 if U is None else U.shape[1]
+        K = ctypes.c_double()
+        gU = np.zeros((n, max(r, 1)))
+        gl = np.zeros(n)
+        rc = self.lib.mhar_ref_dikin_objective(n, r, _p(U), _p(log_sigma), _p(H),
+                                               ctypes.byref(K), _p(gU), _p(gl))
+        if rc != OK:
+            raise RuntimeError(f"mhar_ref_dikin_objective failed: {rc}")
+        return K.value, gU[:, :r], gl
+
+    def dikin_train_step(self, A, b, X, U, v, k_pow=8, eta=0.5):
+        """One burn-in update towards the Dikin ellipsoid at mean(X).
+        Returns (U, log_sigma, v, lam), all new arrays."""
+        A, b, X = map(_f64, (A, b, X))
+        m, n = A.shape
+        X = X.reshape(-1, n)
+        U = np.array(U, dtype=np.float64, copy=True)
+        v = np.array(v, dtype=np.float64, copy=True)
+        ls = np.empty(n)
+        lam = ctypes.c_double()
+        rc = self.lib.mhar_ref_dikin_train_step(n, m, _p(A), _p(b), X.shape[0], _p(X), U.shape[1],
+                                                _p(U), _p(ls), _p(v), k_pow, eta,
+                                                ctypes.byref(lam))
+        if rc != OK:
+            raise RuntimeError(f"mhar_ref_dikin_train_step failed: {rc}")
+        return U, ls, v, lam.value

@@ -476,3 +476,154 @@ int mhar_ref_precond_train_step(int64_t n, int64_t r, double* V, double* log_sig
     free(gl);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Direction covariance fitted to the Dikin ellipsoid (not in the paper)     */
+/* ------------------------------------------------------------------------ */
+
+/* The log-barrier phi(x) = -sum_i log(b_i - a_i x) of the inequality rows
+ * has Hessian sum_i a_i a_i^T / s_i(x)^2; its unit ellipsoid at x (the
+ * Dikin ellipsoid) lies inside the polytope.  Evaluated at the mean of the
+ * walk states. */
+int mhar_ref_dikin_hessian(int64_t n, int64_t m, const double* A, const double* b,
+                           int64_t z, const double* X, double* xbar, double* H)
+{
+    if (n <= 0 || m <= 0 || z <= 0 || !A || !b || !X || !H) return MHAR_REF_E_INVALID_ARG;
+    double* mean = (double*)calloc((size_t)n, sizeof(double));
+    double* w = (double*)malloc(sizeof(double) * (size_t)m);
+    int rc = MHAR_REF_OK;
+    for (int64_t k = 0; k < z; ++k)
+        for (int64_t j = 0; j < n; ++j) mean[j] += X[k * n + j];
+    for (int64_t j = 0; j < n; ++j) mean[j] /= (double)z;
+    for (int64_t i = 0; i < m; ++i) {
+        double s = b[i];
+        for (int64_t j = 0; j < n; ++j) s -= A[i * n + j] * mean[j];
+        if (!(s > 0.0)) rc = MHAR_REF_E_NOT_INTERIOR;
+        w[i] = 1.0 / (s * s);
+    }
+    for (int64_t p = 0; p < n; ++p)
+        for (int64_t q = 0; q < n; ++q) {
+            double v = 0.0;
+            for (int64_t i = 0; i < m; ++i) v += w[i] * A[i * n + p] * A[i * n + q];
+            H[p * n + q] = v;
+        }
+    if (xbar) memcpy(xbar, mean, sizeof(double) * (size_t)n);
+    free(mean);
+    free(w);
+    return rc;
+}
+
+/* K(Sigma) = 1/2 tr(H Sigma) - 1/2 log det Sigma, Sigma = U U^T + diag(exp(2 l)):
+ * the Kullback-Leibler divergence of N(0, Sigma) from N(0, H^{-1}) up to a
+ * constant.  dK/dU = (H - Sigma^{-1}) U, dK/dl_i = (H - Sigma^{-1})_ii exp(2 l_i).
+ * Dense n x n algebra. */
+int mhar_ref_dikin_objective(int64_t n, int64_t r, const double* U, const double* log_sigma,
+                             const double* H, double* K, double* grad_U, double* grad_log_sigma)
+{
+    if (n <= 0 || r < 0 || !log_sigma || !H || !K || (r > 0 && !U)) return MHAR_REF_E_INVALID_ARG;
+    size_t nn = (size_t)(n * n);
+    double* Sig = (double*)malloc(sizeof(double) * nn);
+    double* L = (double*)malloc(sizeof(double) * nn);
+    double* Sinv = (double*)malloc(sizeof(double) * nn);
+    double* col = (double*)malloc(sizeof(double) * (size_t)n);
+    int rc;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double v = 0.0;
+            for (int64_t a = 0; a < r; ++a) v += U[i * r + a] * U[j * r + a];
+            if (i == j) v += exp(2.0 * log_sigma[i]);
+            Sig[i * n + j] = v;
+        }
+    rc = cholesky_lower(n, Sig, L);
+    if (rc == MHAR_REF_OK) {
+        double logdet = 0.0;
+        for (int64_t i = 0; i < n; ++i) logdet += 2.0 * log(L[i * n + i]);
+        for (int64_t j = 0; j < n; ++j) {
+            for (int64_t i = 0; i < n; ++i) col[i] = (i == j) ? 1.0 : 0.0;
+            cholesky_solve(n, L, col);
+            for (int64_t i = 0; i < n; ++i) Sinv[i * n + j] = col[i];
+        }
+        double tr = 0.0;
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) tr += H[i * n + j] * Sig[j * n + i];
+        *K = 0.5 * tr - 0.5 * logdet;
+        if (grad_U)
+            for (int64_t i = 0; i < n; ++i)
+                for (int64_t a = 0; a < r; ++a) {
+                    double v = 0.0;
+                    for (int64_t k = 0; k < n; ++k) v += (H[i * n + k] - Sinv[i * n + k]) * U[k * r + a];
+                    grad_U[i * r + a] = v;
+                }
+        if (grad_log_sigma)
+            for (int64_t i = 0; i < n; ++i)
+                grad_log_sigma[i] = (H[i * n + i] - Sinv[i * n + i]) * exp(2.0 * log_sigma[i]);
+    }
+    free(Sig); free(L); free(Sinv); free(col);
+    return rc;
+}
+
+/* One burn-in update of the covariance toward the Dikin ellipsoid at the
+ * mean of the walk states X (z x n):
+ *   1. H = the log-barrier Hessian at mean(X);
+ *   2. J = diag(H)^{-1/2} H diag(H)^{-1/2}; k_pow power iterations
+ *      v <- J v / |J v| from v (in/out), lam = v^T J v (an estimate of
+ *      lambda_max(J) from below);
+ *   3. log_sigma_i = -1/2 log(lam H_ii): the diagonal D = diag(1/(lam H_ii))
+ *      has D^{1/2} H D^{1/2} = J / lam, so N(0, D) is (up to the estimate)
+ *      the largest Gaussian of this diagonal shape inside the Dikin
+ *      ellipsoid;
+ *   4. with that diagonal, U <- U - eta H^{-1} dK/dU (a Newton-type step on
+ *      K: the H^{-1} factor is the inverse of the curvature of the
+ *      tr(H Sigma) term).  With eta = 1/2 the column norms follow the
+ *      Babylonian iteration towards their optimum.
+ * lam_out (may be NULL) receives lam. */
+int mhar_ref_dikin_train_step(int64_t n, int64_t m, const double* A, const double* b,
+                              int64_t z, const double* X, int64_t r, double* U,
+                              double* log_sigma, double* v, int k_pow, double eta,
+                              double* lam_out)
+{
+    if (n <= 0 || m <= 0 || z <= 0 || r <= 0 || !A || !b || !X || !U || !log_sigma || !v ||
+        k_pow < 1)
+        return MHAR_REF_E_INVALID_ARG;
+    size_t nn = (size_t)(n * n), nr = (size_t)(n * r);
+    double* H = (double*)malloc(sizeof(double) * nn);
+    double* L = (double*)malloc(sizeof(double) * nn);
+    double* dsq = (double*)malloc(sizeof(double) * (size_t)n);
+    double* y = (double*)malloc(sizeof(double) * (size_t)n);
+    double* gU = (double*)malloc(sizeof(double) * nr);
+    double* col = (double*)malloc(sizeof(double) * (size_t)n);
+    double K = 0.0, lam = 0.0;
+    int rc = mhar_ref_dikin_hessian(n, m, A, b, z, X, NULL, H);
+    if (rc != MHAR_REF_OK) goto done;
+    for (int64_t i = 0; i < n; ++i) dsq[i] = sqrt(H[i * n + i]);
+    for (int it = 0; it < k_pow; ++it) {
+        double norm2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double t = 0.0;
+            for (int64_t j = 0; j < n; ++j) t += H[i * n + j] / (dsq[i] * dsq[j]) * v[j];
+            y[i] = t;
+            norm2 += t * t;
+        }
+        double norm = sqrt(norm2);
+        for (int64_t i = 0; i < n; ++i) v[i] = y[i] / norm;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double t = 0.0;
+        for (int64_t j = 0; j < n; ++j) t += H[i * n + j] / (dsq[i] * dsq[j]) * v[j];
+        lam += v[i] * t;
+    }
+    for (int64_t i = 0; i < n; ++i) log_sigma[i] = -0.5 * log(lam * H[i * n + i]);
+    rc = mhar_ref_dikin_objective(n, r, U, log_sigma, H, &K, gU, NULL);
+    if (rc != MHAR_REF_OK) goto done;
+    rc = cholesky_lower(n, H, L);
+    if (rc != MHAR_REF_OK) goto done;
+    for (int64_t a = 0; a < r; ++a) {
+        for (int64_t i = 0; i < n; ++i) col[i] = gU[i * r + a];
+        cholesky_solve(n, L, col);
+        for (int64_t i = 0; i < n; ++i) U[i * r + a] -= eta * col[i];
+    }
+    if (lam_out) *lam_out = lam;
+done:
+    free(H); free(L); free(dsq); free(y); free(gU); free(col);
+    return rc;
+}

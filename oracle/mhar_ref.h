@@ -45,6 +45,7 @@ extern "C" {
 #define MHAR_REF_TAG_DIR     0
 #define MHAR_REF_TAG_THETA   1
 #define MHAR_REF_TAG_LOWRANK 2
+#define MHAR_REF_TAG_TRAIN   4
 
 /* Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11). */
 void mhar_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -112,6 +113,25 @@ int mhar_ref_precond_train_step(int64_t n, int64_t r, double* V, double* log_sig
                                 double* m1V, double* m2V, double* m1l, double* m2l, int64_t z,
                                 const double* X, int64_t t, double lr, double beta1,
                                 double beta2, double eps, double* U_out);
+
+/* Log-barrier Hessian sum_i a_i a_i^T / s_i^2, s = b - A xbar, at the mean
+ * xbar of the walk states X (z x n); H is n x n, xbar (n, may be NULL).
+ * MHAR_REF_E_NOT_INTERIOR if some s_i <= 0. */
+int mhar_ref_dikin_hessian(int64_t n, int64_t m, const double* A, const double* b,
+                           int64_t z, const double* X, double* xbar, double* H);
+
+/* K = 1/2 tr(H Sigma) - 1/2 log det Sigma for Sigma = U U^T + diag(exp(2 log_sigma))
+ * and its gradient with respect to U and log_sigma (either may be NULL). */
+int mhar_ref_dikin_objective(int64_t n, int64_t r, const double* U, const double* log_sigma,
+                             const double* H, double* K, double* grad_U, double* grad_log_sigma);
+
+/* One burn-in update towards the Dikin ellipsoid at the mean state: Hessian,
+ * k_pow power iterations on the Jacobi-scaled Hessian (v in/out), the
+ * inscribed diagonal log_sigma (out), then U <- U - eta H^{-1} dK/dU. */
+int mhar_ref_dikin_train_step(int64_t n, int64_t m, const double* A, const double* b,
+                              int64_t z, const double* X, int64_t r, double* U,
+                              double* log_sigma, double* v, int k_pow, double eta,
+                              double* lam_out);
 
 #ifdef __cplusplus
 }

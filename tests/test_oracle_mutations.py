@@ -8,6 +8,7 @@ import oracle as oracle_pkg
 from oracle import TAG_DIR, Oracle, load
 
 from . import test_oracle_chord as chord
+from . import test_oracle_dikin as dikin
 from . import test_oracle_precond as precond
 from . import test_oracle_projection as proj
 from . import test_oracle_rng as rng
@@ -31,6 +32,11 @@ PINS = [
     precond.test_direction_covariance,
     precond.test_train_step_gradient_finite_differences,
     precond.test_train_step_scale_equivariance,
+    dikin.test_hessian_is_barrier_second_difference,
+    dikin.test_objective_minimum_is_closed_form,
+    dikin.test_objective_gradient_finite_differences,
+    dikin.test_train_step_axis_box_closed_form,
+    lambda o: dikin.test_train_step_reaches_closed_form_optimum(o, 8, 2),
 ]
 
 MUTANTS = {
@@ -50,12 +56,28 @@ MUTANTS = {
     "projection_skipped": ("d[i] = v;", "d[i] = h[i];"),
     "precond_scale": ("h[j] = v + exp(log_sigma[j]) * h[j];",
                       "h[j] = v + exp(2.0 * log_sigma[j]) * h[j];"),
-    "nll_grad_factor": ("grad_U[i * r + a] = v;", "grad_U[i * r + a] = 0.5 * v;"),
-    "nll_logdet": ("logdet += 2.0 * log(L[i * n + i]);", "logdet += log(L[i * n + i]);"),
+    "nll_grad_factor": ("* U[k * r + a];\n                grad_U[i * r + a] = v;",
+                        "* U[k * r + a];\n                grad_U[i * r + a] = 0.5 * v;"),
+    "nll_logdet": ("\n    for (int64_t i = 0; i < n; ++i) logdet += 2.0 * log(L[i * n + i]);",
+                   "\n    for (int64_t i = 0; i < n; ++i) logdet += log(L[i * n + i]);"),
+    "dikin_logdet": ("\n        for (int64_t i = 0; i < n; ++i) logdet += 2.0 * log(L[i * n + i]);",
+                     "\n        for (int64_t i = 0; i < n; ++i) logdet += log(L[i * n + i]);"),
     "adam_bias": ("double mh = m1[i] / c1;", "double mh = m1[i];"),
     "train_chain_scale": ("gV[i * r + a] = gU[i * r + a] * exp(log_sigma[i]);",
                           "gV[i * r + a] = gU[i * r + a];"),
     "train_chain_rowsum": ("gl[i] += gU[i * r + a] * U[i * r + a];", ";"),
+    "dikin_weight_power": ("w[i] = 1.0 / (s * s);", "w[i] = 1.0 / s;"),
+    "dikin_row_index": ("v += w[i] * A[i * n + p] * A[i * n + q];",
+                        "v += w[i] * A[i * n + p] * A[i * n + p];"),
+    "dikin_kl_half": ("*K = 0.5 * tr - 0.5 * logdet;", "*K = 0.5 * tr - logdet;"),
+    "dikin_grad_sign": ("v += (H[i * n + k] - Sinv[i * n + k]) * U[k * r + a];",
+                        "v += (H[i * n + k] + Sinv[i * n + k]) * U[k * r + a];"),
+    "dikin_grad_l_scale": ("(H[i * n + i] - Sinv[i * n + i]) * exp(2.0 * log_sigma[i]);",
+                           "(H[i * n + i] - Sinv[i * n + i]) * exp(log_sigma[i]);"),
+    "dikin_not_inscribed": ("log_sigma[i] = -0.5 * log(lam * H[i * n + i]);",
+                            "log_sigma[i] = -0.5 * log(H[i * n + i]);"),
+    "dikin_no_newton": ("U[i * r + a] -= eta * col[i];", "U[i * r + a] -= eta * gU[i * r + a];"),
+    "dikin_power_unscaled": ("lam += v[i] * t;", "lam += t;"),
 }
 
 
