@@ -85,7 +85,10 @@ enum {
     MHAR_CHAIN_UNBOUNDED = 1,   /* no row bounds the line on one side (Delta assumed bounded, S2.1) */
     MHAR_CHAIN_DEGENERATE = 2,  /* lambda_max <= lambda_min */
     MHAR_CHAIN_NONFINITE = 4,   /* NaN/Inf in theta or the state */
-    MHAR_CHAIN_INFEASIBLE = 8   /* exact FP64 slack below -1e-12 max(1,|b_i|) */
+    MHAR_CHAIN_INFEASIBLE = 8,  /* exact FP64 slack below -1e-12 max(1,|b_i|) */
+    MHAR_FIT_FAILED = 32        /* (mhar_sync only) a covariance fit step met a non-positive
+                                   pivot or a mean state outside the polytope; that step and
+                                   every later one left the covariance unchanged */
 };
 
 /* Kernel path of the step.  Every path gives the same trajectories (the
@@ -209,7 +212,8 @@ mhar_status_t mhar_set_state(mhar_chains_t chains, const double* X, uint64_t ste
 /* Current step counter (host, no synchronisation). */
 mhar_status_t mhar_get_step(mhar_chains_t chains, uint64_t* step);
 
-/* Synchronise `stream` and return the OR of all per-walk status bits. */
+/* Synchronise `stream` and return the OR of all per-walk status bits, plus
+ * MHAR_FIT_FAILED when an attached covariance's fit failed. */
 mhar_status_t mhar_sync(mhar_chains_t chains, void* stream, int32_t* any_flags);
 
 /* Synchronise `stream` and read the diagnostics counters. */
@@ -223,20 +227,42 @@ mhar_status_t mhar_chains_destroy(mhar_chains_t chains);
 /* Directions become d = P (U eps + exp(l) o h), eps ~ N(0, I_rank) from the
  * LOWRANK stream, h ~ N(0, I_n): Gaussian with covariance
  * Sigma = U U^T + diag(exp(2 l)), symmetric and independent of the state,
- * so the uniform target is kept.  Training fits Sigma to the walk states by
- * Adam on the Gaussian NLL  1/2 log det Sigma + 1/2 tr(Sigma^{-1} S)  (S: the
- * (1/z) covariance of the states about their mean) -- the isotropic
- * pre-processing the paper's cost analysis assumes (S3.1).  U is n x rank
- * row-major FP64, l (log_sigma) has n entries.  Steps taken while a
- * covariance is attached run on the general kernel. */
+ * so the uniform target is kept.  Training brings the body towards the
+ * near-isotropic position the paper's cost analysis assumes (S3.1), by one
+ * of two objectives fixed when the covariance is attached:
+ *   MHAR_FIT_STATES: Adam on the Gaussian NLL of the walk states,
+ *     1/2 log det Sigma + 1/2 tr(Sigma^{-1} S), S their (1/z) covariance
+ *     about their mean;
+ *   MHAR_FIT_DIKIN: the divergence of N(0, Sigma) from the Dikin ellipsoid
+ *     at the mean walk state xbar,
+ *       K = 1/2 tr(H Sigma) - 1/2 log det Sigma,
+ *       H = sum_i a_i a_i^T / (b_i - a_i xbar)^2
+ *     (the log-barrier Hessian; K is KL(N(0,Sigma) | N(0,H^{-1})) up to a
+ *     constant).  Each step sets the diagonal to the largest Gaussian of the
+ *     Jacobi shape diag(H)^{-1} inside the Dikin ellipsoid,
+ *     exp(2 l_i) = 1 / (lam H_ii) with lam the power-iteration estimate
+ *     (4 iterations per step, continued across steps from a unit vector
+ *     drawn from the TRAIN stream, chain i, step 1) of the largest
+ *     eigenvalue of diag(H)^{-1/2} H diag(H)^{-1/2}, and moves U by the
+ *     H^{-1}-preconditioned gradient step U <- U - lr H^{-1} dK/dU.  The
+ *     walk states reveal long axes of an elongated body only once the walks
+ *     have explored them; the slacks of all rows at the mean state reveal
+ *     them at once.  Costs O(n^2 m + n^3) per step (n <= 4096).
+ * U is n x rank row-major FP64, l (log_sigma) has n entries. */
+typedef enum {
+    MHAR_FIT_STATES = 0,
+    MHAR_FIT_DIKIN = 1
+} mhar_fit_t;
 
-/* Device workspace bytes for a covariance of rank 1..64 on these chains. */
-mhar_status_t mhar_precond_workspace_size(mhar_chains_t chains, int32_t rank, size_t* bytes);
+/* Device workspace bytes for a covariance of rank 1..64 on these chains,
+ * trained by `objective` (mhar_fit_t). */
+mhar_status_t mhar_precond_workspace_size(mhar_chains_t chains, int32_t rank, int32_t objective,
+                                          size_t* bytes);
 
 /* Attach a covariance: U_ij = 0.01 N(0,1) from the stream (seed, tag 4,
  * chain = i, step 0), l = 0.  workspace: dev, 256-byte aligned. */
-mhar_status_t mhar_precond_create(mhar_chains_t chains, int32_t rank, void* workspace,
-                                  size_t ws_bytes, void* stream);
+mhar_status_t mhar_precond_create(mhar_chains_t chains, int32_t rank, int32_t objective,
+                                  void* workspace, size_t ws_bytes, void* stream);
 
 /* Set U (dev n x rank) and log_sigma (dev n); clears the Adam moments and
  * sets the trained coordinates V = diag(exp(-log_sigma)) U. */
@@ -246,18 +272,23 @@ mhar_status_t mhar_precond_set(mhar_chains_t chains, const double* U, const doub
 /* Copy U (dev n x rank) and log_sigma (dev n); either may be NULL. */
 mhar_status_t mhar_precond_get(mhar_chains_t chains, double* U, double* log_sigma, void* stream);
 
-/* NLL of the current states and its gradient: nll dev (1 double), grad_U
- * dev (n x rank), grad_log_sigma dev (n); any may be NULL. */
-mhar_status_t mhar_precond_loss(mhar_chains_t chains, double* nll, double* grad_U,
+/* The objective at the current states and (U, l) and its gradient: loss dev
+ * (1 double: the NLL, or K), grad_U dev (n x rank), grad_log_sigma dev (n);
+ * any may be NULL. */
+mhar_status_t mhar_precond_loss(mhar_chains_t chains, double* loss, double* grad_U,
                                 double* grad_log_sigma, void* stream);
 
 /* `steps` burn-in steps: each is one MHAR step with the current Sigma,
- * then one Adam update (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr)
- * from the gradient at the new states.  Adam works in the scale-free
- * coordinates (V, log_sigma) with U = diag(exp(log_sigma)) V: their
- * gradients are diag(exp(log_sigma)) grad_U and grad_log_sigma plus the row
- * sums of grad_U o U, so every axis, long or short, gets an O(1) step.
- * U is rebuilt from V after each update.  MHAR_E_STATE once frozen. */
+ * then one update at the new states.
+ * MHAR_FIT_STATES: one Adam update (beta1 0.9, beta2 0.999, eps 1e-8,
+ *   learning rate lr > 0) in the scale-free coordinates (V, log_sigma) with
+ *   U = diag(exp(log_sigma)) V: their gradients are diag(exp(log_sigma))
+ *   grad_U and grad_log_sigma plus the row sums of grad_U o U, so every
+ *   axis, long or short, gets an O(1) step.  U is rebuilt from V.
+ * MHAR_FIT_DIKIN: the step described above with step size lr in (0, 1];
+ *   lr = 1/2 takes the column norms of U along the Babylonian iteration to
+ *   their optimum.
+ * MHAR_E_STATE once frozen. */
 mhar_status_t mhar_precond_train(mhar_chains_t chains, int64_t steps, double lr, void* stream);
 
 /* Freeze the covariance: later steps use it unchanged, training is refused. */

@@ -670,14 +670,16 @@ mhar_status_t mhar_sync(mhar_chains_t c, void* stream, int32_t* any_flags)
     if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
     hipStream_t s = (hipStream_t)stream;
     std::vector<int> fl(c->z);
-    int gerr = 0;
+    int gerr = 0, fit = 0;
     MHAR_HIP(hipMemcpyAsync(fl.data(), c->flags, sizeof(int) * c->z, hipMemcpyDeviceToHost, s), "status read");
     MHAR_HIP(hipMemcpyAsync(&gerr, c->gerr, sizeof(int), hipMemcpyDeviceToHost, s), "status read");
+    if (c->pc_rank)
+        MHAR_HIP(hipMemcpyAsync(&fit, c->pc.status, sizeof(int), hipMemcpyDeviceToHost, s), "status read");
     MHAR_HIP(hipStreamSynchronize(s), "stream synchronize");
     if (gerr) return fail(MHAR_E_HIP, "a workgroup group wait timed out; the states are not valid");
     int acc = 0;
     for (int v : fl) acc |= v;
-    if (any_flags) *any_flags = acc & 15;
+    if (any_flags) *any_flags = (acc & 15) | (fit ? MHAR_FIT_FAILED : 0);
     return MHAR_OK;
 }
 
@@ -700,29 +702,50 @@ mhar_status_t mhar_get_stats(mhar_chains_t c, void* stream, mhar_stats_t* stats)
     return MHAR_OK;
 }
 
-mhar_status_t mhar_precond_workspace_size(mhar_chains_t c, int32_t rank, size_t* bytes)
+static mhar_status_t check_fit(const mhar_chains* c, int32_t rank, int32_t objective)
 {
-    if (!c || !bytes) return fail(MHAR_E_INVALID_ARG, "chains and bytes must be non-NULL");
     if (rank < 1 || rank > kMaxMeq) return fail(MHAR_E_SHAPE, "rank must be in [1, 64]");
-    *bytes = precond_bytes(c->p->n, rank, c->z, c->p->lda);
+    if (objective != MHAR_FIT_STATES && objective != MHAR_FIT_DIKIN)
+        return fail(MHAR_E_INVALID_ARG, "objective must be MHAR_FIT_STATES or MHAR_FIT_DIKIN");
+    if (objective == MHAR_FIT_DIKIN && c->p->n > kMaxNDikin)
+        return fail(MHAR_E_SHAPE, "the Dikin fit takes n <= 4096");
     return MHAR_OK;
 }
 
-mhar_status_t mhar_precond_create(mhar_chains_t c, int32_t rank, void* ws, size_t ws_bytes, void* stream)
+mhar_status_t mhar_precond_workspace_size(mhar_chains_t c, int32_t rank, int32_t objective,
+                                          size_t* bytes)
+{
+    if (!c || !bytes) return fail(MHAR_E_INVALID_ARG, "chains and bytes must be non-NULL");
+    mhar_status_t st = check_fit(c, rank, objective);
+    if (st) return st;
+    *bytes = precond_bytes(c->p->n, rank, c->z, c->p->lda, objective, c->p->m_pad);
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_create(mhar_chains_t c, int32_t rank, int32_t objective, void* ws,
+                                  size_t ws_bytes, void* stream)
 {
     if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
     if (c->pc_rank) return fail(MHAR_E_STATE, "a covariance is already attached");
-    if (rank < 1 || rank > kMaxMeq) return fail(MHAR_E_SHAPE, "rank must be in [1, 64]");
+    mhar_status_t st = check_fit(c, rank, objective);
+    if (st) return st;
     if (!ws || !aligned256(ws)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < precond_bytes(c->p->n, rank, c->z, c->p->lda))
+    if (ws_bytes < precond_bytes(c->p->n, rank, c->z, c->p->lda, objective, c->p->m_pad))
         return fail(MHAR_E_WORKSPACE, "precond workspace too small");
     c->pc = PrecondBufs{};
     c->pc.n = c->p->n;
     c->pc.r = rank;
     c->pc.z = c->z;
     c->pc.lda = c->p->lda;
+    c->pc.objective = objective;
+    c->pc.m = c->p->m;
+    c->pc.m_pad = c->p->m_pad;
+    c->pc.A64 = c->p->A64;
+    c->pc.b64 = c->p->b64;
     precond_carve(&c->pc, ws);
     MHAR_HIP(launch_precond_init(c->pc, c->seed, (hipStream_t)stream), "covariance init");
+    if (objective == MHAR_FIT_DIKIN)
+        MHAR_HIP(launch_dikin_init(c->pc, c->seed, (hipStream_t)stream), "covariance init");
     c->pc_rank = rank;
     c->pc_frozen = 0;
     c->pc_t = 0;
@@ -764,7 +787,10 @@ mhar_status_t mhar_precond_loss(mhar_chains_t c, double* nll, double* gU, double
     if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
     if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
     hipStream_t s = (hipStream_t)stream;
-    MHAR_HIP(launch_precond_grad(c->pc, c->X, s), "covariance gradient");
+    if (c->pc.objective == MHAR_FIT_DIKIN)
+        MHAR_HIP(launch_dikin_loss(c->pc, c->X, s), "covariance objective");
+    else
+        MHAR_HIP(launch_precond_grad(c->pc, c->X, s), "covariance gradient");
     if (nll) MHAR_HIP(hipMemcpyAsync(nll, c->pc.nll, 8, hipMemcpyDeviceToDevice, s), "loss copy");
     if (gU) MHAR_HIP(hipMemcpyAsync(gU, c->pc.gU, (size_t)c->pc.n * c->pc.r * 8, hipMemcpyDeviceToDevice, s), "gradient copy");
     if (gls) MHAR_HIP(hipMemcpyAsync(gls, c->pc.gl, (size_t)c->pc.n * 8, hipMemcpyDeviceToDevice, s), "gradient copy");
@@ -777,13 +803,19 @@ mhar_status_t mhar_precond_train(mhar_chains_t c, int64_t steps, double lr, void
     if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
     if (c->pc_frozen) return fail(MHAR_E_STATE, "the covariance is frozen");
     if (steps < 0 || !(lr > 0.0)) return fail(MHAR_E_INVALID_ARG, "need steps >= 0 and lr > 0");
+    const bool dikin = c->pc.objective == MHAR_FIT_DIKIN;
+    if (dikin && !(lr <= 1.0)) return fail(MHAR_E_INVALID_ARG, "the Dikin fit takes lr in (0, 1]");
     hipStream_t s = (hipStream_t)stream;
     for (int64_t k = 0; k < steps; ++k) {
         mhar_status_t st = run_steps(c, 1, 0, nullptr, 0, 0, s);
         if (st) return st;
-        MHAR_HIP(launch_precond_grad(c->pc, c->X, s), "covariance gradient");
         c->pc_t += 1;
-        MHAR_HIP(launch_precond_adam(c->pc, c->pc_t, lr, 0.9, 0.999, 1e-8, s), "covariance update");
+        if (dikin) {
+            MHAR_HIP(launch_dikin_train(c->pc, c->X, kDikinPowerIters, lr, s), "covariance update");
+        } else {
+            MHAR_HIP(launch_precond_grad(c->pc, c->X, s), "covariance gradient");
+            MHAR_HIP(launch_precond_adam(c->pc, c->pc_t, lr, 0.9, 0.999, 1e-8, s), "covariance update");
+        }
     }
     return MHAR_OK;
 }

@@ -21,6 +21,7 @@ constexpr int kScreenWalks = 128;
 constexpr int kRecRows = 256;    // tiled path: rows x walks of a recompute tile
 constexpr int kRecWalks = 64;
 constexpr int kMaxMeq = 64;
+constexpr int kMaxNDikin = 4096; // the Dikin covariance fit keeps two n x n FP64 matrices
 
 enum Prec { kFP64 = 0, kFP32 = 1, kBF16X3 = 2 };
 
@@ -149,6 +150,7 @@ hipError_t launch_export_flags(const int* flags, int z, int32_t* out, int clear_
 // ---- learned preconditioner (direction covariance U U^T + diag(exp(2 l))) ----
 struct PrecondBufs {
     int n, r, z, lda;
+    int objective;                      // 0: Gaussian NLL of the states; 1: Dikin ellipsoid
     double *U, *logsig, *esig;          // covariance factor, log scales, exp(log scales)
     double *V;                          // trained coordinates V = diag(exp(-l)) U (n x r)
     double *m1V, *m2V, *m1l, *m2l;      // Adam moments of V and l
@@ -156,14 +158,32 @@ struct PrecondBufs {
     double *GB, *C, *Cinv, *K;          // r x r each
     double *gU, *gl, *rowterm, *nll;    // n x r, n, n, 2 (NLL, log det C)
     double* part;                       // split-K partial sums of H and G
-    int* status;
+    int* status;                        // sticky: nonzero once a fit step failed (updates skipped)
+    // Dikin fit: the problem's rows, the log-barrier Hessian at the mean state
+    // (N x N, N = n rounded up to 64) and its Cholesky factor, row weights,
+    // power-iteration vectors, sqrt(diag H), H U, the solve result, lambda
+    int m, m_pad, N;
+    const double *A64, *b64;
+    double *Hm, *Lm, *wrow, *pv, *py0, *py1, *dsq, *HU, *Ysol, *lam;
 };
-size_t precond_bytes(int n, int r, int z, int lda);
+size_t precond_bytes(int n, int r, int z, int lda, int objective, int m_pad);
 void precond_carve(PrecondBufs* p, void* ws);
 hipError_t launch_precond_init(const PrecondBufs& p, uint64_t seed, hipStream_t stream);
 hipError_t launch_precond_set_scales(const PrecondBufs& p, hipStream_t stream);
 hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_t stream);
 hipError_t launch_precond_adam(const PrecondBufs& p, int64_t t, double lr, double b1, double b2,
                                double eps, hipStream_t stream);
+hipError_t launch_precond_mean(const PrecondBufs& p, const double* X, hipStream_t stream);
+hipError_t launch_precond_w(const PrecondBufs& p, hipStream_t stream);
+hipError_t launch_precond_capacitance(const PrecondBufs& p, hipStream_t stream);
+// Dikin fit (mhar_dikin.hip)
+constexpr int kDikinPowerIters = 4;   // power iterations per training step
+int dikin_order(int n);
+size_t dikin_bytes(int n, int r, int m_pad);
+void dikin_carve(PrecondBufs* p, void* ws);
+hipError_t launch_dikin_init(const PrecondBufs& p, uint64_t seed, hipStream_t stream);
+hipError_t launch_dikin_loss(const PrecondBufs& p, const double* X, hipStream_t stream);
+hipError_t launch_dikin_train(const PrecondBufs& p, const double* X, int k_pow, double eta,
+                              hipStream_t stream);
 
 }  // namespace mhar

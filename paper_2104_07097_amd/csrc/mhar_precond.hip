@@ -34,8 +34,9 @@ constexpr uint32_t kTagTrain = 4;
 
 __global__ void precond_init_kernel(int n, int r, uint64_t seed, double* U, double* V,
                                     double* logsig, double* esig, double* m1V, double* m2V,
-                                    double* m1l, double* m2l)
+                                    double* m1l, double* m2l, int* status)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
     const int64_t total = (int64_t)n * r;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -59,8 +60,9 @@ __global__ void precond_init_kernel(int n, int r, uint64_t seed, double* U, doub
 
 // scales of a caller-given (U, l): exp(l) and the trained coordinates V = U / exp(l)
 __global__ void scales_kernel(int n, int r, const double* U, const double* logsig, double* esig,
-                              double* V)
+                              double* V, int* status)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *status = 0;
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
         const double e = exp(logsig[j]);
         esig[j] = e;
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(64) void chol_kernel(int r, const double* C, const 
     }
     if (lane == 0) {
         *logdet = ld;
-        *status = bad;
+        if (bad) atomicOr(status, 4);
     }
     if (bad) return;
     if (lane < r) {
@@ -297,9 +299,11 @@ __global__ __launch_bounds__(64) void chol_kernel(int r, const double* C, const 
 __global__ void grad_kernel(int n, int r, const double* __restrict__ W, const double* __restrict__ H,
                             const double* __restrict__ K, const double* __restrict__ Cinv,
                             const double* __restrict__ G, const double* __restrict__ logsig,
-                            const double* __restrict__ Sd, double* gU, double* gl, double* rowterm)
+                            const double* __restrict__ Sd, const int* status, double* gU,
+                            double* gl, double* rowterm)
 {
     __shared__ double R[kMaxMeq], V[kMaxMeq], Wr[kMaxMeq], Hr[kMaxMeq];
+    if (*status) return;   // C was not factorised: Cinv and K are not valid
     const int i = blockIdx.x, q = threadIdx.x;
     const double dinv = exp(-2.0 * logsig[i]);
     if (q < r) {
@@ -375,8 +379,9 @@ __global__ __launch_bounds__(256) void nll_kernel(int n, int r, const double* ro
 __global__ void adam_kernel(int n, int r, int64_t t, double lr, double b1, double b2, double eps,
                             double* U, double* V, const double* gU, double* m1V, double* m2V,
                             double* logsig, const double* gl, double* m1l, double* m2l,
-                            double* esig)
+                            double* esig, const int* status)
 {
+    if (*status) return;   // the gradient was not formed
     const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int64_t row = (int64_t)i * r;
@@ -407,7 +412,7 @@ inline int blocks_for(int64_t total, int threads)
 
 }  // namespace
 
-size_t precond_bytes(int n, int r, int z, int lda)
+size_t precond_bytes(int n, int r, int z, int lda, int objective, int m_pad)
 {
     (void)lda;
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
@@ -421,6 +426,7 @@ size_t precond_bytes(int n, int r, int z, int lda)
     b += al(64);                      // nll, logdet
     b += al(64);                      // status
     b += al((size_t)kSplit * (nr > rr ? nr : rr) * 8);   // split-K partial sums
+    if (objective == 1) b += dikin_bytes(n, r, m_pad);
     return b;
 }
 
@@ -458,19 +464,21 @@ void precond_carve(PrecondBufs* p, void* ws)
     p->nll = (double*)take(64);
     p->status = (int*)take(64);
     p->part = (double*)take((size_t)kSplit * (nr > rr ? nr : rr) * 8);
+    if (p->objective == 1) dikin_carve(p, b + o);
 }
 
 hipError_t launch_precond_init(const PrecondBufs& p, uint64_t seed, hipStream_t stream)
 {
     hipLaunchKernelGGL(precond_init_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0,
-                       stream, p.n, p.r, seed, p.U, p.V, p.logsig, p.esig, p.m1V, p.m2V, p.m1l, p.m2l);
+                       stream, p.n, p.r, seed, p.U, p.V, p.logsig, p.esig, p.m1V, p.m2V, p.m1l, p.m2l,
+                       p.status);
     return hipGetLastError();
 }
 
 hipError_t launch_precond_set_scales(const PrecondBufs& p, hipStream_t stream)
 {
     hipLaunchKernelGGL(scales_kernel, dim3(blocks_for(p.n, 64)), dim3(64), 0, stream, p.n, p.r, p.U,
-                       p.logsig, p.esig, p.V);
+                       p.logsig, p.esig, p.V, p.status);
     return hipGetLastError();
 }
 
@@ -493,9 +501,32 @@ hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_
     hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, stream, p.r, p.C, p.GB, p.Cinv, p.K,
                        p.nll + 1, p.status);
     hipLaunchKernelGGL(grad_kernel, dim3(p.n), dim3(64), 0, stream, p.n, p.r, p.W, p.H, p.K, p.Cinv,
-                       p.GB, p.logsig, p.Sd, p.gU, p.gl, rowterm);
+                       p.GB, p.logsig, p.Sd, p.status, p.gU, p.gl, rowterm);
     hipLaunchKernelGGL(nll_kernel, dim3(1), dim3(256), 0, stream, p.n, p.r, rowterm, p.Cinv, p.GB,
                        p.nll + 1, p.nll);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_mean(const PrecondBufs& p, const double* X, hipStream_t stream)
+{
+    hipLaunchKernelGGL(mean_sd_kernel, dim3((p.n + 63) / 64), dim3(512), 0, stream, p.n, p.z,
+                       p.lda, X, p.mean, p.Sd);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_w(const PrecondBufs& p, hipStream_t stream)
+{
+    hipLaunchKernelGGL(w_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0, stream,
+                       p.n, p.r, p.U, p.logsig, p.W);
+    return hipGetLastError();
+}
+
+// C^{-1} and log det C of the capacitance matrix in p.C (K = I + C^{-1} C is
+// formed as a by-product and not used)
+hipError_t launch_precond_capacitance(const PrecondBufs& p, hipStream_t stream)
+{
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, stream, p.r, p.C, p.C, p.Cinv, p.K,
+                       p.nll + 1, p.status);
     return hipGetLastError();
 }
 
@@ -504,7 +535,7 @@ hipError_t launch_precond_adam(const PrecondBufs& p, int64_t t, double lr, doubl
 {
     hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(p.n, 64)), dim3(64), 0, stream, p.n, p.r, t,
                        lr, b1, b2, eps, p.U, p.V, p.gU, p.m1V, p.m2V, p.logsig, p.gl, p.m1l, p.m2l,
-                       p.esig);
+                       p.esig, p.status);
     return hipGetLastError();
 }
 

@@ -33,6 +33,11 @@ CHAIN_UNBOUNDED = 1
 CHAIN_DEGENERATE = 2
 CHAIN_NONFINITE = 4
 CHAIN_INFEASIBLE = 8
+FIT_FAILED = 32
+
+FIT_STATES = 0
+FIT_DIKIN = 1
+FITS = {"states": FIT_STATES, "dikin": FIT_DIKIN}
 
 
 class MharError(RuntimeError):
@@ -81,8 +86,9 @@ SIGNATURES = {
     "mhar_sync": (_st, [_vp, _vp, ctypes.POINTER(ctypes.c_int32)]),
     "mhar_get_stats": (_st, [_vp, _vp, ctypes.POINTER(Stats)]),
     "mhar_chains_destroy": (_st, [_vp]),
-    "mhar_precond_workspace_size": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
-    "mhar_precond_create": (_st, [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
+    "mhar_precond_workspace_size": (_st, [_vp, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "mhar_precond_create": (_st, [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "mhar_precond_set": (_st, [_vp, _vp, _vp, _vp]),
     "mhar_precond_get": (_st, [_vp, _vp, _vp, _vp]),
     "mhar_precond_loss": (_st, [_vp, _vp, _vp, _vp, _vp]),
@@ -271,13 +277,15 @@ class Chains:
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     # ---- learned direction covariance ----
-    def precond_create(self, rank: int):
+    def precond_create(self, rank: int, objective: str = "states"):
         lib = load()
+        fit = FITS[objective]
         sz = ctypes.c_size_t()
-        _check(lib.mhar_precond_workspace_size(self.handle, int(rank), ctypes.byref(sz)))
+        _check(lib.mhar_precond_workspace_size(self.handle, int(rank), fit, ctypes.byref(sz)))
         self._pc_ws, ptr, nbytes = _workspace(self.torch, sz.value, self.problem.device)
-        _check(lib.mhar_precond_create(self.handle, int(rank), ptr, nbytes, self.stream))
+        _check(lib.mhar_precond_create(self.handle, int(rank), fit, ptr, nbytes, self.stream))
         self.rank = int(rank)
+        self.objective = objective
 
     def precond_set(self, U, log_sigma):
         t = self.torch
