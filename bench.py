@@ -1,18 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the MHAR step on one MI355X.
 
-Workload (single-GPU configuration of the headline metric): random
-full-dimensional polytope, n = 100, m = 2000 unit-norm Gaussian rows, b = 1
-(contains the unit ball), z = 1024 walks started at the origin, exact FP64
-slack recompute every 50 steps, A*D on the matrix cores in FP32 and in the
-BF16x3 split (the faster of the two is reported, the other is listed).
+Headline workload (the configuration the metric's learned-vs-plain comparison
+is quoted on): rotated box n = 1000 with sides log-uniform in [1e-3, 1]
+(rows [Q^T; -Q^T], Q Haar) plus 8000 unit-norm Gaussian halfspaces at
+distance 1, m = 10000, z = 8192 walks from the centre, exact FP64 slack
+recompute every 50 steps.  Two samplers on the same seed:
+  * plain: isotropic directions (the paper's MHAR);
+  * learned: rank-64 + diagonal direction covariance fitted for 500 burn-in
+    steps to the Dikin ellipsoid at the mean walk state, then frozen.
+The screening product A*D runs on the matrix cores in BF16x3 and in FP32
+(both give the FP64 chord, hence the same trajectories); the faster is
+reported.
 
 A "step" is one MHAR iteration of all z walks (directions, screening
-product, exact chords, update).  value = z * steps / seconds (chain-steps/s,
-the paper's samples per second with no thinning).  Inputs are resident in
-HBM before timing starts.  Also reported:
-  * roofline of the step kernel from HIP events around every launch;
-  * min-marginal ESS/s from a bitwise-identical recorded replay of 64 walks;
+product, exact chords, update).  value = z * steps / seconds of the learned
+sampler over exactly --steps steps (chain-steps/s, the paper's samples per
+second with no thinning), inputs resident in HBM, the window placed so that
+it ends with an exact recompute.  Also reported per sampler:
+  * min-marginal ESS/s over a 5000-step window after burn-in (64 walks
+    recorded in a bitwise-identical replay, every 5th step), with the largest
+    split R-hat and the largest marginal KS distance to exact samples;
+  * roofline of the dominant kernel (the screening GEMM) from HIP events
+    around each of its launches;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
 """
 import argparse
@@ -68,6 +78,32 @@ def measured_traffic(precision, launch_steps):
     if precision != t["precision"] or launch_steps != t["steps_per_launch"]:
         return None
     if sources_sha256() != t["sources_sha256"]:
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
+# HBM traffic of the headline's screening GEMM per launch (one launch per step),
+# from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch) scaled by what the counters read for a plain device copy in the
+# same run; None until measured, and null once the kernel's sources change.
+TRAFFIC_ROTBOX = None
+TRAFFIC_ROTBOX_SOURCES = ["paper_2104_07097_amd/csrc/mhar_kernels.hip",
+                          "paper_2104_07097_amd/csrc/mhar_device.hpp",
+                          "paper_2104_07097_amd/csrc/mhar_internal.hpp",
+                          "paper_2104_07097_amd/build.py"]
+
+
+def measured_traffic_rotbox(precision):
+    import hashlib
+    t = TRAFFIC_ROTBOX
+    if t is None or t["precision"] != precision:
+        return None
+    h = hashlib.sha256()
+    for rel in TRAFFIC_ROTBOX_SOURCES:
+        h.update(rel.encode())
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sources_sha256"]:
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
@@ -250,71 +286,193 @@ def bench_batched(args):
     return line
 
 
-def bench_rotbox(args):
-    """Learned rank-r + diagonal covariance vs isotropic directions (same seed,
-    same steps): min-marginal ESS/s over a recorded window, plus the max marginal
-    KS distance of the final states to exact samples (equal accuracy check)."""
+def _host():
+    model = "?"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def cpu_baseline_rotbox(p, U, ls, seconds, walks=64):
+    """The oracle as it stands on the headline workload with the learned
+    covariance, on `walks` of the walks (independent, so the rate scales)."""
+    import oracle
+    orc = oracle.Oracle()
+    model, ncpu = _host()
+    threads = min(16, ncpu)
+    X0 = p.X0[:walks]
+    t0 = time.perf_counter()
+    X, _, _ = orc.run(p.A, p.b, X0, 1, seed=0, U=U, log_sigma=ls, threads=threads)
+    one = time.perf_counter() - t0
+    k = int(max(1, min(1000, seconds / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    orc.run(p.A, p.b, X, k, seed=0, step0=1, U=U, log_sigma=ls, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": walks * k / dt, "unit": "chain-steps/s", "cores": threads, "kind": "oracle",
+            "host": f"{model}, {ncpu} logical CPUs",
+            "sample": f"{walks} of the {p.z} walks (walks are independent, the rate scales with "
+                      f"their number), steps 1..{k} from the centre with the learned covariance "
+                      f"(FP64, slack recomputed every step), {dt:.1f} s on {threads} threads"}
+
+
+def _exact_rotbox(p, Q, sides, count, seed=77):
+    """Uniform samples of the rotated box cut by the halfspaces: uniform in the
+    box, rotated, then rejected by the extra rows (acceptance ~ 1)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    Y = rng.uniform(-0.5, 0.5, size=(count, p.n)) * sides[None, :]
+    X = Y @ Q.T
+    return X[np.all(X @ p.A.T <= p.b, axis=1)]
+
+
+def bench_headline(args):
+    """Learned vs plain MHAR on the rotated box (see the module docstring)."""
     import numpy as np
     import torch
     from paper_2104_07097_amd import instances as inst
-    from paper_2104_07097_amd.stats import ks_two_sample, min_marginal_ess
+    from paper_2104_07097_amd.stats import ks_two_sample, max_marginal_rhat, min_marginal_ess
     p, Q, sides = inst.rotbox()
-    steps = args.steps if args.steps != 5000 else 1000
-    rec_chains = 64
-    rng = np.random.default_rng(77)
-    Yr = rng.uniform(-0.5, 0.5, size=(p.z, p.n)) * sides[None, :]
-    exact = Yr @ Q.T
-    exact = exact[np.all(exact @ p.A.T <= p.b, axis=1)]
-    out = {}
+    R, K, W = 50, max(1, args.steps), max(20, args.ess_steps)
+    rec_chains, stride = 64, max(1, args.ess_stride)
+    flops_per_step = 2.0 * p.m * p.n * p.z
+    exact = _exact_rotbox(p, Q, sides, p.z)
+    dev = torch.device("cuda:0")
+    out, fits = {}, {}
     for mode in ("plain", "learned"):
-        prob, ch = _make(p, "bf16x3")
+        handles = {prec: _make(p, prec, recompute_every=R) for prec in ("bf16x3", "fp32")}
+        prob, ch = handles["bf16x3"]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        align = None
         if mode == "learned":
-            ch.precond_create(args.rank)
-            ch.precond_train(args.burnin, 0.05)
+            ch.precond_create(args.rank, "dikin")
+            ch.precond_train(args.burnin, 0.5)
             ch.precond_freeze()
         else:
             ch.step(args.burnin)
+        ch.step(args.warmup)
         torch.cuda.synchronize()
         burn = time.perf_counter() - t0
+        res = {"burnin_s": burn, "burnin_steps": args.burnin, "warmup_steps": args.warmup}
         if mode == "learned":
-            # what the fit learned: share of the trace of Sigma along the true
-            # longest `rank` axes (isotropic directions give rank / n)
             U, ls = (v.cpu().numpy() for v in ch.precond_get())
+            fits = {"U": U, "ls": ls}
+            Sig_top = Q[:, np.argsort(sides)[::-1][:args.rank]]
             Sig = U @ U.T + np.diag(np.exp(2.0 * ls))
-            top = Q[:, np.argsort(sides)[::-1][:args.rank]]
-            align = float(np.trace(top.T @ Sig @ top) / np.trace(Sig))
-        start, _ = ch.state()
-        sec = _timed_steps(ch, steps)
-        Xend, _ = ch.state()
-        # replay the measured window (same seed, same start) recording 64 walks
-        ch.set_state(start, args.burnin)
-        rec = ch.record(steps, 1, rec_chains).cpu().numpy()
-        Xrep, _ = ch.state()
-        ess, _ = min_marginal_ess(rec)
+            res["sigma_share_on_true_top_axes"] = float(np.trace(Sig_top.T @ Sig @ Sig_top) / np.trace(Sig))
+            res["isotropic_share"] = args.rank / p.n
+            res["fit"] = "Dikin ellipsoid at the mean walk state, rank %d + diagonal" % args.rank
+        S0, _ = ch.state()
+        P0 = ch.step_count()
+        # every precision from the same state: the exact recompute of set_state
+        # restarts the schedule, then the window is placed to end with a recompute
+        align = (-K) % R
+        variants = {}
+        for prec, (pb, cb) in handles.items():
+            if prec != "bf16x3" and mode == "learned":
+                dv = lambda a: torch.tensor(a, device=dev)
+                cb.precond_create(args.rank, "dikin")
+                cb.precond_set(dv(fits["U"]), dv(fits["ls"]))
+                cb.precond_freeze()
+            cb.set_state(S0, P0)
+            cb.step(align)
+            rec0 = cb.stats()["recomputes"]
+            cb.trace_enable(4 * K + 8)
+            sec = _timed_steps(cb, K)
+            tr = cb.trace_read()
+            cb.trace_enable(0)
+            st = cb.stats()
+            variants[prec] = {"chain_steps_per_sec": p.z * K / sec, "ms_per_step": sec * 1e3 / K,
+                              "recomputes_in_window": st["recomputes"] - rec0,
+                              "kernel": KERNEL_PATHS.get(st["kernel"], "?"), "trace": tr,
+                              "flags": cb.sync()}
+            log(f"[bench] {mode} {prec}: {sec * 1e3 / K:.3f} ms/step, "
+                f"{p.z * K / sec / 1e6:.2f} M chain-steps/s, screening GEMM "
+                f"{tr['screen']['ms'] / max(1, tr['screen']['launches']):.3f} ms/launch")
+        best = max(variants, key=lambda k: variants[k]["chain_steps_per_sec"])
+        res["variants"] = variants
+        res["best_precision"] = best
+        res["chain_steps_per_sec"] = variants[best]["chain_steps_per_sec"]
+        res["ms_per_step"] = variants[best]["ms_per_step"]
+        # ESS window on the faster precision: timed unrecorded, then replayed
+        # from the same state with 64 walks recorded (bitwise the same walks)
+        pb, cb = handles[best]
+        start, _ = cb.state()
+        s0 = cb.step_count()
+        sec_w = _timed_steps(cb, W)
+        Xend, st_end = cb.state()
+        cb.set_state(start, s0)
+        rec = cb.record(W, stride, rec_chains)
+        Xrep, _ = cb.state()
+        samples = rec.cpu().numpy()
+        del rec
+        ess, per = min_marginal_ess(samples)
         ess *= p.z / rec_chains
+        rhat = max_marginal_rhat(samples)
         Xe = Xend.cpu().numpy()
-        ks = max(ks_two_sample(Xe[:, j], exact[:, j]) for j in range(0, p.n, 10))
-        out[mode] = {"chain_steps_per_sec": p.z * steps / sec, "ms_per_step": sec * 1e3 / steps,
-                     "min_marginal_ess": ess, "min_marginal_ess_per_sec": ess / sec,
-                     "burnin_s": burn, "max_marginal_ks_vs_exact": ks,
-                     "replay_bitwise_identical": bool(torch.equal(Xrep, Xend)),
-                     "flags": ch.sync()}
-        if align is not None:
-            out[mode]["sigma_share_on_true_top_axes"] = align
-            out[mode]["isotropic_share"] = args.rank / p.n
-        ch.close()
-        prob.close()
-    line = _base_line(out["learned"]["chain_steps_per_sec"], steps, args.burnin,
-                      steps / out["learned"]["chain_steps_per_sec"] * p.z, "bf16x3",
-                      {"workload": "rotated box n=1000 (sides log-uniform in [1e-3,1]) + 8000 "
-                                   "unit-norm halfspaces at distance 1, z=8192 from the centre",
-                       "rank": args.rank, "burnin": args.burnin, "window_steps": steps})
+        ks = max(ks_two_sample(Xe[:, j], exact[:, j]) for j in range(p.n))
+        feasible = bool(np.all(Xe @ p.A.T <= p.b + 1e-12 * np.maximum(1.0, np.abs(p.b))))
+        res.update({
+            "window": {"steps": W, "recorded_every": stride, "walks_recorded": rec_chains,
+                       "first_step": s0, "ms_per_step": sec_w * 1e3 / W,
+                       "replay_bitwise_identical": bool(torch.equal(Xrep, Xend))},
+            "min_marginal_ess": ess, "median_marginal_ess": float(np.median(per)) * p.z / rec_chains,
+            "min_marginal_ess_per_sec": ess / sec_w,
+            "max_split_rhat": rhat,
+            "min_marginal_ess_per_sec_gated": ess / sec_w if rhat <= 1.01 else None,
+            "gate": "split R-hat <= 1.01 over every coordinate" + (
+                "" if rhat <= 1.01 else f" fails (max {rhat:.3f}): the walks have not mixed in the window"),
+            "max_marginal_ks_vs_exact": ks, "exact_samples": int(len(exact)),
+            "feasible": feasible, "flags": cb.sync() | int(st_end.abs().sum().item() != 0)})
+        log(f"[bench] {mode}: ESS {ess:.0f} ({ess / sec_w:.0f}/s), max R-hat {rhat:.3f}, "
+            f"max KS {ks:.3f}, feasible {feasible}")
+        out[mode] = res
+        for pb, cb in handles.values():
+            cb.close()
+            pb.close()
+        del handles, start, Xend, Xrep, S0
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    L = out["learned"]
+    best = L["best_precision"]
+    tr = L["variants"][best]["trace"]["screen"]
+    avg = tr["ms"] / max(1, tr["launches"]) / 1e3
+    achieved = flops_per_step / avg / 1e12
+    peak = PEAK_TFLOPS["bf16x3" if best == "bf16x3" else "fp32"]
+    line = _base_line(L["chain_steps_per_sec"], K, args.warmup, L["ms_per_step"] * K / 1e3,
+                      f"f64 chord, {best} screening",
+                      {"workload": "rotated box n=1000 (sides log-uniform in [1e-3,1], Haar rotation) "
+                                   "+ 8000 unit-norm halfspaces at distance 1 (m=10000), z=8192 walks "
+                                   "from the centre; learned rank-64 + diagonal direction covariance "
+                                   "(Dikin fit, 500 burn-in steps, frozen) vs isotropic MHAR",
+                       "n": p.n, "m": p.m, "z": p.z, "rank": args.rank, "burnin": args.burnin,
+                       "recompute_every": R, "timed_window": f"{K} steps ending with an exact recompute"})
+    line["roofline"] = {
+        "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "frac": achieved / peak, "traffic": measured_traffic_rotbox(best),
+        "kernel": f"tiled_screen_kernel<{best}> (screening GEMM A*D, fused slack update and ratio bounds)",
+        "flops_per_launch": flops_per_step, "avg_launch_ms": avg * 1e3,
+        "launches_timed": tr["launches"],
+        "fp32_equivalent_frac": achieved / PEAK_TFLOPS["fp32"],
+        "note": "algorithmic 2 m n z flop per launch; BF16x3 issues three bf16 products per flop"}
     line["learned_vs_plain"] = out
-    line["ess_gain"] = out["learned"]["min_marginal_ess_per_sec"] / max(
-        out["plain"]["min_marginal_ess_per_sec"], 1e-300)
+    line["ess_per_sec_gain"] = L["min_marginal_ess_per_sec"] / max(out["plain"]["min_marginal_ess_per_sec"], 1e-300)
+    line["ks_learned_vs_plain"] = [L["max_marginal_ks_vs_exact"], out["plain"]["max_marginal_ks_vs_exact"]]
+    if not args.no_secondary:
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup, sub.launch_steps, sub.no_ess, sub.no_cpu_baseline = 1000, 200, 500, True, True
+        r2 = bench_randpoly(sub)
+        line["secondary"] = {"workload": r2["config"]["workload"], "value": r2["value"],
+                             "unit": r2["unit"], "ms_per_step": r2["ms_per_step"], "dtype": r2["dtype"],
+                             "roofline_frac": r2["roofline"]["frac"]}
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline_rotbox(p, fits["U"], fits["ls"], args.cpu_seconds)
     return line
 
 
@@ -446,26 +604,30 @@ def bench_fr(args):
 
 
 OTHER_WORKLOADS = {"cube10": bench_cube10, "simplex_cut": bench_simplex_cut,
-                   "batched": bench_batched, "rotbox": bench_rotbox, "table5": bench_table5,
-                   "fr": bench_fr}
+                   "batched": bench_batched, "table5": bench_table5, "fr": bench_fr}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200,
+                    help="timed steps (headline: learned sampler, after burn-in and warm-up)")
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", choices=["auto", "fp32", "bf16x3", "fp64"], default="auto")
     ap.add_argument("--launch-steps", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true")
-    ap.add_argument("--workload", default="randpoly",
-                    choices=["randpoly", "cube10", "simplex_cut", "batched", "rotbox", "table5", "fr"],
-                    help="randpoly (default) is the single-GPU configuration of the headline "
-                         "metric; the others are the remaining configurations")
+    ap.add_argument("--workload", default="rotbox",
+                    choices=["rotbox", "randpoly", "cube10", "simplex_cut", "batched", "table5", "fr"],
+                    help="rotbox (default) is the configuration of the headline metric "
+                         "(learned vs plain); the others are the remaining configurations")
     ap.add_argument("--rank", type=int, default=64, help="rotbox: rank of the learned covariance")
     ap.add_argument("--burnin", type=int, default=500, help="rotbox: burn-in (training) steps")
+    ap.add_argument("--ess-steps", type=int, default=5000, help="rotbox: measured ESS window")
+    ap.add_argument("--ess-stride", type=int, default=5, help="rotbox: recording stride of the window")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="rotbox: skip the short random-polytope line")
     ap.add_argument("--fr-sims", type=int, default=3, help="fr: simulations per (figure, n)")
     ap.add_argument("--table5-seconds", type=float, default=0.25,
                     help="table5: timed seconds per (row, precision)")
@@ -485,10 +647,17 @@ def main():
     if not torch.cuda.is_available():
         log("bench.py needs a HIP device")
         sys.exit(1)
-    if args.workload != "randpoly":
-        line = OTHER_WORKLOADS[args.workload](args)
-        print(json.dumps(line), flush=True)
-        return
+    line = WORKLOADS[args.workload](args)
+    print(json.dumps(line), flush=True)
+    release_device()
+
+
+def bench_randpoly(args):
+    """Random polytope n = 100, m = 2000, z = 1024 (plain MHAR), both screening
+    precisions in launches of --launch-steps steps."""
+    import numpy as np
+    import torch
+    from paper_2104_07097_amd import instances as inst
     launch_steps = max(1, min(args.launch_steps, args.steps))
     steps = (args.steps // launch_steps) * launch_steps
     p = inst.randpoly()  # n=100, m=2000, z=1024
@@ -516,7 +685,7 @@ def main():
     r = results[best]
     value = p.z * steps / r["gpu_time"]
     avg_launch = float(np.mean(r["per_launch"]))
-    flops_per_launch = 2.0 * p.m * p.n * p.z * launch_steps * MFMA_PER_FLOP[best]
+    flops_per_launch = 2.0 * p.m * p.n * p.z * launch_steps   # algorithmic 2 m n z per step
     achieved = flops_per_launch / avg_launch / 1e12
     line = {
         "metric": METRIC,
@@ -542,7 +711,9 @@ def main():
                      "kernel": KERNEL_NAMES.get(r["stats"]["kernel"], "?")
                                + f"<{best}>, {r['stats']['split']} workgroups per 16-walk tile",
                      "avg_launch_ms": avg_launch * 1e3,
-                     "flops_per_launch": flops_per_launch},
+                     "flops_per_launch": flops_per_launch,
+                     "matrix_core_products_per_flop": MFMA_PER_FLOP[best],
+                     "note": "whole-step launch time (directions, exact chords and update included)"},
         "wall_s": sum(results[k]["wall"] for k in precs),
         "feasible": all(results[k]["feasible"] for k in precs),
         "flags": {k: results[k]["flags"] for k in precs},
@@ -563,7 +734,21 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
-    print(json.dumps(line), flush=True)
+    return line
+
+
+def release_device():
+    """Free the device memory torch holds and wait for the device, so that no
+    HIP work is left for interpreter teardown (after a profiler's own
+    finalisation)."""
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+WORKLOADS = dict(OTHER_WORKLOADS, randpoly=bench_randpoly, rotbox=bench_headline)
 
 
 if __name__ == "__main__":

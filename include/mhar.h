@@ -221,6 +221,24 @@ mhar_status_t mhar_get_stats(mhar_chains_t chains, void* stream, mhar_stats_t* s
 
 mhar_status_t mhar_chains_destroy(mhar_chains_t chains);
 
+/* Kernel timing of the tiled path (paper S4.4-S4.5 split over its kernels):
+ * with tracing enabled, every launch of the screening GEMM, the chords
+ * kernel, the directions kernel and the exact recompute that mhar_step
+ * enqueues on the tiled path is bracketed by a pair of HIP events on the
+ * step stream, up to max_launches launches (later launches are not timed).
+ * Other paths run many steps per launch; time them with events around
+ * mhar_step.  The events are created by mhar_trace_enable (max_launches = 0
+ * releases them) and by nothing else; mhar_chains_destroy releases them. */
+typedef struct {
+    int64_t launches[4];   /* 0 screening GEMM, 1 chords, 2 directions, 3 exact recompute */
+    double ms[4];          /* summed event-to-event durations, milliseconds */
+} mhar_trace_t;
+mhar_status_t mhar_trace_enable(mhar_chains_t chains, int32_t max_launches);
+
+/* Synchronise `stream`, sum the durations recorded since enable or the last
+ * read per kernel kind into *out, and start a new record. */
+mhar_status_t mhar_trace_read(mhar_chains_t chains, void* stream, mhar_trace_t* out);
+
 /* ---------------------------------------------------------------------- */
 /* Learned direction covariance (burn-in only; not in the paper)          */
 /* ---------------------------------------------------------------------- */

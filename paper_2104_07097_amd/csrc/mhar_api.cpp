@@ -62,7 +62,13 @@ struct mhar_chains {
     int64_t pc_t;       // Adam step counter
     int split_saved;    // kernel choice before the covariance was attached
     int force_recompute;
+    int pc_lr_stale;    // tiled path: A P U must be recomputed before the next step
+    float pc_eps_g;     // error coefficient of the split screening (n + rank terms)
     PrecondBufs pc;
+    // kernel timing of the tiled path (mhar_trace_enable)
+    KernelTrace trace{nullptr, nullptr, 0, 0};
+    std::vector<hipEvent_t> trace_events;
+    std::vector<int> trace_kinds;
 };
 
 struct mhar_batch {
@@ -290,6 +296,21 @@ StepArgs make_args(const mhar_chains* c)
     a.r = c->pc_rank;
     a.U = c->pc_rank ? c->pc.U : nullptr;
     a.esig = c->pc_rank ? c->pc.esig : nullptr;
+    a.prec = p->prec;
+    a.rk = 0;
+    if (c->pc_rank && c->tiled) {
+        // split screening: A d = A P (exp(l) o h) + (A P U) eps
+        a.rk = c->pc.rk;
+        a.AUop = c->pc.AUop;
+        a.aun = c->pc.aun;
+        a.Eop = c->pc.Eop;
+        a.Hs = c->pc.Hs;
+        a.hn = c->pc.hn;
+        a.en = c->pc.en;
+        a.F = c->pc.F;
+        a.uF = c->pc.uF;
+        a.eps_g = c->pc_eps_g;
+    }
     a.gU = c->gU;
     a.gL = c->gL;
     a.gbar = c->gbar;
@@ -348,7 +369,7 @@ hipError_t launch_any(mhar_chains* c, const StepArgs& a, hipStream_t stream)
         return launch_lane(a, stream);
     }
     c->last_kernel = c->tiled ? MHAR_PATH_TILED : c->split > 0 ? MHAR_PATH_RESIDENT : MHAR_PATH_GENERAL;
-    if (c->tiled) return launch_tiled(c->p->prec, a, stream);
+    if (c->tiled) return launch_tiled(c->p->prec, a, stream, c->trace.cap > 0 ? &c->trace : nullptr);
     if (c->split <= 0) return launch_steps(c->p->prec, a, stream);
     if (c->split > 1) {
         // fresh exchange slots and arrival counters for this launch
@@ -364,10 +385,19 @@ hipError_t launch_any(mhar_chains* c, const StepArgs& a, hipStream_t stream)
 
 // run `steps` steps (and the optional leading recompute), in launches of at
 // most steps_per_launch steps each
+// A P U of the split screening after the covariance changed
+hipError_t refresh_lowrank(mhar_chains* c, hipStream_t stream)
+{
+    if (!(c->pc_rank && c->tiled && c->pc_lr_stale)) return hipSuccess;
+    c->pc_lr_stale = 0;
+    return launch_lowrank_setup(c->pc, stream);
+}
+
 mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, double* rec_out,
                         int64_t stride, int64_t rec_chains, hipStream_t stream)
 {
     const mhar_problem* p = c->p;
+    MHAR_HIP(refresh_lowrank(c, stream), "low-rank screening operand");
     int64_t chunk = p->steps_per_launch > 0 ? p->steps_per_launch : auto_chunk(p);
     int64_t done = 0;
     if (c->force_recompute) {
@@ -702,6 +732,15 @@ mhar_status_t mhar_get_stats(mhar_chains_t c, void* stream, mhar_stats_t* stats)
     return MHAR_OK;
 }
 
+// covariance workspace: the fit's buffers, then (tiled path) the split screening's
+static size_t precond_total_bytes(const mhar_chains* c, int32_t rank, int32_t objective)
+{
+    const mhar_problem* p = c->p;
+    size_t b = precond_bytes(p->n, rank, c->z, p->lda, objective, p->m_pad);
+    if (c->tiled) b = (size_t)round_up((int64_t)b, 256) + lowrank_bytes(p->prec, p->n, rank, p->m_pad, p->lda, c->z_pad, p->m_eq);
+    return b;
+}
+
 static mhar_status_t check_fit(const mhar_chains* c, int32_t rank, int32_t objective)
 {
     if (rank < 1 || rank > kMaxMeq) return fail(MHAR_E_SHAPE, "rank must be in [1, 64]");
@@ -718,7 +757,7 @@ mhar_status_t mhar_precond_workspace_size(mhar_chains_t c, int32_t rank, int32_t
     if (!c || !bytes) return fail(MHAR_E_INVALID_ARG, "chains and bytes must be non-NULL");
     mhar_status_t st = check_fit(c, rank, objective);
     if (st) return st;
-    *bytes = precond_bytes(c->p->n, rank, c->z, c->p->lda, objective, c->p->m_pad);
+    *bytes = precond_total_bytes(c, rank, objective);
     return MHAR_OK;
 }
 
@@ -730,7 +769,7 @@ mhar_status_t mhar_precond_create(mhar_chains_t c, int32_t rank, int32_t objecti
     mhar_status_t st = check_fit(c, rank, objective);
     if (st) return st;
     if (!ws || !aligned256(ws)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < precond_bytes(c->p->n, rank, c->z, c->p->lda, objective, c->p->m_pad))
+    if (ws_bytes < precond_total_bytes(c, rank, objective))
         return fail(MHAR_E_WORKSPACE, "precond workspace too small");
     c->pc = PrecondBufs{};
     c->pc.n = c->p->n;
@@ -742,7 +781,19 @@ mhar_status_t mhar_precond_create(mhar_chains_t c, int32_t rank, int32_t objecti
     c->pc.m_pad = c->p->m_pad;
     c->pc.A64 = c->p->A64;
     c->pc.b64 = c->p->b64;
+    c->pc.prec = c->p->prec;
+    c->pc.m_eq = c->p->m_eq;
+    c->pc.z_pad = c->z_pad;
+    c->pc.Aeq = c->p->Aeq;
+    c->pc.WT = c->p->WT;
     precond_carve(&c->pc, ws);
+    if (c->tiled) {
+        const size_t off = (size_t)round_up(
+            (int64_t)precond_bytes(c->p->n, rank, c->z, c->p->lda, objective, c->p->m_pad), 256);
+        lowrank_carve(&c->pc, (char*)ws + off);
+    }
+    c->pc_eps_g = eps_for(c->p->prec, c->p->n + rank);
+    c->pc_lr_stale = 1;
     MHAR_HIP(launch_precond_init(c->pc, c->seed, (hipStream_t)stream), "covariance init");
     if (objective == MHAR_FIT_DIKIN)
         MHAR_HIP(launch_dikin_init(c->pc, c->seed, (hipStream_t)stream), "covariance init");
@@ -769,6 +820,7 @@ mhar_status_t mhar_precond_set(mhar_chains_t c, const double* U, const double* l
     MHAR_HIP(launch_fill_i32((int*)c->pc.m2l, (int64_t)c->pc.n * 2, 0, s), "moment reset");
     MHAR_HIP(launch_precond_set_scales(c->pc, s), "covariance scale");
     c->pc_t = 0;
+    c->pc_lr_stale = 1;
     return MHAR_OK;
 }
 
@@ -816,6 +868,7 @@ mhar_status_t mhar_precond_train(mhar_chains_t c, int64_t steps, double lr, void
             MHAR_HIP(launch_precond_grad(c->pc, c->X, s), "covariance gradient");
             MHAR_HIP(launch_precond_adam(c->pc, c->pc_t, lr, 0.9, 0.999, 1e-8, s), "covariance update");
         }
+        c->pc_lr_stale = 1;
     }
     return MHAR_OK;
 }
@@ -1006,6 +1059,7 @@ mhar_status_t mhar_batch_step(mhar_batch_t b, int64_t steps, void* stream_)
         if (b->copy_pending) MHAR_HIP(hipEventSynchronize(b->copied), "descriptor buffer reuse");
         for (int i = 0; i < b->count; ++i) {
             mhar_chains* c = b->chains[i];
+            MHAR_HIP(refresh_lowrank(c, stream), "low-rank screening operand");
             int rf = 0;
             if (c->force_recompute) {
                 rf = 1;
@@ -1070,10 +1124,57 @@ mhar_status_t mhar_batch_destroy(mhar_batch_t b)
     return MHAR_OK;
 }
 
+static void trace_release(mhar_chains* c)
+{
+    for (hipEvent_t e : c->trace_events) (void)hipEventDestroy(e);
+    c->trace_events.clear();
+    c->trace_kinds.clear();
+    c->trace = KernelTrace{nullptr, nullptr, 0, 0};
+}
+
+mhar_status_t mhar_trace_enable(mhar_chains_t c, int32_t max_launches)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (max_launches < 0 || max_launches > (1 << 20))
+        return fail(MHAR_E_INVALID_ARG, "max_launches must be in [0, 2^20]");
+    trace_release(c);
+    if (max_launches == 0) return MHAR_OK;
+    c->trace_events.resize(2 * (size_t)max_launches);
+    for (size_t i = 0; i < c->trace_events.size(); ++i) {
+        hipError_t e = hipEventCreate(&c->trace_events[i]);
+        if (e != hipSuccess) {
+            c->trace_events.resize(i);
+            trace_release(c);
+            return hip_fail(e, "trace event create");
+        }
+    }
+    c->trace_kinds.assign((size_t)max_launches, 0);
+    c->trace = KernelTrace{c->trace_events.data(), c->trace_kinds.data(), max_launches, 0};
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_trace_read(mhar_chains_t c, void* stream, mhar_trace_t* out)
+{
+    if (!c || !out) return fail(MHAR_E_INVALID_ARG, "chains and out must be non-NULL");
+    if (c->trace.cap == 0) return fail(MHAR_E_STATE, "tracing is not enabled");
+    MHAR_HIP(hipStreamSynchronize((hipStream_t)stream), "stream synchronize");
+    *out = mhar_trace_t{};
+    for (int i = 0; i < c->trace.used; ++i) {
+        float ms = 0.0f;
+        MHAR_HIP(hipEventElapsedTime(&ms, c->trace.ev[2 * i], c->trace.ev[2 * i + 1]), "trace read");
+        const int k = c->trace.kind[i];
+        out->launches[k] += 1;
+        out->ms[k] += ms;
+    }
+    c->trace.used = 0;
+    return MHAR_OK;
+}
+
 mhar_status_t mhar_chains_destroy(mhar_chains_t c)
 {
     if (!c) return MHAR_OK;
     c->p->live_chains -= 1;
+    trace_release(c);
     delete c;
     return MHAR_OK;
 }

@@ -43,6 +43,7 @@ inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 struct StepArgs {
     // problem
     int n, m, m_pad, lda, m_eq;
+    int prec;               // Prec of the screening operands
     const double* A64;      // m_pad x lda, zero padded
     const float* A32;       // m_pad x lda (FP32 mode)
     const __bf16* Ahi;      // m_pad x lda (BF16X3 mode)
@@ -62,6 +63,18 @@ struct StepArgs {
     int r;
     const double* U;        // n x r
     const double* esig;     // n, exp(log_sigma)
+    // tiled path with a learned covariance: the screening product is split as
+    // A d = A P (exp(l) o h) + (A P U) eps, a contraction over lda + rk columns
+    // whose error bound follows each part's norms (rk = 0: not split)
+    int rk;                 // r rounded up to 32
+    const void* AUop;       // m_pad x rk operand of A P U (FP32, or bf16 hi then lo)
+    const float* aun;       // m_pad, ||(A P U)_i|| rounded up
+    void* Eop;              // z_pad x rk operand of eps (FP32, or bf16 hi then lo)
+    double* Hs;             // z_pad x lda, the isotropic part P (exp(l) o h) in FP64
+    double* hn;             // z_pad, ||P (exp(l) o h)||
+    double* en;             // z_pad, ||eps||
+    double* F;              // z_pad, drift coefficient of the low-rank part of the slack
+    const double* uF;       // ||U||_F (one value)
     // chains
     int z, z_pad;
     double* X;              // z_pad x lda
@@ -113,7 +126,17 @@ hipError_t launch_resident(int prec, const StepArgs& a, hipStream_t stream);
 hipError_t launch_steps(int prec, const StepArgs& a, hipStream_t stream);
 // tiled path for large problems (FP32 / BF16X3): per step a screening GEMM and
 // a chords + directions kernel, and an FP64 recompute GEMM every R steps
-hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream);
+// Optional kernel timing of the tiled path: an event pair around each launch
+// (up to cap launches), with the kind of kernel of each pair.
+enum TraceKind { kTraceScreen = 0, kTraceChords = 1, kTraceDirs = 2, kTraceRecompute = 3,
+                 kTraceKinds = 4 };
+struct KernelTrace {
+    hipEvent_t* ev;   // 2 * cap events
+    int* kind;        // cap
+    int cap, used;
+};
+hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream,
+                        KernelTrace* trace = nullptr);
 // the tiled path over many problems at once: per step one grouped screening
 // launch over the tile table, one grouped chords launch over the 16-walk
 // units and, after the steps flagged in `due` (host array of `steps`), one
@@ -165,6 +188,14 @@ struct PrecondBufs {
     int m, m_pad, N;
     const double *A64, *b64;
     double *Hm, *Lm, *wrow, *pv, *py0, *py1, *dsq, *HU, *Ysol, *lam;
+    // split screening of the tiled path (StepArgs::rk): A P U in operand form
+    // and its row norms, P U (FP64, m_eq > 0), ||U||_F, and per walk the
+    // isotropic part of the direction, its norm, ||eps||, the low-rank drift
+    int rk, prec, m_eq, z_pad;
+    void *AUop, *Eop;
+    float* aun;
+    double *PU, *uF, *Hs, *hn, *en, *F, *AeqU;
+    const double *Aeq, *WT;
 };
 size_t precond_bytes(int n, int r, int z, int lda, int objective, int m_pad);
 void precond_carve(PrecondBufs* p, void* ws);
@@ -176,6 +207,10 @@ hipError_t launch_precond_adam(const PrecondBufs& p, int64_t t, double lr, doubl
 hipError_t launch_precond_mean(const PrecondBufs& p, const double* X, hipStream_t stream);
 hipError_t launch_precond_w(const PrecondBufs& p, hipStream_t stream);
 hipError_t launch_precond_capacitance(const PrecondBufs& p, hipStream_t stream);
+// split screening: workspace bytes, carving, and A P U / ||U||_F after U changed
+size_t lowrank_bytes(int prec, int n, int r, int m_pad, int lda, int z_pad, int m_eq);
+void lowrank_carve(PrecondBufs* p, void* ws);
+hipError_t launch_lowrank_setup(const PrecondBufs& p, hipStream_t stream);
 // Dikin fit (mhar_dikin.hip)
 constexpr int kDikinPowerIters = 4;   // power iterations per training step
 int dikin_order(int n);

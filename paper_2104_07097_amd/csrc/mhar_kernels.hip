@@ -32,6 +32,9 @@ struct ChainLds {
     double theta[kChainTile];
     double E[kChainTile];
     double dnorm[kChainTile];
+    double hnorm[kChainTile];   // split screening: ||isotropic part||, ||eps||, low-rank drift
+    double enorm[kChainTile];
+    double F[kChainTile];
     double y[kChainTile * kMaxMeq];
     unsigned up[kChainTile];
     unsigned um[kChainTile];
@@ -255,13 +258,43 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
 #pragma unroll
             for (int cl = 0; cl < kChainTile; ++cl) {
                 if (c0 + cl < a.z) {
-                    double* dp = a.D + (size_t)(c0 + cl) * lda + j;
-                    *dp = __dadd_rn(v[cl], __dmul_rn(es, *dp));
+                    const size_t o = (size_t)(c0 + cl) * lda + j;
+                    const double hs = __dmul_rn(es, a.D[o]);
+                    a.D[o] = __dadd_rn(v[cl], hs);
+                    if (a.rk > 0) a.Hs[o] = hs;   // the isotropic part, for the split screening
                 }
             }
         }
+        if (a.rk > 0) {
+            // eps as the second block of the screening operand (zero padded to
+            // rk columns) and its norm, before the projection reuses cs->y
+            __syncthreads();
+            const size_t zr = (size_t)a.z_pad * a.rk;
+            for (int item = tid; item < kChainTile * a.rk; item += kThreads) {
+                const int cl = item / a.rk, q = item - cl * a.rk, chain = c0 + cl;
+                const float v = (chain < a.z && q < a.r) ? (float)eps[cl * kMaxMeq + q] : 0.0f;
+                const size_t o = (size_t)chain * a.rk + q;
+                if (a.prec == kBF16X3) {
+                    __bf16 hi, lo;
+                    split_bf16(v, hi, lo);
+                    ((__bf16*)a.Eop)[o] = hi;
+                    ((__bf16*)a.Eop)[zr + o] = lo;
+                } else {
+                    ((float*)a.Eop)[o] = v;
+                }
+            }
+            for (int cl = wave; cl < kChainTile; cl += kWaves) {
+                double v = 0.0;
+                if (c0 + cl < a.z && lane < a.r) v = eps[cl * kMaxMeq + lane] * eps[cl * kMaxMeq + lane];
+                v = wave_sum(v);
+                if (lane == 0) cs->enorm[cl] = sqrt(v);
+            }
+        }
     }
-    if (a.m_eq > 0) {
+    // projection onto null(A_eq) of the direction and, for the split
+    // screening, of its isotropic part
+    for (int part = 0; part < (a.rk > 0 ? 2 : 1) && a.m_eq > 0; ++part) {
+        double* base = part ? a.Hs : a.D;
         __syncthreads();
         // y = A_eq h for every walk; one wave per (walk, equality row)
         for (int pr = wave; pr < kChainTile * a.m_eq; pr += kWaves) {
@@ -270,7 +303,7 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
             double v = 0.0;
             if (chain < a.z) {
                 const double* er = a.Aeq + (size_t)p * lda;
-                const double* hr = a.D + (size_t)chain * lda;
+                const double* hr = base + (size_t)chain * lda;
                 for (int j = lane; j < n; j += 64) v = fma(er[j], hr[j], v);
             }
             v = wave_sum(v);
@@ -282,23 +315,31 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
             int cl = item / n, j = item - cl * n;
             int chain = c0 + cl;
             if (chain >= a.z) continue;
-            double* dp = a.D + (size_t)chain * lda + j;
+            double* dp = base + (size_t)chain * lda + j;
             double v = *dp;
             for (int p = 0; p < a.m_eq; ++p) v = fma(-a.WT[(size_t)p * lda + j], cs->y[cl * kMaxMeq + p], v);
             *dp = v;
         }
     }
     __syncthreads();
-    // norms of d (wave per walk)
+    // norms of d (wave per walk), and of the isotropic part
     for (int cl = wave; cl < kChainTile; cl += kWaves) {
         int chain = c0 + cl;
-        double v = 0.0;
+        double v = 0.0, w = 0.0;
         if (chain < a.z) {
             const double* dr = a.D + (size_t)chain * lda;
             for (int j = lane; j < n; j += 64) v = fma(dr[j], dr[j], v);
+            if (a.rk > 0) {
+                const double* hr = a.Hs + (size_t)chain * lda;
+                for (int j = lane; j < n; j += 64) w = fma(hr[j], hr[j], w);
+            }
         }
         v = wave_sum(v);
-        if (lane == 0) cs->dnorm[cl] = sqrt(v);
+        w = wave_sum(w);
+        if (lane == 0) {
+            cs->dnorm[cl] = sqrt(v);
+            cs->hnorm[cl] = sqrt(w);
+        }
     }
 }
 
@@ -556,7 +597,16 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
         if (chain >= a.z) continue;
         const float up = __uint_as_float(cs->up[cl]);
         const float um = __uint_as_float(cs->um[cl]);
-        const float ed = (float)(cs->dnorm[cl] * (double)a.eps_g) * kHighGrow + 1e-30f;
+        float ed, ed2 = 0.0f, Fk = 0.0f;
+        if (a.rk > 0) {
+            const double hn = cs->hnorm[cl], en = cs->enorm[cl];
+            const double dx = 0x1.0p-36 * (hn + cs->dnorm[cl] + *a.uF * en);
+            ed = (float)(hn * (double)a.eps_g + dx) * kHighGrow + 1e-30f;
+            ed2 = (float)(en * (double)a.eps_g) * kHighGrow;
+            Fk = (float)cs->F[cl] * kHighGrow;
+        } else {
+            ed = (float)(cs->dnorm[cl] * (double)a.eps_g) * kHighGrow + 1e-30f;
+        }
         const float Ek = (float)cs->E[cl] * kHighGrow;
         unsigned long long nex = 0;
         for (int qb = 0; qb < ngroups; qb += 64) {
@@ -573,8 +623,9 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
                 const size_t idx = frag_index<F64>(tile, Q, row, cl);
                 const float s32 = (float)S[idx], g32 = (float)Gb[idx];
                 const float na = a.rownorm[row];
-                float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
-                float e = na * ed;
+                const float nau = a.rk > 0 ? a.aun[row] : 0.0f;
+                float dl = fmaf(nau, Fk, fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f)));
+                float e = fmaf(nau, ed2, na * ed);
                 if (F64) {
                     dl = fmaf(fabsf(s32), 0x1.0p-23f, dl);
                     e = fmaf(fabsf(g32), 0x1.0p-23f, e);
@@ -667,7 +718,16 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
             const double dn = cs->dnorm[cl], at = fabs(th);
             const double us = (double)a.u_s;
             double E = cs->E[cl];
-            E += at * dn * ((double)a.eps_g + 2.0 * us);
+            if (a.rk > 0) {
+                // the slack update's error, split like the screening bound:
+                // |a| part into E, |a P U| part into F
+                const double hn = cs->hnorm[cl], en = cs->enorm[cl];
+                const double dx = 0x1.0p-36 * (hn + dn + *a.uF * en);
+                E += at * (hn * (double)a.eps_g + dx + 2.0 * us * dn);
+                cs->F[cl] += at * en * (double)a.eps_g;
+            } else {
+                E += at * dn * ((double)a.eps_g + 2.0 * us);
+            }
             E += 2.0 * u64 * (sqrt(xo) + at * dn);
             E += us * (1.0 + 0x1.0p-20) * sqrt(xn2);
             cs->E[cl] = E;
@@ -948,16 +1008,48 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     }
     const int esz = 16 / F::per16;   // bytes per element
     const int nk = lda / kTK;
+    // split screening: after the lda columns of A and the direction operand,
+    // rk more columns of A P U and eps (the chunks keep their row and part)
+    const int nk_all = nk + a.rk / kTK;
+    auto retarget = [&]() __attribute__((always_inline)) {
+        const int rk = a.rk;
+        const size_t mr = (size_t)a.m_pad * rk, zr = (size_t)a.z_pad * rk;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int u = tid + i * kThreads;
+            if (u < kAChunks) {
+                const int plane = u / (kTR * kChunkRow), rem = u - plane * kTR * kChunkRow;
+                const int row = rem / kChunkRow, part = rem - row * kChunkRow;
+                const size_t off = (size_t)(ok[i] ? R0 + row : 0) * rk + part * F::per16;
+                if (P == kBF16X3)
+                    src[i] = (const unsigned char*)((const __bf16*)a.AUop + plane * mr + off);
+                else
+                    src[i] = (const unsigned char*)((const float*)a.AUop + off);
+            } else {
+                const int v = u - kAChunks;
+                const int plane = v / (kTW * kChunkRow), rem = v - plane * kTW * kChunkRow;
+                const int row = rem / kChunkRow, part = rem - row * kChunkRow;
+                const size_t off = (size_t)(ok[i] ? C0 + row : 0) * rk + part * F::per16;
+                if (P == kBF16X3)
+                    src[i] = (const unsigned char*)((const __bf16*)a.Eop + plane * zr + off);
+                else
+                    src[i] = (const unsigned char*)((const float*)a.Eop + off);
+            }
+        }
+    };
     // K-steps are fetched kDepth ahead into a ring of register buffers (K-step
     // k in slot k % kDepth) and deposited into the LDS stage the next K-step
     // reads from, so about kDepth K-steps of compute cover the load latency.
     constexpr int kDepth = 1;
     uint4 ring[kDepth][kPer];
+    // K-steps are fetched once each, in increasing order
     auto fetch = [&](uint4* dst, int k) __attribute__((always_inline)) {
-        const bool live = k < nk;
+        if (k == nk && nk_all > nk) retarget();
+        const bool live = k < nk_all;
+        const int kk = k < nk ? k : k - nk;
 #pragma unroll
         for (int i = 0; i < kPer; ++i)
-            dst[i] = (live && ok[i]) ? *(const uint4*)(src[i] + (size_t)k * kTK * esz)
+            dst[i] = (live && ok[i]) ? *(const uint4*)(src[i] + (size_t)kk * kTK * esz)
                                      : make_uint4(0, 0, 0, 0);
     };
     auto deposit = [&](const uint4* from, int stage) __attribute__((always_inline)) {
@@ -1059,13 +1151,13 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     deposit(ring[0], 0);
     __syncthreads();
     fetch(ring[0], kDepth);
-    for (int k0 = 0; k0 < nk; k0 += kDepth) {
+    for (int k0 = 0; k0 < nk_all; k0 += kDepth) {
 #pragma unroll
         for (int u = 0; u < kDepth; ++u) {
             const int k = k0 + u;   // K-step computed here; slot (u + 1) % kDepth holds k + 1
-            if (k < nk) {
+            if (k < nk_all) {
                 compute(k & 1);
-                if (k + 1 < nk) deposit(ring[(u + 1) % kDepth], (k + 1) & 1);
+                if (k + 1 < nk_all) deposit(ring[(u + 1) % kDepth], (k + 1) & 1);
                 __syncthreads();
                 fetch(ring[(u + 1) % kDepth], k + 1 + kDepth);
             }
@@ -1092,7 +1184,17 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             if (cbase >= a.z_pad) break;
             const int tile = cbase / kChainTile, chain = cbase + c;
             const bool active = chain < a.z;
-            const float ed = active ? (float)(a.dn[chain] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+            float ed, ed2 = 0.0f, Fk = 0.0f;
+            if (a.rk > 0) {
+                // |g_hat - g| <= eps_g (|a| |h| + |a P U| |eps|) + |a| dx
+                const double hn = a.hn[chain], en = a.en[chain];
+                const double dx = 0x1.0p-36 * (hn + a.dn[chain] + *a.uF * en);
+                ed = active ? (float)(hn * (double)a.eps_g + dx) * kHighGrow + 1e-30f : 0.0f;
+                ed2 = active ? (float)(en * (double)a.eps_g) * kHighGrow : 0.0f;
+                Fk = (float)a.F[chain] * kHighGrow;
+            } else {
+                ed = active ? (float)(a.dn[chain] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+            }
             const float Ek = (float)a.E[chain] * kHighGrow;
             const float th = (float)a.theta[chain];
             float up = kInf, um = kInf, lp = kInf, lm = kInf;
@@ -1111,8 +1213,9 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
                     }
                     Gw[idx] = gv;
                     const float na = a.rownorm[row];
-                    const float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
-                    const float e = na * ed;
+                    const float nau = a.rk > 0 ? a.aun[row] : 0.0f;
+                    const float dl = fmaf(nau, Fk, fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f)));
+                    const float e = fmaf(nau, ed2, na * ed);
                     float lo_p, hi_p, lo_m, hi_m;
                     ratio_bounds(s_, gv, dl, e, lo_p, hi_p, lo_m, hi_m);
                     up = fminf(up, hi_p);
@@ -1184,6 +1287,11 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
             cs->theta[tid] = a.theta[chain];
             cs->E[tid] = a.E[chain];
             cs->dnorm[tid] = a.dn[chain];
+            if (a.rk > 0) {
+                cs->hnorm[tid] = a.hn[chain];
+                cs->enorm[tid] = a.en[chain];
+                cs->F[tid] = a.F[chain];
+            }
             cs->flags[tid] = 0;
             cs->up[tid] = __float_as_uint(kInf);
             cs->um[tid] = __float_as_uint(kInf);
@@ -1215,6 +1323,7 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
             const int chain = c0 + tid;
             a.theta[chain] = cs->theta[tid];
             a.E[chain] = cs->E[tid];
+            if (a.rk > 0) a.F[chain] = cs->F[tid];
             if (cs->flags[tid] && chain < a.z) atomicOr(&a.flags[chain], cs->flags[tid]);
         }
         if (tid == 0 && cs->exact) atomicAdd(&a.counters[0], cs->exact);
@@ -1223,14 +1332,23 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
     if (!gen_dirs) return;
     make_directions(a, cs, c0, dir_step);
     __syncthreads();
-    if (tid < kChainTile) a.dn[c0 + tid] = cs->dnorm[tid];
+    if (tid < kChainTile) {
+        a.dn[c0 + tid] = cs->dnorm[tid];
+        if (a.rk > 0) {
+            a.hn[c0 + tid] = cs->hnorm[tid];
+            a.en[c0 + tid] = cs->enorm[tid];
+        }
+    }
+    // the screening operand: the direction, or with the split screening its
+    // isotropic part (the low-rank part's operand was written with the draws)
+    const double* Dsrc = a.rk > 0 ? a.Hs : a.D;
     if (P == kBF16X3) {
         __bf16* Dh = (__bf16*)a.Dop;
         __bf16* Dl = Dh + (size_t)a.z_pad * lda;
         for (int item = tid; item < kChainTile * lda; item += kThreads) {
             const int cl = item / lda, j = item - cl * lda, chain = c0 + cl;
             const size_t o = (size_t)chain * lda + j;
-            const float v = (chain < a.z && j < n) ? (float)a.D[o] : 0.0f;
+            const float v = (chain < a.z && j < n) ? (float)Dsrc[o] : 0.0f;
             __bf16 hi, lo;
             split_bf16(v, hi, lo);
             Dh[o] = hi;
@@ -1241,7 +1359,7 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
         for (int item = tid; item < kChainTile * lda; item += kThreads) {
             const int cl = item / lda, j = item - cl * lda, chain = c0 + cl;
             const size_t o = (size_t)chain * lda + j;
-            Df[o] = (chain < a.z && j < n) ? (float)a.D[o] : 0.0f;
+            Df[o] = (chain < a.z && j < n) ? (float)Dsrc[o] : 0.0f;
         }
     }
 }
@@ -1371,8 +1489,10 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
                 v = fma(x, x, v);
             }
             v = wave_sum(v);
-            if (lane == 0)
+            if (lane == 0) {
                 a.E[chain] = ((double)a.u_s * (1.0 + 0x1.0p-20) + (2.0 * n + 4.0) * 0x1.0p-53) * sqrt(v);
+                if (a.rk > 0) a.F[chain] = 0.0;
+            }
         }
     }
 
@@ -1750,8 +1870,27 @@ int batch_blocks_per_cu(int prec, int max_lda)
     return nb < 1 ? 1 : nb;
 }
 
+// event pair around one launch when a trace is attached and has room
+struct TraceScope {
+    KernelTrace* t;
+    hipStream_t s;
+    int slot;
+    TraceScope(KernelTrace* tr, hipStream_t st, int kind) : t(tr), s(st), slot(-1)
+    {
+        if (t && t->used < t->cap) {
+            slot = t->used++;
+            t->kind[slot] = kind;
+            (void)hipEventRecord(t->ev[2 * slot], s);
+        }
+    }
+    ~TraceScope()
+    {
+        if (slot >= 0) (void)hipEventRecord(t->ev[2 * slot + 1], s);
+    }
+};
+
 template <int P>
-static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream)
+static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTrace* trace)
 {
     const size_t lds_s = 2 * (size_t)screen_stage_bytes<P>();
     const size_t lds_r = 2 * (size_t)kRStage;
@@ -1766,6 +1905,7 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream)
     const dim3 grid_s((ts + 7) / 8 * 8), grid_r((tr + 7) / 8 * 8), grid_c(a.z_pad / kChainTile);
     int pending = a.pending0, T = a.T0, since = a.since0;
     if (a.recompute_first) {
+        TraceScope ts_(trace, stream, kTraceRecompute);
         hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kThreads), lds_r, stream, a);
         pending = 0;
         T = 2;
@@ -1776,25 +1916,37 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream)
     const bool own_dirs = a.r == 0;
     const dim3 grid_d(a.z_pad);
     if (a.steps > 0) {
-        if (own_dirs)
+        if (own_dirs) {
+            TraceScope ts_(trace, stream, kTraceDirs);
             hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kThreads), 0, stream, a, a.step0);
-        else
+        } else {
+            TraceScope ts_(trace, stream, kTraceChords);
             hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a,
                                (uint64_t)0, 0, T, 0, 1, a.step0);
+        }
     }
     for (int s = 0; s < a.steps; ++s) {
         const uint64_t step = a.step0 + (uint64_t)s;
         const bool more = s + 1 < a.steps;
-        hipLaunchKernelGGL(tiled_screen_kernel<P>, grid_s, dim3(kThreads), lds_s, stream, a,
-                           pending, T);
-        hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a, step, s,
-                           T, 1, (int)(more && !own_dirs), step + 1);
-        if (more && own_dirs)
+        {
+            TraceScope ts_(trace, stream, kTraceScreen);
+            hipLaunchKernelGGL(tiled_screen_kernel<P>, grid_s, dim3(kThreads), lds_s, stream, a,
+                               pending, T);
+        }
+        {
+            TraceScope ts_(trace, stream, kTraceChords);
+            hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a, step, s,
+                               T, 1, (int)(more && !own_dirs), step + 1);
+        }
+        if (more && own_dirs) {
+            TraceScope ts_(trace, stream, kTraceDirs);
             hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kThreads), 0, stream, a, step + 1);
+        }
         pending = 1;
         T += 1;
         since += 1;
         if (since >= a.R) {
+            TraceScope ts_(trace, stream, kTraceRecompute);
             hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kThreads), lds_r, stream, a);
             pending = 0;
             T = 2;
@@ -1853,11 +2005,11 @@ hipError_t launch_grouped(int prec, const StepArgs* descs, const int4* stiles, i
     }
 }
 
-hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream)
+hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream, KernelTrace* trace)
 {
     switch (prec) {
-    case kFP32: return launch_tiled_t<kFP32>(a, stream);
-    case kBF16X3: return launch_tiled_t<kBF16X3>(a, stream);
+    case kFP32: return launch_tiled_t<kFP32>(a, stream, trace);
+    case kBF16X3: return launch_tiled_t<kBF16X3>(a, stream, trace);
     default: return hipErrorInvalidValue;
     }
 }

@@ -410,7 +410,139 @@ inline int blocks_for(int64_t total, int threads)
     return (int)(b < 1 ? 1 : (b > 65535 ? 65535 : b));
 }
 
+// ---- split screening of the tiled path: A P U and ||U||_F ----
+
+// Y = A_eq U (m_eq x r), one thread per entry, sequential over the coordinates
+__global__ void lowrank_aequ_kernel(int n, int lda, int r, int m_eq, const double* __restrict__ Aeq,
+                                    const double* __restrict__ U, double* Y)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m_eq * r) return;
+    const int p = e / r, q = e - p * r;
+    double v = 0.0;
+    for (int j = 0; j < n; ++j) v = fma(Aeq[(size_t)p * lda + j], U[(size_t)j * r + q], v);
+    Y[e] = v;
+}
+
+// P U = U - W Y (W^T rows = (A_eq A_eq^T)^{-1} A_eq), or a copy of U
+__global__ void lowrank_pu_kernel(int n, int lda, int r, int m_eq, const double* __restrict__ WT,
+                                  const double* __restrict__ Y, const double* __restrict__ U,
+                                  double* PU)
+{
+    const int64_t total = (int64_t)n * r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(e / r), q = (int)(e - (int64_t)j * r);
+        double v = U[e];
+        for (int p = 0; p < m_eq; ++p) v = fma(-WT[(size_t)p * lda + j], Y[p * r + q], v);
+        PU[e] = v;
+    }
+}
+
+// Row i of A P U (FP64, lane = rank column, sequential over the coordinates),
+// written as the screening operand (rk columns, zero padded) with its norm
+// rounded up; one wave per row
+__global__ __launch_bounds__(256) void lowrank_au_kernel(int n, int lda, int r, int rk, int m_pad,
+                                                         int bf16, const double* __restrict__ A64,
+                                                         const double* __restrict__ PU,
+                                                         void* AUop, float* aun)
+{
+    const int q = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= m_pad) return;
+    const double* ar = A64 + (size_t)i * lda;
+    double v = 0.0;
+    if (q < r)
+        for (int j = 0; j < n; ++j) v = fma(ar[j], PU[(size_t)j * r + q], v);
+    const double nrm = sqrt(wave_sum(v * v));
+    if (q < rk) {
+        const size_t o = (size_t)i * rk + q;
+        if (bf16) {
+            __bf16 hi, lo;
+            split_bf16((float)v, hi, lo);
+            ((__bf16*)AUop)[o] = hi;
+            ((__bf16*)AUop)[(size_t)m_pad * rk + o] = lo;
+        } else {
+            ((float*)AUop)[o] = (float)v;
+        }
+    }
+    if (q == 0) aun[i] = (float)nrm * (1.0f + 0x1.0p-20f);
+}
+
+// ||U||_F (one workgroup, fixed-shape tree)
+__global__ __launch_bounds__(256) void lowrank_frob_kernel(int64_t count, const double* U, double* out)
+{
+    __shared__ double ps[256];
+    const int tid = threadIdx.x;
+    double v = 0.0;
+    for (int64_t e = tid; e < count; e += 256) v = fma(U[e], U[e], v);
+    ps[tid] = v;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) ps[tid] += ps[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) *out = sqrt(ps[0]);
+}
+
 }  // namespace
+
+size_t lowrank_bytes(int prec, int n, int r, int m_pad, int lda, int z_pad, int m_eq)
+{
+    (void)prec;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t rk = (size_t)round_up(r, 32);
+    size_t b = 0;
+    b += al((size_t)m_pad * rk * 4);       // A P U operand (FP32, or bf16 hi + lo)
+    b += al((size_t)m_pad * 4);            // its row norms
+    b += al((size_t)z_pad * rk * 4);       // eps operand
+    b += al((size_t)n * r * 8);            // P U
+    b += al((size_t)(m_eq > 0 ? m_eq : 1) * r * 8);   // A_eq U
+    b += al(64);                           // ||U||_F
+    b += al((size_t)z_pad * lda * 8);      // isotropic part of the directions
+    b += 3 * al((size_t)z_pad * 8);        // hn, en, F
+    return b;
+}
+
+void lowrank_carve(PrecondBufs* p, void* ws)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    char* b = (char*)ws;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* q = b + o;
+        o += al(bytes);
+        return q;
+    };
+    const size_t rk = (size_t)round_up(p->r, 32);
+    p->rk = (int)rk;
+    p->AUop = take((size_t)p->m_pad * rk * 4);
+    p->aun = (float*)take((size_t)p->m_pad * 4);
+    p->Eop = take((size_t)p->z_pad * rk * 4);
+    p->PU = (double*)take((size_t)p->n * p->r * 8);
+    p->uF = (double*)take(64);
+    double* aequ = (double*)take((size_t)(p->m_eq > 0 ? p->m_eq : 1) * p->r * 8);
+    p->Hs = (double*)take((size_t)p->z_pad * p->lda * 8);
+    p->hn = (double*)take((size_t)p->z_pad * 8);
+    p->en = (double*)take((size_t)p->z_pad * 8);
+    p->F = (double*)take((size_t)p->z_pad * 8);
+    p->AeqU = aequ;
+}
+
+hipError_t launch_lowrank_setup(const PrecondBufs& p, hipStream_t stream)
+{
+    if (p.m_eq > 0)
+        hipLaunchKernelGGL(lowrank_aequ_kernel, dim3((p.m_eq * p.r + 255) / 256), dim3(256), 0,
+                           stream, p.n, p.lda, p.r, p.m_eq, p.Aeq, p.U, p.AeqU);
+    hipLaunchKernelGGL(lowrank_pu_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0,
+                       stream, p.n, p.lda, p.r, p.m_eq, p.WT, p.AeqU, p.U, p.PU);
+    hipLaunchKernelGGL(lowrank_au_kernel, dim3((p.m_pad + 3) / 4), dim3(256), 0, stream, p.n, p.lda,
+                       p.r, p.rk, p.m_pad, p.prec == kBF16X3 ? 1 : 0, p.A64, p.PU, p.AUop, p.aun);
+    hipLaunchKernelGGL(lowrank_frob_kernel, dim3(1), dim3(256), 0, stream, (int64_t)p.n * p.r, p.U,
+                       p.uF);
+    return hipGetLastError();
+}
+
 
 size_t precond_bytes(int n, int r, int z, int lda, int objective, int m_pad)
 {

@@ -52,6 +52,13 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 4)]
 
 
+class Trace(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4)]
+
+
+TRACE_KINDS = ("screen", "chords", "dirs", "recompute")
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_uint64), ("chain_steps", ctypes.c_uint64),
                 ("exact_rows", ctypes.c_uint64), ("recomputes", ctypes.c_uint64),
@@ -93,6 +100,8 @@ SIGNATURES = {
     "mhar_precond_get": (_st, [_vp, _vp, _vp, _vp]),
     "mhar_precond_loss": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "mhar_precond_train": (_st, [_vp, _i64, ctypes.c_double, _vp]),
+    "mhar_trace_enable": (_st, [_vp, ctypes.c_int32]),
+    "mhar_trace_read": (_st, [_vp, _vp, ctypes.POINTER(Trace)]),
     "mhar_precond_freeze": (_st, [_vp]),
     "mhar_precond_destroy": (_st, [_vp]),
     "mhar_batch_workspace_size": (_st, [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]),
@@ -275,6 +284,14 @@ class Chains:
         s = Stats()
         _check(load().mhar_get_stats(self.handle, self.stream, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def trace_enable(self, max_launches: int):
+        _check(load().mhar_trace_enable(self.handle, int(max_launches)))
+
+    def trace_read(self) -> dict:
+        t = Trace()
+        _check(load().mhar_trace_read(self.handle, self.stream, ctypes.byref(t)))
+        return {k: {"launches": t.launches[i], "ms": t.ms[i]} for i, k in enumerate(TRACE_KINDS)}
 
     # ---- learned direction covariance ----
     def precond_create(self, rank: int, objective: str = "states"):

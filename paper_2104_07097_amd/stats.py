@@ -64,6 +64,32 @@ def ess(draws: np.ndarray) -> float:
     return float(m * n / tau)
 
 
+def split_rhat(draws: np.ndarray) -> float:
+    """Split potential scale reduction R-hat of one scalar quantity (Gelman et
+    al., BDA3 S11.4): chains (rows) cut in halves, sqrt(var_plus / W) with W
+    the mean within-half variance and var_plus = (n-1)/n W + B/n.  Near 1 when
+    the halves agree; well above 1 when the chains have not mixed."""
+    draws = np.asarray(draws, dtype=np.float64)
+    if draws.ndim == 1:
+        draws = draws[None, :]
+    t = draws.shape[1]
+    half = t // 2
+    x = np.concatenate([draws[:, :half], draws[:, t - half:]], axis=0)
+    n = x.shape[1]
+    w = x.var(axis=1, ddof=1).mean()
+    b_over_n = x.mean(axis=1).var(ddof=1)
+    var_plus = w * (n - 1.0) / n + b_over_n
+    if not w > 0:
+        return float("inf") if var_plus > 0 else 1.0
+    return float(np.sqrt(var_plus / w))
+
+
+def max_marginal_rhat(samples: np.ndarray) -> float:
+    """samples: (iterations, chains, n).  The largest split R-hat over coordinates."""
+    samples = np.asarray(samples, dtype=np.float64)
+    return max(split_rhat(samples[:, :, j].T) for j in range(samples.shape[2]))
+
+
 def min_marginal_ess(samples: np.ndarray) -> tuple[float, np.ndarray]:
     """samples: (iterations, chains, n).  Returns (min over coordinates, per-coordinate ESS)."""
     samples = np.asarray(samples, dtype=np.float64)

@@ -3,7 +3,8 @@ the Friedman-Rafsky statistic against its null distribution (simulation) and
 against clearly different laws."""
 import numpy as np
 
-from paper_2104_07097_amd.stats import ess, friedman_rafsky, ks_distance, ks_two_sample
+from paper_2104_07097_amd.stats import (ess, friedman_rafsky, ks_distance, ks_two_sample,
+                                        split_rhat)
 
 
 def test_ess_iid():
@@ -58,3 +59,22 @@ def test_friedman_rafsky_runs_by_hand():
     y = np.array([[0.5], [5.0]])
     R, _ = friedman_rafsky(x, y)
     assert R == 1 + 3   # order 0(x) .5(y) 1(x) 2(x) 5(y): changes x-y, y-x, x-y
+
+
+def test_split_rhat():
+    rng = np.random.default_rng(9)
+    # i.i.d. chains: R-hat within sampling error of 1
+    assert abs(split_rhat(rng.standard_normal((8, 4000))) - 1.0) < 0.01
+    # chains stuck at different levels: between-half variance dominates
+    stuck = rng.standard_normal((8, 4000)) * 0.1 + np.arange(8)[:, None]
+    assert split_rhat(stuck) > 5.0
+    # a trend within each chain shows up through the split halves
+    trend = rng.standard_normal((8, 4000)) * 0.1 + np.linspace(0, 3, 4000)[None, :]
+    assert split_rhat(trend) > 2.0
+    # closed form for two halves of constant levels a, b with within variance s^2:
+    # W = s^2, B/n = var(levels, ddof=1) -> R = sqrt(((n-1)/n s^2 + B/n) / s^2)
+    x = np.concatenate([np.full(1000, 0.0), np.full(1000, 1.0)])[None, :]
+    x = x + np.tile([-0.5, 0.5], 1000)[None, :]   # within-half variance 0.25 (ddof=1: 0.25025)
+    w = np.var(np.tile([-0.5, 0.5], 500), ddof=1)
+    want = np.sqrt((999.0 / 1000.0 * w + 0.5) / w)
+    assert abs(split_rhat(x) - want) < 1e-12
