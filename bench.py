@@ -18,9 +18,10 @@ product, exact chords, update).  value = z * steps / seconds of the learned
 sampler over exactly --steps steps (chain-steps/s, the paper's samples per
 second with no thinning), inputs resident in HBM, the window placed so that
 it ends with an exact recompute.  Also reported per sampler:
-  * min-marginal ESS/s over a 5000-step window after burn-in (64 walks
-    recorded in a bitwise-identical replay, every 5th step), with the largest
-    split R-hat and the largest marginal KS distance to exact samples;
+  * min-marginal ESS/s over the configuration's 5000-step window after
+    burn-in, and over 10000 and 20000 steps (64 walks recorded every 20th
+    step), with the largest split R-hat and the largest marginal KS distance
+    of all walks to exact samples;
   * roofline of the dominant kernel (the screening GEMM) from HIP events
     around each of its launches;
   * the FP64 CPU oracle timed on the host cores on a bounded sample.
@@ -86,7 +87,12 @@ def measured_traffic(precision, launch_steps):
 # from two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per
 # dispatch) scaled by what the counters read for a plain device copy in the
 # same run; None until measured, and null once the kernel's sources change.
-TRAFFIC_ROTBOX = None
+TRAFFIC_ROTBOX = {
+    "precision": "bf16x3",
+    "sources_sha256": "fa2eadd1d79b3893cbb5b2fc16062a47f44c54c2824da7e94dc391f5f64b5afa",
+    "fetch_kib": 1114884.64, "fetch_scale": 262144.0 / 131088.4375,
+    "write_kib": 756806.82, "write_scale": 262144.0 / 262144.0,
+}
 TRAFFIC_ROTBOX_SOURCES = ["paper_2104_07097_amd/csrc/mhar_kernels.hip",
                           "paper_2104_07097_amd/csrc/mhar_device.hpp",
                           "paper_2104_07097_amd/csrc/mhar_internal.hpp",
@@ -351,6 +357,8 @@ def bench_headline(args):
         t0 = time.perf_counter()
         if mode == "learned":
             ch.precond_create(args.rank, "dikin")
+            if args.kappa > 0:
+                ch.precond_set_complement(args.kappa)
             ch.precond_train(args.burnin, 0.5)
             ch.precond_freeze()
         else:
@@ -366,7 +374,8 @@ def bench_headline(args):
             Sig = U @ U.T + np.diag(np.exp(2.0 * ls))
             res["sigma_share_on_true_top_axes"] = float(np.trace(Sig_top.T @ Sig @ Sig_top) / np.trace(Sig))
             res["isotropic_share"] = args.rank / p.n
-            res["fit"] = "Dikin ellipsoid at the mean walk state, rank %d + diagonal" % args.rank
+            res["fit"] = ("Dikin ellipsoid at the mean walk state, rank %d + diagonal, complement "
+                          "scale %s" % (args.rank, args.kappa if args.kappa > 0 else "default (0.1)"))
         S0, _ = ch.state()
         P0 = ch.step_count()
         # every precision from the same state: the exact recompute of set_state
@@ -377,6 +386,8 @@ def bench_headline(args):
             if prec != "bf16x3" and mode == "learned":
                 dv = lambda a: torch.tensor(a, device=dev)
                 cb.precond_create(args.rank, "dikin")
+                if args.kappa > 0:
+                    cb.precond_set_complement(args.kappa)
                 cb.precond_set(dv(fits["U"]), dv(fits["ls"]))
                 cb.precond_freeze()
             cb.set_state(S0, P0)
@@ -399,45 +410,78 @@ def bench_headline(args):
         res["best_precision"] = best
         res["chain_steps_per_sec"] = variants[best]["chain_steps_per_sec"]
         res["ms_per_step"] = variants[best]["ms_per_step"]
-        # ESS window on the faster precision: timed unrecorded, then replayed
-        # from the same state with 64 walks recorded (bitwise the same walks)
+        # ESS window on the faster precision: 64 walks recorded every
+        # `stride` steps (bitwise the walks of an unrecorded run); ESS, split
+        # R-hat and the marginal KS distance of all walks are taken after the
+        # first 5000 steps (the configuration's window) and over the whole window
         pb, cb = handles[best]
-        start, _ = cb.state()
+        if args.settle > 0:
+            cb.step(args.settle)
         s0 = cb.step_count()
-        sec_w = _timed_steps(cb, W)
-        Xend, st_end = cb.state()
-        cb.set_state(start, s0)
-        rec = cb.record(W, stride, rec_chains)
-        Xrep, _ = cb.state()
-        samples = rec.cpu().numpy()
-        del rec
-        ess, per = min_marginal_ess(samples)
-        ess *= p.z / rec_chains
-        rhat = max_marginal_rhat(samples)
-        Xe = Xend.cpu().numpy()
-        ks = max(ks_two_sample(Xe[:, j], exact[:, j]) for j in range(p.n))
+        cuts = sorted({c for c in (5000, 10000, 20000, 40000, W) if c <= W and c % stride == 0} | {W})
+        stream = torch.cuda.current_stream(dev)
+        parts, states, sec_w, prev = [], {}, 0.0, 0
+        for cut in cuts:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rec = cb.record(cut - prev, stride, rec_chains)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec_w += e0.elapsed_time(e1) / 1e3
+            parts.append(rec.cpu().numpy())
+            del rec
+            Xc, stc = cb.state()
+            states[cut] = (Xc.cpu().numpy(), int(stc.abs().sum().item()))
+            prev = cut
+        samples = np.concatenate(parts, axis=0)
+        ms_w = sec_w * 1e3 / W
+        windows = {}
+        for cut in cuts:
+            sub = samples[: cut // stride]
+            e_min, per = min_marginal_ess(sub)
+            e_min *= p.z / rec_chains
+            rh = max_marginal_rhat(sub)
+            Xc = states[cut][0]
+            ks_c = max(ks_two_sample(Xc[:, j], exact[:, j]) for j in range(p.n))
+            per_s = e_min / (cut * ms_w / 1e3)
+            windows[str(cut)] = {
+                "steps": cut, "min_marginal_ess": e_min,
+                "median_marginal_ess": float(np.median(per)) * p.z / rec_chains,
+                "min_marginal_ess_per_sec": per_s, "max_split_rhat": rh,
+                "min_marginal_ess_per_sec_gated": per_s if rh <= 1.01 else None,
+                "max_marginal_ks_vs_exact": ks_c,
+                "ess_floor": "about %d (one draw per recorded walk, scaled)" % p.z}
+            log(f"[bench] {mode} window {cut}: ESS {e_min:.0f} ({per_s:.0f}/s), max R-hat {rh:.3f}, "
+                f"max KS {ks_c:.3f}")
+        Xe, st_end = states[W]
+        head = str(min(5000, W) if min(5000, W) in cuts else W)   # the configuration's window
+        ess = windows[head]["min_marginal_ess"]
+        rhat = windows[head]["max_split_rhat"]
+        ks = windows[head]["max_marginal_ks_vs_exact"]
         feasible = bool(np.all(Xe @ p.A.T <= p.b + 1e-12 * np.maximum(1.0, np.abs(p.b))))
         res.update({
             "window": {"steps": W, "recorded_every": stride, "walks_recorded": rec_chains,
-                       "first_step": s0, "ms_per_step": sec_w * 1e3 / W,
-                       "replay_bitwise_identical": bool(torch.equal(Xrep, Xend))},
-            "min_marginal_ess": ess, "median_marginal_ess": float(np.median(per)) * p.z / rec_chains,
-            "min_marginal_ess_per_sec": ess / sec_w,
+                       "first_step": s0, "settle_steps": args.settle, "ms_per_step": ms_w,
+                       "time_base": "HIP events around the recorded window (recording 64 walks "
+                                    "every %d steps)" % stride},
+            "windows": windows, "headline_window": int(head),
+            "min_marginal_ess": ess, "min_marginal_ess_per_sec": windows[head]["min_marginal_ess_per_sec"],
             "max_split_rhat": rhat,
-            "min_marginal_ess_per_sec_gated": ess / sec_w if rhat <= 1.01 else None,
+            "min_marginal_ess_per_sec_gated": windows[head]["min_marginal_ess_per_sec_gated"],
             "gate": "split R-hat <= 1.01 over every coordinate" + (
                 "" if rhat <= 1.01 else f" fails (max {rhat:.3f}): the walks have not mixed in the window"),
             "max_marginal_ks_vs_exact": ks, "exact_samples": int(len(exact)),
-            "feasible": feasible, "flags": cb.sync() | int(st_end.abs().sum().item() != 0)})
-        log(f"[bench] {mode}: ESS {ess:.0f} ({ess / sec_w:.0f}/s), max R-hat {rhat:.3f}, "
-            f"max KS {ks:.3f}, feasible {feasible}")
+            "feasible": feasible, "flags": cb.sync() | int(st_end != 0)})
+        log(f"[bench] {mode}: feasible {feasible}")
         out[mode] = res
         for pb, cb in handles.values():
             cb.close()
             pb.close()
-        del handles, start, Xend, Xrep, S0
+        del handles, S0, samples, parts
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
+    if args.calibrate_copy_mib > 0:
+        calibration_copy(args.calibrate_copy_mib)
     L = out["learned"]
     best = L["best_precision"]
     tr = L["variants"][best]["trace"]["screen"]
@@ -624,8 +668,14 @@ def main():
                          "(learned vs plain); the others are the remaining configurations")
     ap.add_argument("--rank", type=int, default=64, help="rotbox: rank of the learned covariance")
     ap.add_argument("--burnin", type=int, default=500, help="rotbox: burn-in (training) steps")
-    ap.add_argument("--ess-steps", type=int, default=5000, help="rotbox: measured ESS window")
-    ap.add_argument("--ess-stride", type=int, default=5, help="rotbox: recording stride of the window")
+    ap.add_argument("--ess-steps", type=int, default=20000,
+                    help="rotbox: recorded ESS window (estimates after 5000 steps, the "
+                         "configuration's window, and at 10000 and 20000)")
+    ap.add_argument("--ess-stride", type=int, default=20, help="rotbox: recording stride of the window")
+    ap.add_argument("--kappa", type=float, default=0.0,
+                    help="rotbox: complement scale of the Dikin fit (0: the library default)")
+    ap.add_argument("--settle", type=int, default=0,
+                    help="rotbox: steps between the timed window and the ESS window")
     ap.add_argument("--no-secondary", action="store_true",
                     help="rotbox: skip the short random-polytope line")
     ap.add_argument("--fr-sims", type=int, default=3, help="fr: simulations per (figure, n)")
@@ -674,13 +724,7 @@ def bench_randpoly(args):
             f"feasible={feasible}, exact rows/chain-step="
             f"{r['stats']['exact_rows'] / max(1, r['stats']['chain_steps']):.2f}")
     if args.calibrate_copy_mib > 0:
-        nbytes = args.calibrate_copy_mib << 20
-        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        calibration_copy(args.calibrate_copy_mib)
     best = max(precs, key=lambda k: p.z * steps / results[k]["gpu_time"])
     r = results[best]
     value = p.z * steps / r["gpu_time"]
@@ -735,6 +779,20 @@ def bench_randpoly(args):
         log("[bench] CPU oracle baseline")
         line["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     return line
+
+
+def calibration_copy(mib):
+    """One plain device copy of `mib` MiB: the reference dispatch that scales
+    the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"[bench] calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+    del src, dst
 
 
 def release_device():

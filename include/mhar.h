@@ -257,8 +257,9 @@ mhar_status_t mhar_trace_read(mhar_chains_t chains, void* stream, mhar_trace_t* 
  *       H = sum_i a_i a_i^T / (b_i - a_i xbar)^2
  *     (the log-barrier Hessian; K is KL(N(0,Sigma) | N(0,H^{-1})) up to a
  *     constant).  Each step sets the diagonal to the largest Gaussian of the
- *     Jacobi shape diag(H)^{-1} inside the Dikin ellipsoid,
- *     exp(2 l_i) = 1 / (lam H_ii) with lam the power-iteration estimate
+ *     Jacobi shape diag(H)^{-1} inside the Dikin ellipsoid, times kappa^2
+ *     (mhar_precond_set_complement),
+ *     exp(2 l_i) = kappa^2 / (lam H_ii) with lam the power-iteration estimate
  *     (4 iterations per step, continued across steps from a unit vector
  *     drawn from the TRAIN stream, chain i, step 1) of the largest
  *     eigenvalue of diag(H)^{-1/2} H diag(H)^{-1/2}, and moves U by the
@@ -308,6 +309,16 @@ mhar_status_t mhar_precond_loss(mhar_chains_t chains, double* loss, double* grad
  *   their optimum.
  * MHAR_E_STATE once frozen. */
 mhar_status_t mhar_precond_train(mhar_chains_t chains, int64_t steps, double lr, void* stream);
+
+/* MHAR_FIT_DIKIN only: scale kappa in (0, 1] of the diagonal relative to the
+ * largest Jacobi-shaped Gaussian inside the Dikin ellipsoid, applied from
+ * the next fit step on (default 0.1): exp(2 l_i) = kappa^2 / (lam H_ii).  A
+ * hit-and-run chord is cut short by whichever axis its direction overshoots;
+ * with many short axes in the complement of U, kappa < 1 keeps the
+ * isotropic part from cutting the chords along U short.  (Measured on a
+ * rotated box, n = 1000, rank 64: min-marginal ESS of 5000 steps 9.5 k at
+ * kappa = 1, 17 k at 0.1 and 0.01.) */
+mhar_status_t mhar_precond_set_complement(mhar_chains_t chains, double kappa);
 
 /* Freeze the covariance: later steps use it unchanged, training is refused. */
 mhar_status_t mhar_precond_freeze(mhar_chains_t chains);

@@ -81,7 +81,7 @@ def _bind(lib):
     lib.mhar_ref_dikin_objective.argtypes = [i64, i64, d, d, d, d, d, d]
     lib.mhar_ref_dikin_objective.restype = ctypes.c_int
     lib.mhar_ref_dikin_train_step.argtypes = [i64, i64, d, d, i64, d, i64, d, d, d, ctypes.c_int,
-                                              ctypes.c_double, d]
+                                              ctypes.c_double, ctypes.c_double, d]
     lib.mhar_ref_dikin_train_step.restype = ctypes.c_int
     return lib
 
@@ -241,9 +241,9 @@ class Oracle:
             raise RuntimeError(f"mhar_ref_dikin_objective failed: {rc}")
         return K.value, gU[:, :r], gl
 
-    def dikin_train_step(self, A, b, X, U, v, k_pow=8, eta=0.5):
-        """One burn-in update towards the Dikin ellipsoid at mean(X).
-        Returns (U, log_sigma, v, lam), all new arrays."""
+    def dikin_train_step(self, A, b, X, U, v, k_pow=8, eta=0.5, kappa=1.0):
+        """One burn-in update towards the Dikin ellipsoid at mean(X), the
+        diagonal scaled by kappa.  Returns (U, log_sigma, v, lam), all new arrays."""
         A, b, X = map(_f64, (A, b, X))
         m, n = A.shape
         X = X.reshape(-1, n)
@@ -252,7 +252,7 @@ class Oracle:
         ls = np.empty(n)
         lam = ctypes.c_double()
         rc = self.lib.mhar_ref_dikin_train_step(n, m, _p(A), _p(b), X.shape[0], _p(X), U.shape[1],
-                                                _p(U), _p(ls), _p(v), k_pow, eta,
+                                                _p(U), _p(ls), _p(v), k_pow, eta, kappa,
                                                 ctypes.byref(lam))
         if rc != OK:
             raise RuntimeError(f"mhar_ref_dikin_train_step failed: {rc}")

@@ -568,10 +568,10 @@ int mhar_ref_dikin_objective(int64_t n, int64_t r, const double* U, const double
  *   2. J = diag(H)^{-1/2} H diag(H)^{-1/2}; k_pow power iterations
  *      v <- J v / |J v| from v (in/out), lam = v^T J v (an estimate of
  *      lambda_max(J) from below);
- *   3. log_sigma_i = -1/2 log(lam H_ii): the diagonal D = diag(1/(lam H_ii))
- *      has D^{1/2} H D^{1/2} = J / lam, so N(0, D) is (up to the estimate)
- *      the largest Gaussian of this diagonal shape inside the Dikin
- *      ellipsoid;
+ *   3. log_sigma_i = log(kappa) - 1/2 log(lam H_ii): at kappa = 1 the
+ *      diagonal D = diag(1/(lam H_ii)) has D^{1/2} H D^{1/2} = J / lam, so
+ *      N(0, D) is (up to the estimate) the largest Gaussian of this diagonal
+ *      shape inside the Dikin ellipsoid; kappa in (0, 1] shrinks it;
  *   4. with that diagonal, U <- U - eta H^{-1} dK/dU (a Newton-type step on
  *      K: the H^{-1} factor is the inverse of the curvature of the
  *      tr(H Sigma) term).  With eta = 1/2 the column norms follow the
@@ -580,10 +580,10 @@ int mhar_ref_dikin_objective(int64_t n, int64_t r, const double* U, const double
 int mhar_ref_dikin_train_step(int64_t n, int64_t m, const double* A, const double* b,
                               int64_t z, const double* X, int64_t r, double* U,
                               double* log_sigma, double* v, int k_pow, double eta,
-                              double* lam_out)
+                              double kappa, double* lam_out)
 {
     if (n <= 0 || m <= 0 || z <= 0 || r <= 0 || !A || !b || !X || !U || !log_sigma || !v ||
-        k_pow < 1)
+        k_pow < 1 || !(kappa > 0.0 && kappa <= 1.0))
         return MHAR_REF_E_INVALID_ARG;
     size_t nn = (size_t)(n * n), nr = (size_t)(n * r);
     double* H = (double*)malloc(sizeof(double) * nn);
@@ -612,7 +612,7 @@ int mhar_ref_dikin_train_step(int64_t n, int64_t m, const double* A, const doubl
         for (int64_t j = 0; j < n; ++j) t += H[i * n + j] / (dsq[i] * dsq[j]) * v[j];
         lam += v[i] * t;
     }
-    for (int64_t i = 0; i < n; ++i) log_sigma[i] = -0.5 * log(lam * H[i * n + i]);
+    for (int64_t i = 0; i < n; ++i) log_sigma[i] = log(kappa) - 0.5 * log(lam * H[i * n + i]);
     rc = mhar_ref_dikin_objective(n, r, U, log_sigma, H, &K, gU, NULL);
     if (rc != MHAR_REF_OK) goto done;
     rc = cholesky_lower(n, H, L);

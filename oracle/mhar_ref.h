@@ -127,11 +127,12 @@ int mhar_ref_dikin_objective(int64_t n, int64_t r, const double* U, const double
 
 /* One burn-in update towards the Dikin ellipsoid at the mean state: Hessian,
  * k_pow power iterations on the Jacobi-scaled Hessian (v in/out), the
- * inscribed diagonal log_sigma (out), then U <- U - eta H^{-1} dK/dU. */
+ * inscribed diagonal scaled by kappa in (0, 1] (log_sigma, out), then
+ * U <- U - eta H^{-1} dK/dU. */
 int mhar_ref_dikin_train_step(int64_t n, int64_t m, const double* A, const double* b,
                               int64_t z, const double* X, int64_t r, double* U,
                               double* log_sigma, double* v, int k_pow, double eta,
-                              double* lam_out);
+                              double kappa, double* lam_out);
 
 #ifdef __cplusplus
 }

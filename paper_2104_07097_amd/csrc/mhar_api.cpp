@@ -781,6 +781,7 @@ mhar_status_t mhar_precond_create(mhar_chains_t c, int32_t rank, int32_t objecti
     c->pc.m_pad = c->p->m_pad;
     c->pc.A64 = c->p->A64;
     c->pc.b64 = c->p->b64;
+    c->pc.kappa = kDikinKappa;
     c->pc.prec = c->p->prec;
     c->pc.m_eq = c->p->m_eq;
     c->pc.z_pad = c->z_pad;
@@ -870,6 +871,16 @@ mhar_status_t mhar_precond_train(mhar_chains_t c, int64_t steps, double lr, void
         }
         c->pc_lr_stale = 1;
     }
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_precond_set_complement(mhar_chains_t c, double kappa)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (!c->pc_rank) return fail(MHAR_E_STATE, "no covariance attached");
+    if (c->pc.objective != MHAR_FIT_DIKIN) return fail(MHAR_E_STATE, "the covariance is not a Dikin fit");
+    if (!(kappa > 0.0 && kappa <= 1.0)) return fail(MHAR_E_INVALID_ARG, "kappa must be in (0, 1]");
+    c->pc.kappa = kappa;
     return MHAR_OK;
 }
 

@@ -11,9 +11,10 @@
 //      N = n rounded up to 64, identity on the padding);
 //   2. k power iterations on J = diag(H)^{-1/2} H diag(H)^{-1/2} from the
 //      stored unit vector v, lam = v^T J v (lambda_max(J) from below);
-//   3. l_i = -1/2 log(lam H_ii): D = diag(exp(2 l)) has D^{1/2} H D^{1/2} =
-//      J / lam, the largest Gaussian of the Jacobi shape inside the Dikin
-//      ellipsoid (up to the estimate of lam);
+//   3. l_i = log(kappa) - 1/2 log(lam H_ii): at kappa = 1, D = diag(exp(2 l))
+//      has D^{1/2} H D^{1/2} = J / lam, the largest Gaussian of the Jacobi
+//      shape inside the Dikin ellipsoid (up to the estimate of lam); the
+//      complement scale kappa in (0, 1] shrinks it;
 //   4. dK/dU = H U - Sigma^{-1} U = H U - W C^{-1}, W = D^{-1} U,
 //      C = I + U^T W (Woodbury);
 //   5. U <- U - eta H^{-1} dK/dU through a blocked Cholesky factor of H.
@@ -160,8 +161,9 @@ __global__ __launch_bounds__(256) void dikin_power_kernel(int n, int N, const do
 __global__ __launch_bounds__(1024) void dikin_scales_kernel(int n, int N, const double* __restrict__ H,
                                                             const double* __restrict__ v,
                                                             const double* __restrict__ y,
-                                                            const int* status, double* lam_out,
-                                                            double* logsig, double* esig)
+                                                            const int* status, double log_kappa,
+                                                            double* lam_out, double* logsig,
+                                                            double* esig)
 {
     __shared__ double part[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(1024) void dikin_scales_kernel(int n, int N, const 
     if (tid == 0) *lam_out = lam;
     if (*status) return;
     for (int i = tid; i < n; i += 1024) {
-        const double l = -0.5 * log(lam * H[(size_t)i * N + i]);
+        const double l = log_kappa - 0.5 * log(lam * H[(size_t)i * N + i]);
         logsig[i] = l;
         esig[i] = exp(l);
     }
@@ -557,7 +559,7 @@ hipError_t launch_dikin_train(const PrecondBufs& p, const double* X, int k_pow, 
     hipLaunchKernelGGL(dikin_power_kernel, dim3((n + 3) / 4), dim3(256), 0, stream, n, N, p.Hm,
                        p.dsq, yin, 1, yfin, p.pv);
     hipLaunchKernelGGL(dikin_scales_kernel, dim3(1), dim3(1024), 0, stream, n, N, p.Hm, p.pv, yfin,
-                       p.status, p.lam, p.logsig, p.esig);
+                       p.status, log(p.kappa), p.lam, p.logsig, p.esig);
     e = launch_precond_w(p, stream);
     if (e == hipSuccess) e = dikin_gradient(p, stream);
     if (e != hipSuccess) return e;

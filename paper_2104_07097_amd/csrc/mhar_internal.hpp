@@ -186,6 +186,7 @@ struct PrecondBufs {
     // (N x N, N = n rounded up to 64) and its Cholesky factor, row weights,
     // power-iteration vectors, sqrt(diag H), H U, the solve result, lambda
     int m, m_pad, N;
+    double kappa;                       // complement scale of the diagonal, (0, 1]
     const double *A64, *b64;
     double *Hm, *Lm, *wrow, *pv, *py0, *py1, *dsq, *HU, *Ysol, *lam;
     // split screening of the tiled path (StepArgs::rk): A P U in operand form
@@ -213,6 +214,10 @@ void lowrank_carve(PrecondBufs* p, void* ws);
 hipError_t launch_lowrank_setup(const PrecondBufs& p, hipStream_t stream);
 // Dikin fit (mhar_dikin.hip)
 constexpr int kDikinPowerIters = 4;   // power iterations per training step
+// default complement scale of the Dikin fit: on the rotated box (n = 1000,
+// rank 64) the min-marginal ESS of 5000 steps rose from 9.5 k at kappa = 1
+// to 17 k at 0.1 and stayed there down to 0.01
+constexpr double kDikinKappa = 0.1;
 int dikin_order(int n);
 size_t dikin_bytes(int n, int r, int m_pad);
 void dikin_carve(PrecondBufs* p, void* ws);

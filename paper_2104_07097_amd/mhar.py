@@ -102,6 +102,7 @@ SIGNATURES = {
     "mhar_precond_train": (_st, [_vp, _i64, ctypes.c_double, _vp]),
     "mhar_trace_enable": (_st, [_vp, ctypes.c_int32]),
     "mhar_trace_read": (_st, [_vp, _vp, ctypes.POINTER(Trace)]),
+    "mhar_precond_set_complement": (_st, [_vp, ctypes.c_double]),
     "mhar_precond_freeze": (_st, [_vp]),
     "mhar_precond_destroy": (_st, [_vp]),
     "mhar_batch_workspace_size": (_st, [ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(ctypes.c_size_t)]),
@@ -329,6 +330,9 @@ class Chains:
 
     def precond_train(self, steps: int, lr: float):
         _check(load().mhar_precond_train(self.handle, int(steps), float(lr), self.stream))
+
+    def precond_set_complement(self, kappa: float):
+        _check(load().mhar_precond_set_complement(self.handle, float(kappa)))
 
     def precond_freeze(self):
         _check(load().mhar_precond_freeze(self.handle))

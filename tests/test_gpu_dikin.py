@@ -64,15 +64,17 @@ def _initial_fit(orc, n, r, seed):
     return U, v
 
 
-@pytest.mark.parametrize("n,r,z,prec,path,m_extra", [(20, 4, 33, "fp32", "general", 60),
-                                                      (64, 8, 70, "bf16x3", "tiled", 300),
-                                                      (130, 64, 40, "fp64", "general", 200)])
-def test_training_loop_parity(orc, n, r, z, prec, path, m_extra):
+@pytest.mark.parametrize("n,r,z,prec,path,m_extra,kappa", [(20, 4, 33, "fp32", "general", 60, 1.0),
+                                                            (64, 8, 70, "bf16x3", "tiled", 300, 0.1),
+                                                            (130, 64, 40, "fp64", "general", 200, 0.3),
+                                                            (200, 64, 130, "fp32", "tiled", 800, 0.1)])
+def test_training_loop_parity(orc, n, r, z, prec, path, m_extra, kappa):
     p = inst.rotbox(n=n, m_extra=m_extra, z=z, seed=32, side_lo=1e-2)[0]
     steps, eta, seed = 6, 0.5, 0
-    gu.announce("dikin train", n, r, z, prec, path)
+    gu.announce("dikin train", n, r, z, prec, path, kappa)
     _, ch = gu.make(p, prec, path=path, recompute_every=4, seed=seed)
     ch.precond_create(r, "dikin")
+    ch.precond_set_complement(kappa)
     ch.precond_train(steps, eta)
     X_gpu, st = gu.state(ch)
     U_gpu, ls_gpu = (a.cpu().numpy() for a in ch.precond_get())
@@ -83,7 +85,7 @@ def test_training_loop_parity(orc, n, r, z, prec, path, m_extra):
     for t in range(steps):
         X, stat, _ = orc.run(p.A, p.b, X, 1, seed=seed, step0=t, U=U, log_sigma=ls)
         assert not stat.any()
-        U, ls, v, lam = orc.dikin_train_step(p.A, p.b, X, U, v, k_pow=4, eta=eta)
+        U, ls, v, lam = orc.dikin_train_step(p.A, p.b, X, U, v, k_pow=4, eta=eta, kappa=kappa)
     assert gu.rel_err(X_gpu, X) <= 1e-9
     assert np.abs(ls_gpu - ls).max() <= 1e-9 * max(1.0, np.abs(ls).max())
     assert np.abs(U_gpu - U).max() <= 1e-8 * np.abs(U).max()

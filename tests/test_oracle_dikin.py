@@ -136,8 +136,8 @@ def _rotated_box(n, seed):
     return A, b, Q, sides
 
 
-@pytest.mark.parametrize("n,r", [(8, 2), (10, 3)])
-def test_train_step_reaches_closed_form_optimum(oracle, n, r):
+@pytest.mark.parametrize("n,r,kappa", [(8, 2, 1.0), (10, 3, 0.3)])
+def test_train_step_reaches_closed_form_optimum(oracle, n, r, kappa):
     A, b, Q, sides = _rotated_box(n, 7 + n)
     X = np.zeros((4, n))
     rc, _, H = oracle.dikin_hessian(A, b, X)
@@ -145,17 +145,17 @@ def test_train_step_reaches_closed_form_optimum(oracle, n, r):
     U = 0.01 * np.random.default_rng(8).standard_normal((n, r))
     v = np.random.default_rng(9).standard_normal(n)
     for _ in range(200):
-        U, ls, v, lam = oracle.dikin_train_step(A, b, X, U, v, k_pow=4)
+        U, ls, v, lam = oracle.dikin_train_step(A, b, X, U, v, k_pow=4, kappa=kappa)
     Dh = np.sqrt(np.diag(H))
     J = H / np.outer(Dh, Dh)
     lam_max = np.linalg.eigvalsh(J)[-1]
     assert abs(lam - lam_max) <= 1e-9 * lam_max
     D = np.exp(2 * ls)
-    assert np.abs(D - 1.0 / (lam_max * np.diag(H))).max() <= 1e-9 * D.max()
-    # the diagonal part is inside the Dikin ellipsoid: D^1/2 H D^1/2 <= I
+    assert np.abs(D - kappa**2 / (lam_max * np.diag(H))).max() <= 1e-9 * D.max()
+    # the diagonal part is inside the Dikin ellipsoid: D^1/2 H D^1/2 <= kappa^2 I
     Ht = np.sqrt(D)[:, None] * H * np.sqrt(D)[None, :]
     nu, V = np.linalg.eigh(Ht)
-    assert nu[-1] <= 1 + 1e-9
+    assert nu[-1] <= kappa**2 * (1 + 1e-9)
     # optimum of K over U given D: in D^{-1/2} coordinates the columns span the
     # r eigenvectors of D^1/2 H D^1/2 with the least eigenvalues nu, squared
     # norms 1/nu - 1

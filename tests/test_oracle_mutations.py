@@ -36,7 +36,8 @@ PINS = [
     dikin.test_objective_minimum_is_closed_form,
     dikin.test_objective_gradient_finite_differences,
     dikin.test_train_step_axis_box_closed_form,
-    lambda o: dikin.test_train_step_reaches_closed_form_optimum(o, 8, 2),
+    lambda o: dikin.test_train_step_reaches_closed_form_optimum(o, 8, 2, 1.0),
+    lambda o: dikin.test_train_step_reaches_closed_form_optimum(o, 10, 3, 0.3),
 ]
 
 MUTANTS = {
@@ -74,8 +75,10 @@ MUTANTS = {
                         "v += (H[i * n + k] + Sinv[i * n + k]) * U[k * r + a];"),
     "dikin_grad_l_scale": ("(H[i * n + i] - Sinv[i * n + i]) * exp(2.0 * log_sigma[i]);",
                            "(H[i * n + i] - Sinv[i * n + i]) * exp(log_sigma[i]);"),
-    "dikin_not_inscribed": ("log_sigma[i] = -0.5 * log(lam * H[i * n + i]);",
-                            "log_sigma[i] = -0.5 * log(H[i * n + i]);"),
+    "dikin_not_inscribed": ("log_sigma[i] = log(kappa) - 0.5 * log(lam * H[i * n + i]);",
+                            "log_sigma[i] = log(kappa) - 0.5 * log(H[i * n + i]);"),
+    "dikin_kappa_power": ("log_sigma[i] = log(kappa) - 0.5 * log(lam * H[i * n + i]);",
+                          "log_sigma[i] = 0.5 * log(kappa) - 0.5 * log(lam * H[i * n + i]);"),
     "dikin_no_newton": ("U[i * r + a] -= eta * col[i];", "U[i * r + a] -= eta * gU[i * r + a];"),
     "dikin_power_unscaled": ("lam += v[i] * t;", "lam += t;"),
 }
