@@ -239,6 +239,26 @@ mhar_status_t mhar_trace_enable(mhar_chains_t chains, int32_t max_launches);
  * read per kernel kind into *out, and start a new record. */
 mhar_status_t mhar_trace_read(mhar_chains_t chains, void* stream, mhar_trace_t* out);
 
+/* For callers that cannot allocate device memory (a serving loop, a harness
+ * that forbids it): mhar_problem_create + mhar_chains_create + mhar_step +
+ * mhar_get_state + the two destroys in one call, with both workspaces carved
+ * from one static device array of 64 MiB per GPU (held from the library's
+ * load until the process ends) instead of caller workspaces.  Runs `steps`
+ * isotropic MHAR steps of z walks from X (dev, z x n FP64, in place: the
+ * start points in, the states after the steps out), global chain ids
+ * chain_offset.., step counter starting at step0; status (dev, int32 z)
+ * receives the per-walk bits.  The other arguments are those of
+ * mhar_problem_create.  MHAR_E_WORKSPACE (before any device work) when the
+ * two workspaces exceed the array.  Calls no device allocation routine.
+ * Synchronises `stream` like the create calls.  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one GPU (other threads, other
+ * streams) race; each call initialises what it reads. */
+mhar_status_t mhar_run_noalloc(int64_t n, int64_t m, const double* A, const double* b,
+                               int64_t m_eq, const double* A_eq, const double* b_eq, int64_t z,
+                               double* X, int32_t* status, uint64_t seed, uint64_t chain_offset,
+                               uint64_t step0, int64_t steps, const mhar_options_t* opt,
+                               void* stream);
+
 /* ---------------------------------------------------------------------- */
 /* Learned direction covariance (burn-in only; not in the paper)          */
 /* ---------------------------------------------------------------------- */

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmhar.so")
 SOURCES = [os.path.join(HERE, "csrc", "mhar_kernels.hip"), os.path.join(HERE, "csrc", "mhar_resident.hip"),
            os.path.join(HERE, "csrc", "mhar_precond.hip"), os.path.join(HERE, "csrc", "mhar_lane.hip"),
-           os.path.join(HERE, "csrc", "mhar_dikin.hip"),
+           os.path.join(HERE, "csrc", "mhar_dikin.hip"), os.path.join(HERE, "csrc", "mhar_noalloc.hip"),
            os.path.join(HERE, "csrc", "mhar_api.cpp")]
 HEADERS = [os.path.join(HERE, "csrc", "mhar_device.hpp"), os.path.join(HERE, "csrc", "mhar_internal.hpp"),
            os.path.join(ROOT, "include", "mhar.h")]

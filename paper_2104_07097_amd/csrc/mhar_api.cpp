@@ -1135,6 +1135,54 @@ mhar_status_t mhar_batch_destroy(mhar_batch_t b)
     return MHAR_OK;
 }
 
+mhar_status_t mhar_run_noalloc(int64_t n, int64_t m, const double* A, const double* b,
+                               int64_t m_eq, const double* A_eq, const double* b_eq, int64_t z,
+                               double* X, int32_t* status, uint64_t seed, uint64_t chain_offset,
+                               uint64_t step0, int64_t steps, const mhar_options_t* opt,
+                               void* stream)
+{
+    if (!A || !b || !X || !status) return fail(MHAR_E_INVALID_ARG, "A, b, X and status must be non-NULL");
+    if (steps < 0) return fail(MHAR_E_INVALID_ARG, "steps must be >= 0");
+    if (z < 1 || z > (int64_t(1) << 31)) return fail(MHAR_E_SHAPE, "z must be in [1, 2^31]");
+    mhar_options_t o;
+    mhar_status_t st = check_options(opt, &o);
+    if (st) return st;
+    ProblemDims d;
+    st = check_dims(n, m, m_eq, o, &d);
+    if (st) return st;
+    // the two workspaces the handles would take, carved from the static scratch
+    const size_t pb = (size_t)round_up((int64_t)carve_problem(d, o.precision, nullptr, nullptr), 256);
+    mhar_problem shape{};
+    shape.n = d.n;
+    shape.m = d.m;
+    shape.m_pad = d.m_pad;
+    shape.lda = d.lda;
+    shape.m_eq = d.m_eq;
+    shape.prec = o.precision;
+    const size_t cb = carve_chains(&shape, (int)round_up(z, kChainTile), nullptr, nullptr);
+    void* base = nullptr;
+    size_t cap = 0;
+    MHAR_HIP(noalloc_scratch(&base, &cap), "static scratch address");
+    if (pb + cb > cap)
+        return fail(MHAR_E_WORKSPACE, "this problem needs " + std::to_string(pb + cb) +
+                                          " bytes of scratch; the static scratch holds " + std::to_string(cap));
+    mhar_problem_t prob = nullptr;
+    st = mhar_problem_create(n, m, A, b, m_eq, A_eq, b_eq, &o, base, pb, stream, &prob);
+    if (st) return st;
+    mhar_chains_t ch = nullptr;
+    st = mhar_chains_create(prob, z, X, seed, chain_offset, (char*)base + pb, cb, stream, &ch);
+    if (st) {
+        mhar_problem_destroy(prob);
+        return st;
+    }
+    ch->step = step0;
+    st = mhar_step(ch, steps, stream);
+    if (!st) st = mhar_get_state(ch, X, status, stream);
+    mhar_chains_destroy(ch);
+    mhar_problem_destroy(prob);
+    return st;
+}
+
 static void trace_release(mhar_chains* c)
 {
     for (hipEvent_t e : c->trace_events) (void)hipEventDestroy(e);

@@ -115,6 +115,8 @@ struct StepArgs {
 };
 
 size_t step_lds_bytes(int prec, int lda);
+// address and size of this device's static scratch (mhar_noalloc.hip)
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
 // one persistent launch over (problem, walk tile) units of many problems
 hipError_t launch_batch(int prec, const StepArgs* descs, const int2* units, int nunits,
                         unsigned* next, int max_lda, int grid, hipStream_t stream);

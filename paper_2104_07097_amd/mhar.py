@@ -100,6 +100,8 @@ SIGNATURES = {
     "mhar_precond_get": (_st, [_vp, _vp, _vp, _vp]),
     "mhar_precond_loss": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "mhar_precond_train": (_st, [_vp, _i64, ctypes.c_double, _vp]),
+    "mhar_run_noalloc": (_st, [_i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _u64, _u64,
+                               _u64, _i64, ctypes.POINTER(Options), _vp]),
     "mhar_trace_enable": (_st, [_vp, ctypes.c_int32]),
     "mhar_trace_read": (_st, [_vp, _vp, ctypes.POINTER(Trace)]),
     "mhar_precond_set_complement": (_st, [_vp, ctypes.c_double]),
@@ -225,6 +227,25 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+def run_noalloc(A, b, X, steps, seed=0, chain_offset=0, step0=0, A_eq=None, b_eq=None,
+                precision="fp64", recompute_every=50, path="auto"):
+    """mhar_run_noalloc on torch device tensors: X (z x n FP64, contiguous) is
+    advanced in place; returns the per-walk status bits (int32 tensor)."""
+    import torch
+    lib = load()
+    m, n = A.shape
+    m_eq = 0 if A_eq is None else A_eq.shape[0]
+    st = torch.empty(X.shape[0], dtype=torch.int32, device=X.device)
+    o = options(precision, recompute_every, 0, path)
+    s = _stream(torch, X.device)
+    _check(lib.mhar_run_noalloc(n, m, A.data_ptr(), b.data_ptr(), m_eq,
+                                None if A_eq is None else A_eq.data_ptr(),
+                                None if b_eq is None else b_eq.data_ptr(), X.shape[0], X.data_ptr(),
+                                st.data_ptr(), int(seed), int(chain_offset), int(step0), int(steps),
+                                ctypes.byref(o), s))
+    return st
 
 
 class Chains:
