@@ -65,3 +65,21 @@ def small_cases():
         "split3_xcd": inst.randpoly(n=64, m=1500, z=128, seed=15),
     }
     return cases
+
+
+def ulp_sensitivity(orc, p, steps, P=None, reps=3):
+    """How far the oracle's own trajectory moves after `steps` steps when each
+    state is perturbed by one ulp (relative 2.2e-16, random signs) before every
+    step: the scale of the difference that ulp-level disagreements of log, sin
+    and cos in the directions (all that differs between the HIP path and the
+    oracle) can grow to under the chaotic map.  Max relative error over reps."""
+    Xa, _, _ = orc.run(p.A, p.b, p.X0, steps, seed=0, P=P)
+    worst = 0.0
+    for rep in range(reps):
+        rng = np.random.default_rng(rep)
+        Xb = p.X0.copy()
+        for s in range(steps):
+            Xb = Xb * (1 + 2.2e-16 * rng.choice([-1.0, 1.0], Xb.shape))
+            Xb, _, _ = orc.run(p.A, p.b, Xb, 1, seed=0, P=P, step0=s)
+        worst = max(worst, rel_err(Xb, Xa))
+    return worst

@@ -5,7 +5,10 @@ after 100 steps and to O(1) after ~1000 (measured on the oracle itself).
 Parity is therefore checked
   * per step: from the same state (taken from the oracle), one GPU step and
     one oracle step agree to 1e-11 (relative, max over walks/coordinates);
-  * over short horizons: 30 steps from the start agree to 1e-8;
+  * over 100 steps from the start: agree to within twice the oracle's own
+    sensitivity to one-ulp perturbations of every state (computed per case on
+    the CPU: 8e-15 to 1.1e-10 on these cases), since the GPU's states differ
+    from the oracle's only by ulps of log, sin and cos in the directions;
 in every product precision, since the chord is always evaluated exactly in
 FP64.  Long runs are judged statistically (test_gpu_stats.py)."""
 import numpy as np
@@ -50,15 +53,16 @@ def test_one_step_parity(orc, case, prec):
 def test_short_horizon_parity(orc, case, prec):
     p = gu.small_cases()[case]
     P = gu.oracle_projection(orc, p)
-    gu.announce("30-step", case, prec)
+    gu.announce("100-step", case, prec)
     prob, ch = gu.make(p, prec, recompute_every=7)
-    ch.step(30)
+    ch.step(100)
     got, gst = gu.state(ch)
-    want, st, _ = orc.run(p.A, p.b, p.X0, 30, seed=0, P=P)
+    want, st, _ = orc.run(p.A, p.b, p.X0, 100, seed=0, P=P)
     err = gu.rel_err(got, want)
-    print(f"  rel err after 30 steps {err:.2e}", flush=True)
+    tol = max(1e-13, 2.0 * gu.ulp_sensitivity(orc, p, 100, P=P))
+    print(f"  rel err after 100 steps {err:.2e} (bound {tol:.2e})", flush=True)
     assert not gst.any()
-    assert err <= 1e-8, (case, prec, err)
+    assert err <= tol, (case, prec, err, tol)
     assert gu.feasible(p, got)
 
 

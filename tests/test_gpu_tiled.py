@@ -60,15 +60,16 @@ def test_tiled_one_step_parity(orc, case, prec):
 def test_tiled_short_horizon_parity(orc, case, prec):
     p = cases()[case]
     P = gu.oracle_projection(orc, p)
-    gu.announce("tiled 30-step", case, prec)
+    gu.announce("tiled 100-step", case, prec)
     prob, ch = gu.make(p, prec, recompute_every=7, path="tiled")
-    ch.step(30)
+    ch.step(100)
     got, gst = gu.state(ch)
-    want, _, _ = orc.run(p.A, p.b, p.X0, 30, seed=0, P=P)
+    want, _, _ = orc.run(p.A, p.b, p.X0, 100, seed=0, P=P)
     err = gu.rel_err(got, want)
-    print(f"  rel err after 30 steps {err:.2e}", flush=True)
+    tol = max(1e-13, 2.0 * gu.ulp_sensitivity(orc, p, 100, P=P))
+    print(f"  rel err after 100 steps {err:.2e} (bound {tol:.2e})", flush=True)
     assert not gst.any()
-    assert err <= 1e-8, (case, prec, err)
+    assert err <= tol, (case, prec, err, tol)
     assert gu.feasible(p, got)
 
 

@@ -9,6 +9,7 @@ from oracle import TAG_DIR, Oracle, load
 
 from . import test_oracle_chord as chord
 from . import test_oracle_dikin as dikin
+from . import test_oracle_flags as flags
 from . import test_oracle_precond as precond
 from . import test_oracle_projection as proj
 from . import test_oracle_rng as rng
@@ -38,6 +39,11 @@ PINS = [
     dikin.test_train_step_axis_box_closed_form,
     lambda o: dikin.test_train_step_reaches_closed_form_optimum(o, 8, 2, 1.0),
     lambda o: dikin.test_train_step_reaches_closed_form_optimum(o, 10, 3, 0.3),
+    flags.test_facet_chord_end_is_zero,
+    flags.test_rounding_below_facet_is_clamped,
+    flags.test_past_facet_is_infeasible_and_clamped,
+    flags.test_vertex_leaving_through_two_facets_is_degenerate,
+    flags.test_nan_coordinate_is_nonfinite,
 ]
 
 MUTANTS = {
@@ -67,6 +73,11 @@ MUTANTS = {
     "train_chain_scale": ("gV[i * r + a] = gU[i * r + a] * exp(log_sigma[i]);",
                           "gV[i * r + a] = gU[i * r + a];"),
     "train_chain_rowsum": ("gl[i] += gU[i * r + a] * U[i * r + a];", ";"),
+    "slack_not_clamped": ("if (s < 0.0) s = 0.0;", ";"),
+    "infeasible_no_tolerance": ("if (s < -tol) f |= MHAR_REF_CHAIN_INFEASIBLE;",
+                                "if (s < 0.0) f |= MHAR_REF_CHAIN_INFEASIBLE;"),
+    "degenerate_strict": ("} else if (!(hi > lo)) {", "} else if (!(hi >= lo)) {"),
+    "nonfinite_unchecked": ("if (!finite) flags |= MHAR_REF_CHAIN_NONFINITE;", ";"),
     "dikin_weight_power": ("w[i] = 1.0 / (s * s);", "w[i] = 1.0 / s;"),
     "dikin_row_index": ("v += w[i] * A[i * n + p] * A[i * n + q];",
                         "v += w[i] * A[i * n + p] * A[i * n + p];"),
