@@ -209,6 +209,28 @@ mhar_status_t mhar_get_state(mhar_chains_t chains, double* X, int32_t* status, v
  * resume from a checkpoint.  The states are not re-validated. */
 mhar_status_t mhar_set_state(mhar_chains_t chains, const double* X, uint64_t step, void* stream);
 
+/* Checkpoint of the whole chain and training state (Alg. 2's X_t with the
+ * step counter t, and an attached covariance with its training state): the
+ * states, the per-walk status bits, the step counter and, when a covariance
+ * is attached, U, V, log sigma, the Adam moments and step count, the Dikin
+ * fit's power vector and complement scale, the frozen flag and the fit's
+ * failure flag.  host_buf NULL: *bytes receives the size needed.  Otherwise
+ * host_buf (host memory, *bytes long) is filled after synchronising
+ * `stream`, and *bytes receives the size written.  The slack is not saved:
+ * a restore recomputes it exactly, which leaves the trajectories unchanged
+ * (the chord is evaluated exactly). */
+mhar_status_t mhar_checkpoint(mhar_chains_t chains, void* host_buf, size_t* bytes, void* stream);
+
+/* Restore a checkpoint into chains of the same problem shape, walk count,
+ * seed and chain offset; a checkpoint with a covariance needs one of the
+ * same rank and objective attached first (mhar_precond_create), one without
+ * needs none.  Continuing from the restored handle gives bitwise the
+ * trajectories (and covariance updates) of an uninterrupted run.
+ * Synchronises `stream` before returning (the buffer may then be reused).
+ * Errors: MHAR_E_INVALID_ARG (not a checkpoint, truncated), MHAR_E_SHAPE,
+ * MHAR_E_STATE (seed, chain offset or covariance mismatch). */
+mhar_status_t mhar_restore(mhar_chains_t chains, const void* host_buf, size_t bytes, void* stream);
+
 /* Current step counter (host, no synchronisation). */
 mhar_status_t mhar_get_step(mhar_chains_t chains, uint64_t* step);
 

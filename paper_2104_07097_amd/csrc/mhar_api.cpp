@@ -1183,6 +1183,151 @@ mhar_status_t mhar_run_noalloc(int64_t n, int64_t m, const double* A, const doub
     return st;
 }
 
+// ---- checkpoint and restore ----
+// Host layout: a fixed header, then X (z x n FP64), the status bits (z int32,
+// padded to 8 bytes), and with a covariance U, V, the Adam moments of V (n x r
+// FP64 each), log sigma and the moments of log sigma (n each), the Dikin fit's
+// power vector (n).  Native byte order.
+struct CkptHeader {
+    char magic[8];          // "MHARCKPT"
+    uint32_t version;       // 1
+    uint32_t has_pc;
+    int64_t n, z;
+    uint64_t seed, chain_offset, step;
+    int32_t rank, objective, frozen, fit_status;
+    int64_t adam_t;
+    double kappa;
+};
+
+static size_t ckpt_bytes(const mhar_chains* c)
+{
+    const size_t n = c->p->n, z = c->z;
+    size_t b = sizeof(CkptHeader) + z * n * 8 + (z * 4 + 7) / 8 * 8;
+    if (c->pc_rank) b += 4 * n * c->pc_rank * 8 + 4 * n * 8;
+    return b;
+}
+
+mhar_status_t mhar_checkpoint(mhar_chains_t c, void* host_buf, size_t* bytes, void* stream)
+{
+    if (!c || !bytes) return fail(MHAR_E_INVALID_ARG, "chains and bytes must be non-NULL");
+    const size_t need = ckpt_bytes(c);
+    if (!host_buf) {
+        *bytes = need;
+        return MHAR_OK;
+    }
+    if (*bytes < need) return fail(MHAR_E_WORKSPACE, "checkpoint buffer too small: need " + std::to_string(need) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = c->p->n, z = c->z, r = c->pc_rank;
+    char* out = (char*)host_buf;
+    CkptHeader h{};
+    std::memcpy(h.magic, "MHARCKPT", 8);
+    h.version = 1;
+    h.has_pc = r > 0;
+    h.n = n;
+    h.z = z;
+    h.seed = c->seed;
+    h.chain_offset = c->chain_offset;
+    h.step = c->step;
+    h.rank = r;
+    h.objective = r ? c->pc.objective : 0;
+    h.frozen = c->pc_frozen;
+    h.adam_t = c->pc_t;
+    h.kappa = r ? c->pc.kappa : 0.0;
+    size_t o = sizeof(CkptHeader);
+    MHAR_HIP(hipMemcpy2DAsync(out + o, (size_t)n * 8, c->X, (size_t)c->p->lda * 8, (size_t)n * 8, z,
+                              hipMemcpyDeviceToHost, s), "state read");
+    o += (size_t)z * n * 8;
+    MHAR_HIP(hipMemcpyAsync(out + o, c->flags, (size_t)z * 4, hipMemcpyDeviceToHost, s), "status read");
+    int32_t* st = (int32_t*)(out + o);
+    o += ((size_t)z * 4 + 7) / 8 * 8;
+    int fit = 0;
+    if (r) {
+        const size_t nr = (size_t)n * r * 8, nb = (size_t)n * 8;
+        const double* arrays[4] = {c->pc.U, c->pc.V, c->pc.m1V, c->pc.m2V};
+        for (const double* a : arrays) {
+            MHAR_HIP(hipMemcpyAsync(out + o, a, nr, hipMemcpyDeviceToHost, s), "covariance read");
+            o += nr;
+        }
+        const double* vecs[3] = {c->pc.logsig, c->pc.m1l, c->pc.m2l};
+        for (const double* a : vecs) {
+            MHAR_HIP(hipMemcpyAsync(out + o, a, nb, hipMemcpyDeviceToHost, s), "covariance read");
+            o += nb;
+        }
+        if (c->pc.objective == MHAR_FIT_DIKIN)
+            MHAR_HIP(hipMemcpyAsync(out + o, c->pc.pv, nb, hipMemcpyDeviceToHost, s), "covariance read");
+        else
+            std::memset(out + o, 0, nb);
+        o += nb;
+        MHAR_HIP(hipMemcpyAsync(&fit, c->pc.status, sizeof(int), hipMemcpyDeviceToHost, s), "status read");
+    }
+    MHAR_HIP(hipStreamSynchronize(s), "stream synchronize");
+    for (int k = 0; k < z; ++k) st[k] &= 15;
+    h.fit_status = fit;
+    std::memcpy(out, &h, sizeof(h));
+    *bytes = need;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_restore(mhar_chains_t c, const void* host_buf, size_t bytes, void* stream)
+{
+    if (!c || !host_buf) return fail(MHAR_E_INVALID_ARG, "chains and host_buf must be non-NULL");
+    if (bytes < sizeof(CkptHeader)) return fail(MHAR_E_INVALID_ARG, "not a checkpoint (too short)");
+    CkptHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (std::memcmp(h.magic, "MHARCKPT", 8) != 0 || h.version != 1)
+        return fail(MHAR_E_INVALID_ARG, "not a checkpoint of this library version");
+    const int n = c->p->n, z = c->z, r = c->pc_rank;
+    if (h.n != n || h.z != z) return fail(MHAR_E_SHAPE, "the checkpoint has other n or z");
+    if (h.seed != c->seed || h.chain_offset != c->chain_offset)
+        return fail(MHAR_E_STATE, "the checkpoint was taken with another seed or chain offset");
+    if ((int)h.has_pc != (r > 0) || (r && (h.rank != r || h.objective != c->pc.objective)))
+        return fail(MHAR_E_STATE, "attach a covariance of the checkpoint's rank and objective first "
+                                  "(or detach it when the checkpoint has none)");
+    if (bytes < ckpt_bytes(c)) return fail(MHAR_E_INVALID_ARG, "checkpoint truncated");
+    hipStream_t s = (hipStream_t)stream;
+    const char* in = (const char*)host_buf;
+    size_t o = sizeof(CkptHeader);
+    // the states go through D (zeroed again afterwards) to the padded layout
+    MHAR_HIP(hipMemcpyAsync(c->D, in + o, (size_t)z * n * 8, hipMemcpyHostToDevice, s), "state write");
+    o += (size_t)z * n * 8;
+    MHAR_HIP(launch_copy_states(n, c->p->lda, z, c->z_pad, c->D, c->X, s), "state import");
+    MHAR_HIP(launch_fill_i32((int*)c->D, (int64_t)c->z_pad * c->p->lda * 2, 0, s), "direction reset");
+    MHAR_HIP(launch_fill_i32(c->flags, c->z_pad, 0, s), "status reset");
+    MHAR_HIP(launch_fill_i32((int*)c->theta, (int64_t)c->z_pad * 2, 0, s), "theta reset");
+    const size_t st_off = o;
+    o += ((size_t)z * 4 + 7) / 8 * 8;
+    if (r) {
+        const size_t nr = (size_t)n * r * 8, nb = (size_t)n * 8;
+        double* arrays[4] = {c->pc.U, c->pc.V, c->pc.m1V, c->pc.m2V};
+        for (double* a : arrays) {
+            MHAR_HIP(hipMemcpyAsync(a, in + o, nr, hipMemcpyHostToDevice, s), "covariance write");
+            o += nr;
+        }
+        double* vecs[3] = {c->pc.logsig, c->pc.m1l, c->pc.m2l};
+        for (double* a : vecs) {
+            MHAR_HIP(hipMemcpyAsync(a, in + o, nb, hipMemcpyHostToDevice, s), "covariance write");
+            o += nb;
+        }
+        if (c->pc.objective == MHAR_FIT_DIKIN)
+            MHAR_HIP(hipMemcpyAsync(c->pc.pv, in + o, nb, hipMemcpyHostToDevice, s), "covariance write");
+        o += nb;
+        MHAR_HIP(launch_precond_esig(c->pc, s), "covariance scale");
+        MHAR_HIP(launch_fill_i32(c->pc.status, 1, h.fit_status, s), "fit status");
+        c->pc_t = h.adam_t;
+        c->pc_frozen = h.frozen;
+        c->pc.kappa = h.kappa;
+        c->pc_lr_stale = 1;
+    }
+    c->step = h.step;
+    // exact slack of the restored states, then the saved status bits
+    mhar_status_t st = run_steps(c, 0, 1, nullptr, 0, 0, s);
+    if (st) return st;
+    MHAR_HIP(hipMemcpyAsync(c->flags, in + st_off, (size_t)z * 4, hipMemcpyHostToDevice, s), "status write");
+    // the host buffer may be reused once this returns
+    MHAR_HIP(hipStreamSynchronize(s), "stream synchronize");
+    return MHAR_OK;
+}
+
 static void trace_release(mhar_chains* c)
 {
     for (hipEvent_t e : c->trace_events) (void)hipEventDestroy(e);

@@ -208,6 +208,7 @@ hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_
 hipError_t launch_precond_adam(const PrecondBufs& p, int64_t t, double lr, double b1, double b2,
                                double eps, hipStream_t stream);
 hipError_t launch_precond_mean(const PrecondBufs& p, const double* X, hipStream_t stream);
+hipError_t launch_precond_esig(const PrecondBufs& p, hipStream_t stream);
 hipError_t launch_precond_w(const PrecondBufs& p, hipStream_t stream);
 hipError_t launch_precond_capacitance(const PrecondBufs& p, hipStream_t stream);
 // split screening: workspace bytes, carving, and A P U / ||U||_F after U changed

@@ -58,6 +58,13 @@ __global__ void precond_init_kernel(int n, int r, uint64_t seed, double* U, doub
     }
 }
 
+// exp(l) only (restoring a checkpoint brings V with it)
+__global__ void esig_kernel(int n, const double* logsig, double* esig)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+        esig[j] = exp(logsig[j]);
+}
+
 // scales of a caller-given (U, l): exp(l) and the trained coordinates V = U / exp(l)
 __global__ void scales_kernel(int n, int r, const double* U, const double* logsig, double* esig,
                               double* V, int* status)
@@ -636,6 +643,13 @@ hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_
                        p.GB, p.logsig, p.Sd, p.status, p.gU, p.gl, rowterm);
     hipLaunchKernelGGL(nll_kernel, dim3(1), dim3(256), 0, stream, p.n, p.r, rowterm, p.Cinv, p.GB,
                        p.nll + 1, p.nll);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_esig(const PrecondBufs& p, hipStream_t stream)
+{
+    hipLaunchKernelGGL(esig_kernel, dim3(blocks_for(p.n, 256)), dim3(256), 0, stream, p.n, p.logsig,
+                       p.esig);
     return hipGetLastError();
 }
 

@@ -102,6 +102,8 @@ SIGNATURES = {
     "mhar_precond_train": (_st, [_vp, _i64, ctypes.c_double, _vp]),
     "mhar_run_noalloc": (_st, [_i64, _i64, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _u64, _u64,
                                _u64, _i64, ctypes.POINTER(Options), _vp]),
+    "mhar_checkpoint": (_st, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t), _vp]),
+    "mhar_restore": (_st, [_vp, _vp, ctypes.c_size_t, _vp]),
     "mhar_trace_enable": (_st, [_vp, ctypes.c_int32]),
     "mhar_trace_read": (_st, [_vp, _vp, ctypes.POINTER(Trace)]),
     "mhar_precond_set_complement": (_st, [_vp, ctypes.c_double]),
@@ -306,6 +308,18 @@ class Chains:
         s = Stats()
         _check(load().mhar_get_stats(self.handle, self.stream, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def checkpoint(self) -> bytes:
+        lib = load()
+        sz = ctypes.c_size_t()
+        _check(lib.mhar_checkpoint(self.handle, None, ctypes.byref(sz), self.stream))
+        buf = ctypes.create_string_buffer(sz.value)
+        _check(lib.mhar_checkpoint(self.handle, buf, ctypes.byref(sz), self.stream))
+        return buf.raw[:sz.value]
+
+    def restore(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(load().mhar_restore(self.handle, buf, len(blob), self.stream))
 
     def trace_enable(self, max_launches: int):
         _check(load().mhar_trace_enable(self.handle, int(max_launches)))

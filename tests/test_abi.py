@@ -95,3 +95,12 @@ def test_large_n_only_on_the_tiled_path(n, prec, path, code):
     o = mhar.options(prec, path=path)
     sz = ctypes.c_size_t()
     assert lib.mhar_problem_workspace_size(n, 3 * n, 1, ctypes.byref(o), ctypes.byref(sz)) == code
+
+
+def test_checkpoint_arguments_checked():
+    lib = mhar.load()
+    sz = ctypes.c_size_t()
+    assert lib.mhar_checkpoint(None, None, ctypes.byref(sz), None) == mhar.E_INVALID_ARG
+    assert lib.mhar_restore(None, None, 0, None) == mhar.E_INVALID_ARG
+    assert lib.mhar_trace_read(None, None, None) == mhar.E_INVALID_ARG
+    assert lib.mhar_precond_set_complement(None, 0.5) == mhar.E_INVALID_ARG
