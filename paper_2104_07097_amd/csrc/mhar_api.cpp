@@ -1095,17 +1095,18 @@ mhar_status_t mhar_batch_step(mhar_batch_t b, int64_t steps, void* stream_)
         }
         if (b->ntu > 0) {
             // which steps of this launch some tiled problem recomputes after
-            int first = 0;
+            int first = 0, any_split = 0;
             b->due.assign((size_t)k, 0);
             for (int i = 0; i < b->count; ++i) {
                 if (!b->chains[i]->tiled) continue;   // general-kernel part
                 const StepArgs& a = b->descs_host[i];
                 first |= a.recompute_first;
+                any_split |= a.rk > 0;
                 for (int64_t s = (a.R - 1 - a.since0); s < k; s += a.R) b->due[(size_t)s] = 1;
             }
             MHAR_HIP(launch_grouped(b->prec, b->descs_dev, b->stiles_dev, b->nst, b->tunits_dev,
                                     b->ntu, b->rtiles_dev, b->nrt, (int)k, first, b->due.data(),
-                                    stream), "grouped tiled launch");
+                                    any_split, stream), "grouped tiled launch");
         }
         for (mhar_chains* c : b->chains) advance_schedule(c, k);
         done += k;

@@ -67,9 +67,9 @@ struct StepArgs {
     // A d = A P (exp(l) o h) + (A P U) eps, a contraction over lda + rk columns
     // whose error bound follows each part's norms (rk = 0: not split)
     int rk;                 // r rounded up to 32
-    const void* AUop;       // m_pad x rk operand of A P U (FP32, or bf16 hi then lo)
+    const void* AUop;       // operand of A P U: rows of length lda (first rk used), FP32 or bf16 hi then lo
     const float* aun;       // m_pad, ||(A P U)_i|| rounded up
-    void* Eop;              // z_pad x rk operand of eps (FP32, or bf16 hi then lo)
+    void* Eop;              // operand of eps in the layout of Dop (first rk columns used)
     double* Hs;             // z_pad x lda, the isotropic part P (exp(l) o h) in FP64
     double* hn;             // z_pad, ||P (exp(l) o h)||
     double* en;             // z_pad, ||eps||
@@ -145,7 +145,7 @@ hipError_t launch_tiled(int prec, const StepArgs& a, hipStream_t stream,
 // grouped recompute launch (each tile checks its own problem's schedule)
 hipError_t launch_grouped(int prec, const StepArgs* descs, const int4* stiles, int nst,
                           const int2* units, int nunits, const int4* rtiles, int nrt, int steps,
-                          int first, const unsigned char* due, hipStream_t stream);
+                          int first, const unsigned char* due, int any_split, hipStream_t stream);
 
 // one-time setup
 hipError_t launch_convert_problem(int prec, int n, int m, int m_pad, int lda, const double* A,

@@ -266,14 +266,15 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
             }
         }
         if (a.rk > 0) {
-            // eps as the second block of the screening operand (zero padded to
-            // rk columns) and its norm, before the projection reuses cs->y
+            // eps as the second block of the screening operand (its first rk
+            // columns, zero padded, in the direction operand's layout) and its
+            // norm, before the projection reuses cs->y
             __syncthreads();
-            const size_t zr = (size_t)a.z_pad * a.rk;
+            const size_t zr = (size_t)a.z_pad * lda;
             for (int item = tid; item < kChainTile * a.rk; item += kThreads) {
                 const int cl = item / a.rk, q = item - cl * a.rk, chain = c0 + cl;
                 const float v = (chain < a.z && q < a.r) ? (float)eps[cl * kMaxMeq + q] : 0.0f;
-                const size_t o = (size_t)chain * a.rk + q;
+                const size_t o = (size_t)chain * lda + q;
                 if (a.prec == kBF16X3) {
                     __bf16 hi, lo;
                     split_bf16(v, hi, lo);
@@ -958,7 +959,10 @@ __device__ __forceinline__ void sched_at(const StepArgs& a, int s, int& pending,
 }
 
 // One (256-row block rb, 128-walk block cb) tile of the screening GEMM and its epilogue.
-template <int P>
+// SPLIT: the contraction continues over the rk columns of A P U and eps
+// (a learned covariance); a separate instantiation keeps the isotropic
+// kernel's registers as they were.
+template <int P, bool SPLIT>
 __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int T,
                             unsigned char* smem)
 {
@@ -1009,31 +1013,24 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     const int esz = 16 / F::per16;   // bytes per element
     const int nk = lda / kTK;
     // split screening: after the lda columns of A and the direction operand,
-    // rk more columns of A P U and eps (the chunks keep their row and part)
-    const int nk_all = nk + a.rk / kTK;
+    // rk more columns of A P U and eps, stored with the same row stride, so
+    // each chunk's source moves by one byte offset per operand and plane
+    const int nk_all = SPLIT ? nk + a.rk / kTK : nk;
     auto retarget = [&]() __attribute__((always_inline)) {
-        const int rk = a.rk;
-        const size_t mr = (size_t)a.m_pad * rk, zr = (size_t)a.z_pad * rk;
+        const size_t mz = (size_t)a.m_pad * lda;
 #pragma unroll
         for (int i = 0; i < kPer; ++i) {
-            const int u = tid + i * kThreads;
+            const int u = tid + i * kThreads;   // A chunks first (u < kAChunks), same i for every tid
             if (u < kAChunks) {
-                const int plane = u / (kTR * kChunkRow), rem = u - plane * kTR * kChunkRow;
-                const int row = rem / kChunkRow, part = rem - row * kChunkRow;
-                const size_t off = (size_t)(ok[i] ? R0 + row : 0) * rk + part * F::per16;
-                if (P == kBF16X3)
-                    src[i] = (const unsigned char*)((const __bf16*)a.AUop + plane * mr + off);
-                else
-                    src[i] = (const unsigned char*)((const float*)a.AUop + off);
+                const int plane = u / (kTR * kChunkRow);
+                const unsigned char* from = P == kBF16X3
+                    ? (const unsigned char*)(plane ? a.Alo : a.Ahi)
+                    : (const unsigned char*)a.A32;
+                const unsigned char* to = (const unsigned char*)a.AUop + (size_t)plane * mz * esz;
+                src[i] += to - from;
             } else {
-                const int v = u - kAChunks;
-                const int plane = v / (kTW * kChunkRow), rem = v - plane * kTW * kChunkRow;
-                const int row = rem / kChunkRow, part = rem - row * kChunkRow;
-                const size_t off = (size_t)(ok[i] ? C0 + row : 0) * rk + part * F::per16;
-                if (P == kBF16X3)
-                    src[i] = (const unsigned char*)((const __bf16*)a.Eop + plane * zr + off);
-                else
-                    src[i] = (const unsigned char*)((const float*)a.Eop + off);
+                // eps and the direction operand share their layout (planes of z_pad x lda)
+                src[i] += (const unsigned char*)a.Eop - (const unsigned char*)a.Dop;
             }
         }
     };
@@ -1044,7 +1041,7 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     uint4 ring[kDepth][kPer];
     // K-steps are fetched once each, in increasing order
     auto fetch = [&](uint4* dst, int k) __attribute__((always_inline)) {
-        if (k == nk && nk_all > nk) retarget();
+        if (SPLIT && k == nk && nk_all > nk) retarget();
         const bool live = k < nk_all;
         const int kk = k < nk ? k : k - nk;
 #pragma unroll
@@ -1185,7 +1182,8 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             const int tile = cbase / kChainTile, chain = cbase + c;
             const bool active = chain < a.z;
             float ed, ed2 = 0.0f, Fk = 0.0f;
-            if (a.rk > 0) {
+            const bool split = SPLIT && a.rk > 0;
+            if (split) {
                 // |g_hat - g| <= eps_g (|a| |h| + |a P U| |eps|) + |a| dx
                 const double hn = a.hn[chain], en = a.en[chain];
                 const double dx = 0x1.0p-36 * (hn + a.dn[chain] + *a.uF * en);
@@ -1213,9 +1211,13 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
                     }
                     Gw[idx] = gv;
                     const float na = a.rownorm[row];
-                    const float nau = a.rk > 0 ? a.aun[row] : 0.0f;
-                    const float dl = fmaf(nau, Fk, fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f)));
-                    const float e = fmaf(nau, ed2, na * ed);
+                    float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                    float e = na * ed;
+                    if (split) {
+                        const float nau = a.aun[row];
+                        dl = fmaf(nau, Fk, dl);
+                        e = fmaf(nau, ed2, e);
+                    }
                     float lo_p, hi_p, lo_m, hi_m;
                     ratio_bounds(s_, gv, dl, e, lo_p, hi_p, lo_m, hi_m);
                     up = fminf(up, hi_p);
@@ -1242,18 +1244,19 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     }
 }
 
-template <int P>
+template <int P, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int pending, int T)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nrb = (a.m_pad + kTR - 1) / kTR, ncb = (a.z_pad + kTW - 1) / kTW;
     const int t = xcd_tile(blockIdx.x, nrb * ncb);
     if (t >= nrb * ncb) return;
-    screen_tile<P>(a, t / ncb, t % ncb, pending, T, smem);
+    screen_tile<P, SPLIT>(a, t / ncb, t % ncb, pending, T, smem);
 }
 
-// Screening tiles of many problems: entry (problem, rb, cb) per workgroup.
-template <int P>
+// Screening tiles of many problems: entry (problem, rb, cb) per workgroup
+// (SPLIT when some problem of the batch has a learned covariance).
+template <int P, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void grouped_screen_kernel(const StepArgs* __restrict__ descs,
                                                                   const int4* __restrict__ tiles,
                                                                   int ntiles, int s)
@@ -1265,7 +1268,7 @@ __global__ __launch_bounds__(kThreads) void grouped_screen_kernel(const StepArgs
     int pending, T;
     bool due;
     sched_at(a, s, pending, T, due);
-    screen_tile<P>(a, e.y, e.z, pending, T, smem);
+    screen_tile<P, SPLIT>(a, e.y, e.z, pending, T, smem);
 }
 
 // Chords of step `step` for one 16-walk tile (do_chords), then the directions
@@ -1894,8 +1897,9 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTr
 {
     const size_t lds_s = 2 * (size_t)screen_stage_bytes<P>();
     const size_t lds_r = 2 * (size_t)kRStage;
-    hipError_t e = hipFuncSetAttribute((const void*)tiled_screen_kernel<P>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
+    const void* screen_fn = a.rk > 0 ? (const void*)tiled_screen_kernel<P, true>
+                                     : (const void*)tiled_screen_kernel<P, false>;
+    hipError_t e = hipFuncSetAttribute(screen_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)tiled_recompute_kernel,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
@@ -1930,8 +1934,12 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTr
         const bool more = s + 1 < a.steps;
         {
             TraceScope ts_(trace, stream, kTraceScreen);
-            hipLaunchKernelGGL(tiled_screen_kernel<P>, grid_s, dim3(kThreads), lds_s, stream, a,
-                               pending, T);
+            if (a.rk > 0)
+                hipLaunchKernelGGL((tiled_screen_kernel<P, true>), grid_s, dim3(kThreads), lds_s,
+                                   stream, a, pending, T);
+            else
+                hipLaunchKernelGGL((tiled_screen_kernel<P, false>), grid_s, dim3(kThreads), lds_s,
+                                   stream, a, pending, T);
         }
         {
             TraceScope ts_(trace, stream, kTraceChords);
@@ -1962,12 +1970,13 @@ template <int P>
 static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, int nst,
                                    const int2* units, int nunits, const int4* rtiles, int nrt,
                                    int steps, int first, const unsigned char* due,
-                                   hipStream_t stream)
+                                   int any_split, hipStream_t stream)
 {
     const size_t lds_s = 2 * (size_t)screen_stage_bytes<P>();
     const size_t lds_r = 2 * (size_t)kRStage;
-    hipError_t e = hipFuncSetAttribute((const void*)grouped_screen_kernel<P>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
+    const void* screen_fn = any_split ? (const void*)grouped_screen_kernel<P, true>
+                                      : (const void*)grouped_screen_kernel<P, false>;
+    hipError_t e = hipFuncSetAttribute(screen_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)grouped_recompute_kernel,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
@@ -1979,8 +1988,12 @@ static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, in
         hipLaunchKernelGGL(grouped_chords_kernel<P>, dim3(nunits), dim3(kThreads), 0, stream, descs,
                            units, nunits, 0, 0, 1);
     for (int s = 0; s < steps; ++s) {
-        hipLaunchKernelGGL(grouped_screen_kernel<P>, dim3(nst), dim3(kThreads), lds_s, stream, descs,
-                           stiles, nst, s);
+        if (any_split)
+            hipLaunchKernelGGL((grouped_screen_kernel<P, true>), dim3(nst), dim3(kThreads), lds_s,
+                               stream, descs, stiles, nst, s);
+        else
+            hipLaunchKernelGGL((grouped_screen_kernel<P, false>), dim3(nst), dim3(kThreads), lds_s,
+                               stream, descs, stiles, nst, s);
         hipLaunchKernelGGL(grouped_chords_kernel<P>, dim3(nunits), dim3(kThreads), 0, stream, descs,
                            units, nunits, s, 1, (int)(s + 1 < steps));
         if (due[s])
@@ -1994,13 +2007,13 @@ static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, in
 
 hipError_t launch_grouped(int prec, const StepArgs* descs, const int4* stiles, int nst,
                           const int2* units, int nunits, const int4* rtiles, int nrt, int steps,
-                          int first, const unsigned char* due, hipStream_t stream)
+                          int first, const unsigned char* due, int any_split, hipStream_t stream)
 {
     switch (prec) {
     case kFP32: return launch_grouped_t<kFP32>(descs, stiles, nst, units, nunits, rtiles, nrt, steps,
-                                               first, due, stream);
+                                               first, due, any_split, stream);
     case kBF16X3: return launch_grouped_t<kBF16X3>(descs, stiles, nst, units, nunits, rtiles, nrt,
-                                                   steps, first, due, stream);
+                                                   steps, first, due, any_split, stream);
     default: return hipErrorInvalidValue;
     }
 }

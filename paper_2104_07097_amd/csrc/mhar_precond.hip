@@ -447,8 +447,8 @@ __global__ void lowrank_pu_kernel(int n, int lda, int r, int m_eq, const double*
 }
 
 // Row i of A P U (FP64, lane = rank column, sequential over the coordinates),
-// written as the screening operand (rk columns, zero padded) with its norm
-// rounded up; one wave per row
+// written as the screening operand (the first rk columns of a row of length
+// lda, as A's operand, zero padded) with its norm rounded up; one wave per row
 __global__ __launch_bounds__(256) void lowrank_au_kernel(int n, int lda, int r, int rk, int m_pad,
                                                          int bf16, const double* __restrict__ A64,
                                                          const double* __restrict__ PU,
@@ -463,12 +463,12 @@ __global__ __launch_bounds__(256) void lowrank_au_kernel(int n, int lda, int r, 
         for (int j = 0; j < n; ++j) v = fma(ar[j], PU[(size_t)j * r + q], v);
     const double nrm = sqrt(wave_sum(v * v));
     if (q < rk) {
-        const size_t o = (size_t)i * rk + q;
+        const size_t o = (size_t)i * lda + q;
         if (bf16) {
             __bf16 hi, lo;
             split_bf16((float)v, hi, lo);
             ((__bf16*)AUop)[o] = hi;
-            ((__bf16*)AUop)[(size_t)m_pad * rk + o] = lo;
+            ((__bf16*)AUop)[(size_t)m_pad * lda + o] = lo;
         } else {
             ((float*)AUop)[o] = (float)v;
         }
@@ -500,9 +500,11 @@ size_t lowrank_bytes(int prec, int n, int r, int m_pad, int lda, int z_pad, int 
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     const size_t rk = (size_t)round_up(r, 32);
     size_t b = 0;
-    b += al((size_t)m_pad * rk * 4);       // A P U operand (FP32, or bf16 hi + lo)
+    // the operands keep the row stride lda of A's and the direction's, of
+    // which the first rk columns are used
+    b += al((size_t)m_pad * lda * 4);      // A P U operand (FP32, or bf16 hi + lo)
     b += al((size_t)m_pad * 4);            // its row norms
-    b += al((size_t)z_pad * rk * 4);       // eps operand
+    b += al((size_t)z_pad * lda * 4);      // eps operand
     b += al((size_t)n * r * 8);            // P U
     b += al((size_t)(m_eq > 0 ? m_eq : 1) * r * 8);   // A_eq U
     b += al(64);                           // ||U||_F
@@ -523,9 +525,9 @@ void lowrank_carve(PrecondBufs* p, void* ws)
     };
     const size_t rk = (size_t)round_up(p->r, 32);
     p->rk = (int)rk;
-    p->AUop = take((size_t)p->m_pad * rk * 4);
+    p->AUop = take((size_t)p->m_pad * p->lda * 4);
     p->aun = (float*)take((size_t)p->m_pad * 4);
-    p->Eop = take((size_t)p->z_pad * rk * 4);
+    p->Eop = take((size_t)p->z_pad * p->lda * 4);
     p->PU = (double*)take((size_t)p->n * p->r * 8);
     p->uF = (double*)take(64);
     double* aequ = (double*)take((size_t)(p->m_eq > 0 ? p->m_eq : 1) * p->r * 8);
