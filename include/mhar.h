@@ -392,11 +392,45 @@ mhar_status_t mhar_batch_create(int32_t count, const mhar_chains_t* chains, void
 /* Enqueue `steps` steps of every handle in the batch. */
 mhar_status_t mhar_batch_step(mhar_batch_t batch, int64_t steps, void* stream);
 
-/* Release the batch; the handles return to their own kernel paths.  The
- * batch is released even when the wait for its last descriptor copy or the
- * release of its pinned buffer reports an error, which is then returned
- * (MHAR_E_HIP). */
+/* Release the batch; the handles return to their own kernel paths (a
+ * packed batch destroys the handles it created).  The batch is released
+ * even when the wait for its last descriptor copy or the release of its
+ * pinned buffer reports an error, which is then returned (MHAR_E_HIP). */
 mhar_status_t mhar_batch_destroy(mhar_batch_t batch);
+
+/* Packed batches: `count` inequality-only polytopes {A_i x <= b_i} (paper
+ * S2.1) given as one device array per field plus host offsets, so that a
+ * caller can hold each field of the whole batch in one tensor:
+ *   n, m, z       host arrays of count sizes (n_i <= 1152, any m_i, z_i >= 1);
+ *   A_packed      dev FP64; problem i's A (m_i x n_i row-major) starts at
+ *                 element A_offsets[i] (host array);
+ *   b_packed      dev FP64; b_i (m_i) starts at b_offsets[i];
+ *   X0_packed     dev FP64; the start points of problem i (z_i x n_i
+ *                 row-major, walk k in row k) start at X0_offsets[i].
+ * Walk k of problem i draws its random numbers as walk W_i + k of `seed`,
+ * W_i = z_0 + ... + z_{i-1}, so every walk of the batch has its own stream
+ * (the total must not exceed 2^32).  One precision (opt) for all problems.
+ * The library creates a problem and a chains handle per polytope inside
+ * the workspace (dev, 256-byte aligned, ws_bytes >= the size below), checks
+ * that every start point is strictly interior (one synchronisation of
+ * `stream` per problem; MHAR_E_NOT_INTERIOR names the problem), and returns
+ * a batch that owns them: read them through mhar_batch_get_chains and step
+ * them with mhar_batch_step; mhar_batch_destroy releases them.  The packed
+ * inputs may be freed once the call returns.  Errors leave nothing
+ * allocated. */
+mhar_status_t mhar_batch_packed_workspace_size(int32_t count, const int64_t* n, const int64_t* m,
+                                               const int64_t* z, const mhar_options_t* opt, size_t* bytes);
+mhar_status_t mhar_batch_create_packed(int32_t count, const int64_t* n, const int64_t* m, const int64_t* z,
+                                       const double* A_packed, const int64_t* A_offsets,
+                                       const double* b_packed, const int64_t* b_offsets,
+                                       const double* X0_packed, const int64_t* X0_offsets, uint64_t seed,
+                                       const mhar_options_t* opt, void* workspace, size_t ws_bytes,
+                                       void* stream, mhar_batch_t* out);
+
+/* The chains handle of problem i (0 <= i < count) of a batch, borrowed: it
+ * stays valid while the batch lives; for mhar_get_state, mhar_record and
+ * the other per-handle calls. */
+mhar_status_t mhar_batch_get_chains(mhar_batch_t batch, int32_t i, mhar_chains_t* out);
 
 #ifdef __cplusplus
 }

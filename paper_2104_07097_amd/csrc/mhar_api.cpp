@@ -90,6 +90,9 @@ struct mhar_batch {
     int4* stiles_dev;
     int4* rtiles_dev;
     std::vector<unsigned char> due; // per step of a launch: some problem recomputes after it
+    // packed creation: the batch owns its problems and chains handles
+    std::vector<mhar_problem*> owned_problems;
+    bool owns_chains = false;
 };
 
 namespace {
@@ -1131,8 +1134,131 @@ mhar_status_t mhar_batch_destroy(mhar_batch_t b)
     if (e == hipSuccess) e = e2;
     e2 = hipHostFree(b->descs_host);
     if (e == hipSuccess) e = e2;
+    if (b->owns_chains)
+        for (mhar_chains* c : b->chains) mhar_chains_destroy(c);
+    for (mhar_problem* p : b->owned_problems) mhar_problem_destroy(p);
     delete b;
     if (e != hipSuccess) return hip_fail(e, "batch teardown");
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_batch_get_chains(mhar_batch_t b, int32_t i, mhar_chains_t* out)
+{
+    if (!b || !out) return fail(MHAR_E_INVALID_ARG, "batch and out must be non-NULL");
+    if (i < 0 || i >= b->count) return fail(MHAR_E_INVALID_ARG, "index outside the batch");
+    *out = b->chains[i];
+    return MHAR_OK;
+}
+
+// Workspace of a packed batch: per problem its problem workspace then its
+// chains workspace (each 256-byte aligned), then the batch tables sized for
+// the larger of the two kernel paths of every problem.
+static mhar_status_t packed_layout(int32_t count, const int64_t* n, const int64_t* m, const int64_t* z,
+                                   const mhar_options_t& o, std::vector<size_t>* offs, size_t* total)
+{
+    if (count < 1 || !n || !m || !z) return fail(MHAR_E_INVALID_ARG, "need count >= 1 and the n, m, z arrays");
+    size_t at = 0;
+    BatchPlan bound;
+    uint64_t walks = 0;
+    for (int i = 0; i < count; ++i) {
+        ProblemDims d;
+        mhar_status_t st = check_dims(n[i], m[i], 0, o, &d);
+        if (st) return fail(st, "problem " + std::to_string(i) + ": " + g_last_error);
+        if (d.lda > kMaxN) return fail(MHAR_E_UNSUPPORTED, "problem " + std::to_string(i) + ": batches take n <= " + std::to_string(kMaxN));
+        if (z[i] < 1 || z[i] > (int64_t(1) << 31)) return fail(MHAR_E_SHAPE, "z must be in [1, 2^31]");
+        walks += (uint64_t)z[i];
+        if (walks > (uint64_t(1) << 32)) return fail(MHAR_E_SHAPE, "the batch's walks must number at most 2^32");
+        mhar_problem shape{};
+        shape.n = d.n;
+        shape.m = d.m;
+        shape.m_pad = d.m_pad;
+        shape.lda = d.lda;
+        shape.prec = o.precision;
+        const size_t pb = carve_problem(d, o.precision, nullptr, nullptr);
+        const int z_pad = (int)round_up(z[i], kChainTile);
+        const size_t cb = carve_chains(&shape, z_pad, nullptr, nullptr);
+        if (offs) offs->push_back(at);
+        at += (size_t)round_up((int64_t)pb, 256);
+        if (offs) offs->push_back(at);
+        at += (size_t)round_up((int64_t)cb, 256);
+        const int tiles = z_pad / kChainTile;
+        bound.gen_units.resize(bound.gen_units.size() + tiles);
+        bound.tiled_units.resize(bound.tiled_units.size() + tiles);
+        bound.stiles.resize(bound.stiles.size() + (size_t)((d.m_pad + kScreenRows - 1) / kScreenRows) *
+                                                     ((z_pad + kScreenWalks - 1) / kScreenWalks));
+        bound.rtiles.resize(bound.rtiles.size() + (size_t)((d.m_pad + kRecRows - 1) / kRecRows) *
+                                                     ((z_pad + kRecWalks - 1) / kRecWalks));
+    }
+    if (offs) offs->push_back(at);
+    *total = at + carve_batch(count, bound, nullptr, nullptr);
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_batch_packed_workspace_size(int32_t count, const int64_t* n, const int64_t* m,
+                                               const int64_t* z, const mhar_options_t* opt, size_t* bytes)
+{
+    if (!bytes) return fail(MHAR_E_INVALID_ARG, "bytes is NULL");
+    mhar_options_t o;
+    mhar_status_t st = check_options(opt, &o);
+    if (st) return st;
+    return packed_layout(count, n, m, z, o, nullptr, bytes);
+}
+
+mhar_status_t mhar_batch_create_packed(int32_t count, const int64_t* n, const int64_t* m, const int64_t* z,
+                                       const double* A_packed, const int64_t* A_offsets,
+                                       const double* b_packed, const int64_t* b_offsets,
+                                       const double* X0_packed, const int64_t* X0_offsets, uint64_t seed,
+                                       const mhar_options_t* opt, void* ws, size_t ws_bytes, void* stream,
+                                       mhar_batch_t* out)
+{
+    if (!out) return fail(MHAR_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!A_packed || !A_offsets || !b_packed || !b_offsets || !X0_packed || !X0_offsets)
+        return fail(MHAR_E_INVALID_ARG, "packed arrays and offsets must be non-NULL");
+    mhar_options_t o;
+    mhar_status_t st = check_options(opt, &o);
+    if (st) return st;
+    std::vector<size_t> offs;
+    size_t need = 0;
+    st = packed_layout(count, n, m, z, o, &offs, &need);
+    if (st) return st;
+    for (int i = 0; i < count; ++i)
+        if (A_offsets[i] < 0 || b_offsets[i] < 0 || X0_offsets[i] < 0)
+            return fail(MHAR_E_INVALID_ARG, "negative offset for problem " + std::to_string(i));
+    if (!ws || !aligned256(ws)) return fail(MHAR_E_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < need) return fail(MHAR_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+    unsigned char* base = (unsigned char*)ws;
+    std::vector<mhar_problem*> probs;
+    std::vector<mhar_chains_t> chains;
+    auto cleanup = [&](mhar_status_t code) {
+        const std::string msg = g_last_error;
+        for (mhar_chains* c : chains) mhar_chains_destroy(c);
+        for (mhar_problem* p : probs) mhar_problem_destroy(p);
+        g_last_error = msg;
+        return code;
+    };
+    uint64_t walk0 = 0;
+    for (int i = 0; i < count; ++i) {
+        const size_t p_at = offs[2 * i], c_at = offs[2 * i + 1], end = offs[2 * i + 2];
+        mhar_problem_t p = nullptr;
+        st = mhar_problem_create(n[i], m[i], A_packed + A_offsets[i], b_packed + b_offsets[i], 0, nullptr,
+                                 nullptr, &o, base + p_at, c_at - p_at, stream, &p);
+        if (st) return cleanup(fail(st, "problem " + std::to_string(i) + ": " + g_last_error));
+        probs.push_back(p);
+        mhar_chains_t c = nullptr;
+        st = mhar_chains_create(p, z[i], X0_packed + X0_offsets[i], seed, walk0, base + c_at, end - c_at,
+                                stream, &c);
+        if (st) return cleanup(fail(st, "problem " + std::to_string(i) + ": " + g_last_error));
+        chains.push_back(c);
+        walk0 += (uint64_t)z[i];
+    }
+    const size_t tab = offs[2 * count];
+    mhar_batch_t b = nullptr;
+    st = mhar_batch_create(count, chains.data(), base + tab, ws_bytes - tab, &b);
+    if (st) return cleanup(st);
+    b->owned_problems = probs;
+    b->owns_chains = true;
+    *out = b;
     return MHAR_OK;
 }
 

@@ -113,6 +113,12 @@ SIGNATURES = {
     "mhar_batch_create": (_st, [ctypes.c_int32, ctypes.POINTER(_vp), _vp, ctypes.c_size_t,
                                 ctypes.POINTER(_vp)]),
     "mhar_batch_step": (_st, [_vp, _i64, _vp]),
+    "mhar_batch_packed_workspace_size": (_st, [ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(Options),
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+    "mhar_batch_create_packed": (_st, [ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       _u64, ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
+                                       ctypes.POINTER(_vp)]),
+    "mhar_batch_get_chains": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "mhar_batch_destroy": (_st, [_vp]),
 }
 
@@ -408,6 +414,78 @@ class Batch:
 
     def step(self, steps: int):
         _check(load().mhar_batch_step(self.handle, int(steps), _stream(self.torch, self.device)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().mhar_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PackedBatch:
+    """Polytopes given as packed device arrays with host offsets, stepped as
+    one batch (mhar_batch_create_packed); the batch owns its handles."""
+
+    def __init__(self, n, m, z, A_packed, A_offsets, b_packed, b_offsets, X0_packed, X0_offsets,
+                 seed=0, precision="fp32", recompute_every=50, path="auto"):
+        import torch
+        self.torch = torch
+        self.device = A_packed.device
+        self.n, self.m, self.z = [int(v) for v in n], [int(v) for v in m], [int(v) for v in z]
+        count = len(self.n)
+        i64 = lambda v: (ctypes.c_int64 * count)(*[int(x) for x in v])
+        self._arrays = [i64(self.n), i64(self.m), i64(self.z), i64(A_offsets), i64(b_offsets),
+                        i64(X0_offsets)]
+        cn, cm, cz, ao, bo, xo = [ctypes.cast(a, _vp) for a in self._arrays]
+        self.opt = options(precision, recompute_every, 0, path)
+        lib = load()
+        sz = ctypes.c_size_t()
+        _check(lib.mhar_batch_packed_workspace_size(count, cn, cm, cz, ctypes.byref(self.opt),
+                                                    ctypes.byref(sz)))
+        self._ws, ptr, nbytes = _workspace(torch, sz.value, self.device)
+        h = ctypes.c_void_p()
+        f64 = lambda t: t.to(device=self.device, dtype=torch.float64).contiguous()
+        A_packed, b_packed, X0_packed = f64(A_packed), f64(b_packed), f64(X0_packed)
+        _check(lib.mhar_batch_create_packed(count, cn, cm, cz, A_packed.data_ptr(), ao, b_packed.data_ptr(),
+                                            bo, X0_packed.data_ptr(), xo, int(seed), ctypes.byref(self.opt),
+                                            ptr, nbytes, _stream(torch, self.device), ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_lists(cls, As, bs, X0s, **kw):
+        """Pack per-problem tensors (A_i m_i x n_i, b_i, X0_i z_i x n_i)."""
+        import torch
+        def pack(ts):
+            flat = [t.reshape(-1) for t in ts]
+            offs = [0]
+            for t in flat[:-1]:
+                offs.append(offs[-1] + t.numel())
+            return torch.cat(flat), offs
+        Ap, Ao = pack(As)
+        bp, bo = pack(bs)
+        Xp, Xo = pack(X0s)
+        return cls([a.shape[1] for a in As], [a.shape[0] for a in As], [x.shape[0] for x in X0s],
+                   Ap, Ao, bp, bo, Xp, Xo, **kw)
+
+    def chains_handle(self, i: int):
+        h = ctypes.c_void_p()
+        _check(load().mhar_batch_get_chains(self.handle, int(i), ctypes.byref(h)))
+        return h
+
+    def step(self, steps: int):
+        _check(load().mhar_batch_step(self.handle, int(steps), _stream(self.torch, self.device)))
+
+    def state(self, i: int):
+        X = self.torch.empty((self.z[i], self.n[i]), dtype=self.torch.float64, device=self.device)
+        st = self.torch.empty(self.z[i], dtype=self.torch.int32, device=self.device)
+        _check(load().mhar_get_state(self.chains_handle(i), X.data_ptr(), st.data_ptr(),
+                                     _stream(self.torch, self.device)))
+        return X, st
 
     def close(self):
         if getattr(self, "handle", None):

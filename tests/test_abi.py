@@ -104,3 +104,32 @@ def test_checkpoint_arguments_checked():
     assert lib.mhar_restore(None, None, 0, None) == mhar.E_INVALID_ARG
     assert lib.mhar_trace_read(None, None, None) == mhar.E_INVALID_ARG
     assert lib.mhar_precond_set_complement(None, 0.5) == mhar.E_INVALID_ARG
+
+
+def test_packed_batch_sizes_and_arguments():
+    lib = mhar.load()
+    arr = lambda *v: (ctypes.c_int64 * len(v))(*v)
+    sz = ctypes.c_size_t()
+    o = mhar.options("fp32")
+    assert lib.mhar_batch_packed_workspace_size(2, arr(20, 40), arr(100, 300), arr(64, 64),
+                                                ctypes.byref(o), ctypes.byref(sz)) == mhar.OK
+    small = sz.value
+    assert lib.mhar_batch_packed_workspace_size(2, arr(20, 40), arr(100, 300), arr(64, 640),
+                                                ctypes.byref(o), ctypes.byref(sz)) == mhar.OK
+    assert sz.value > small > 0
+    # each problem's handles and the batch tables: at least both problem workspaces
+    p1, p2 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.mhar_problem_workspace_size(20, 100, 0, ctypes.byref(o), ctypes.byref(p1)) == mhar.OK
+    assert lib.mhar_problem_workspace_size(40, 300, 0, ctypes.byref(o), ctypes.byref(p2)) == mhar.OK
+    assert small > p1.value + p2.value
+    for count, n, code in [(0, (20,), mhar.E_INVALID_ARG), (1, (0,), mhar.E_SHAPE),
+                           (1, (2000,), mhar.E_UNSUPPORTED)]:
+        assert lib.mhar_batch_packed_workspace_size(count, arr(*n), arr(100), arr(16), ctypes.byref(o),
+                                                    ctypes.byref(sz)) == code, (count, n)
+    assert lib.mhar_batch_packed_workspace_size(1, arr(20), arr(100), arr(0), ctypes.byref(o),
+                                                ctypes.byref(sz)) == mhar.E_SHAPE
+    h = ctypes.c_void_p()
+    offs = arr(0)
+    assert lib.mhar_batch_create_packed(1, arr(20), arr(100), arr(16), None, offs, None, offs, None, offs, 0,
+                                        ctypes.byref(o), None, 0, None, ctypes.byref(h)) == mhar.E_INVALID_ARG
+    assert lib.mhar_batch_get_chains(None, 0, ctypes.byref(h)) == mhar.E_INVALID_ARG
