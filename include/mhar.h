@@ -98,7 +98,7 @@ typedef enum {
     MHAR_PATH_GENERAL = 1,   /* one workgroup per 16 walks over all rows, slack in HBM */
     MHAR_PATH_RESIDENT = 2,  /* slack in registers, rows split over co-resident workgroups;
                                 FP32/BF16X3, n <= 256, m <= 8192 (else MHAR_E_UNSUPPORTED) */
-    MHAR_PATH_TILED = 3,     /* per step a screening GEMM over 256-row x 128-walk tiles and a
+    MHAR_PATH_TILED = 3,     /* per step a screening GEMM over 128-row x 128-walk tiles and a
                                 chords kernel; FP32/BF16X3 (else MHAR_E_UNSUPPORTED) */
     MHAR_PATH_LANE = 4       /* a few lanes per walk, every row evaluated exactly in FP64 each
                                 step (no screening product, so any precision); n <= 32, or

@@ -323,7 +323,7 @@ StepArgs make_args(const mhar_chains* c)
 
 // Automatic choice between the general and the tiled path (reduced
 // precision only): the general kernel streams all of A once per 16 walks, the
-// tiled path once per 128 walks and one row tile of D per 256 rows, which wins
+// tiled path once per 128 walks and one row tile of D per 128 rows, which wins
 // once A no longer sits in one XCD's L2.
 int use_tiled(const mhar_problem* p, int z_pad)
 {

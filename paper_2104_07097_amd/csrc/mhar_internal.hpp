@@ -16,7 +16,7 @@ constexpr int kKAlign = 32;      // padded row length (K) granularity
 constexpr int kMaxN = 1152;      // LDS holds 16 padded FP64 rows of length <= kMaxN
 constexpr int kMaxNResident = 256;  // longest padded row of the register-resident kernel
 constexpr int kMaxNTiled = 8192; // the tiled path keeps no row of length n in LDS
-constexpr int kScreenRows = 256; // tiled path: rows x walks of a screening tile
+constexpr int kScreenRows = 128; // tiled path: rows x walks of a screening tile
 constexpr int kScreenWalks = 128;
 constexpr int kRecRows = 256;    // tiled path: rows x walks of a recompute tile
 constexpr int kRecWalks = 64;

@@ -898,9 +898,10 @@ __global__ __launch_bounds__(kThreads) void mhar_batch_kernel(const StepArgs* __
 // With one workgroup per 16 walks, every workgroup streams all of A each
 // step, which bounds large problems by the A stream.  The tiled path splits a
 // step into three kernels instead:
-//   tiled_screen : G = A D as a GEMM over (256-row x 128-walk) tiles with A and
-//                  the direction operand staged through LDS (double buffered),
-//                  fused with the deferred slack update and the ratio bounds;
+//   tiled_screen : G = A D as a GEMM over (128-row x 128-walk) tiles, two
+//                  workgroups of 4 waves per CU, operands streamed by direct
+//                  global-to-LDS loads through two stages, fused with the
+//                  deferred slack update and the ratio bounds;
 //                  per (64-row group, walk) it writes the least lower bound
 //                  and the least upper bound of each chord end;
 //   tiled_chords : per 16-walk tile, the chord-end bound as the minimum over
@@ -919,31 +920,48 @@ constexpr int kTR = kScreenRows;   // rows per screening tile
 constexpr int kTW = kScreenWalks;  // walks per screening tile
 constexpr int kTK = 32;    // K per LDS stage
 
+constexpr int kScreenThreads = 256;   // 4 waves, each a 64-row x 64-walk quarter of a tile
+constexpr int kStageBytes = 32768;    // one K-step of both operands, in either format
+constexpr int kChunksPerWave = kStageBytes / 1024 / (kScreenThreads / 64);   // 8
+
+// A stage holds one K-step (32 columns) of the tile's 128 rows of A and 128
+// walks of the direction operand in four planes of 128 rows x 64 bytes:
+//   BF16X3: A hi | A lo | D hi | D lo (32 BF16 columns per row)
+//   FP32:   A columns 0-15 | A columns 16-31 | D columns 0-15 | D columns 16-31
+// filled by direct global-to-LDS loads: one load instruction writes 1 KB (64
+// lanes x 16 bytes) of consecutive LDS, and each lane fetches the global 16
+// bytes that belong in its slot.  Rows are not padded; the four 16-byte slots
+// of row r are permuted by an XOR with (r >> 1) & 3, which measurements of
+// ds_read_b128 on gfx950 show to be free of bank conflicts for the MFMA
+// operand reads (16 rows at one slot), unlike row padding or an XOR with r.
+constexpr int kPlaneBytes = 8192;
 template <int P> struct TileFmt;
 template <> struct TileFmt<kBF16X3> {
-    static constexpr int planes = 2;       // hi, lo
-    static constexpr int per16 = 8;        // elements per 16-byte chunk
-    static constexpr int row_bytes = 80;   // 32 bf16 + 16 bytes of padding
+    static constexpr int per16 = 8;           // elements per 16-byte slot
 };
 template <> struct TileFmt<kFP32> {
-    static constexpr int planes = 1;
     static constexpr int per16 = 4;
-    static constexpr int row_bytes = 144;  // 32 floats + 16 bytes of padding
 };
-
-template <int P>
-__host__ __device__ constexpr int screen_stage_bytes()
-{
-    return TileFmt<P>::planes * (kTR + kTW) * TileFmt<P>::row_bytes;
-}
+__device__ __forceinline__ int slot_swz(int row) { return (row >> 1) & 3; }
 
 // Tile t of the launch for workgroup `bid`: workgroups are dealt round-robin to
-// the 8 XCDs, so XCD x gets the contiguous tile range [x*per, (x+1)*per) and
-// its concurrently resident workgroups share row blocks of A in its L2.
+// the 8 XCDs, so XCD x gets the contiguous tile range [x*per, (x+1)*per).
 __device__ __forceinline__ int xcd_tile(int bid, int total)
 {
     const int per = (total + 7) >> 3;
     return (bid & 7) * per + (bid >> 3);
+}
+
+// Tile t in groups of kTileGroup row blocks taken column by column, so that
+// the tiles an XCD runs at once share a few row blocks of A and a few walk
+// blocks of the direction operand in its L2.
+constexpr int kTileGroup = 4;
+__device__ __forceinline__ void tile_coords(int t, int nrb, int ncb, int& rb, int& cb)
+{
+    const int span = kTileGroup * ncb, first = t / span * kTileGroup;
+    const int gsz = min(nrb - first, kTileGroup), r = t - t / span * span;
+    rb = first + r % gsz;
+    cb = r / gsz;
 }
 
 // Slack schedule of step s of a launch (s = 0 is the launch's first step):
@@ -958,101 +976,101 @@ __device__ __forceinline__ void sched_at(const StepArgs& a, int s, int& pending,
     recompute_after = since + 1 == a.R;
 }
 
-// One (256-row block rb, 128-walk block cb) tile of the screening GEMM and its epilogue.
+// Wait until at most N vector-memory operations of this wave are outstanding
+// (gfx9 s_waitcnt encoding; expcnt and lgkmcnt left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// Wait for this wave's LDS reads.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+// Workgroup barrier that the compiler may not move memory accesses across and
+// that does not itself wait for the stage loads in flight (wait_vm says which
+// loads must have landed).
+__device__ __forceinline__ void tile_barrier() { asm volatile("s_barrier" ::: "memory"); }
+// 16 bytes from global memory to LDS byte address lds + 16 * lane (the LDS
+// base is wave-uniform, in M0).  The instruction returns nothing to
+// registers; its completion is counted by vmcnt like any load, and the
+// "memory" clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void load_to_lds(const void* src, unsigned lds)
+{
+    asm volatile("global_load_lds_dwordx4 %0, off" :: "v"(src), "{m0}"(lds) : "memory");
+}
+
+// One (128-row block rb, 128-walk block cb) tile of the screening GEMM and its epilogue.
 // SPLIT: the contraction continues over the rk columns of A P U and eps
 // (a learned covariance); a separate instantiation keeps the isotropic
 // kernel's registers as they were.
 template <int P, bool SPLIT>
-__device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int T,
-                            unsigned char* smem)
+__device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int T)
 {
     typedef TileFmt<P> F;
-    constexpr int kChunkRow = kTK / F::per16;              // 16-byte chunks per row and plane
-    constexpr int kAChunks = F::planes * kTR * kChunkRow;  // 2048 in both formats
-    constexpr int kChunks = F::planes * (kTR + kTW) * kChunkRow;
-    constexpr int kPer = kChunks / kThreads;               // 6
-    static_assert(kChunks % kThreads == 0, "chunk split");
+    __shared__ __align__(1024) unsigned char stage0[kStageBytes];
+    __shared__ __align__(1024) unsigned char stage1[kStageBytes];
+    constexpr int esz = 16 / F::per16;   // bytes per element
     const int R0 = rb * kTR, C0 = cb * kTW;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the stage loads' LDS base
     const int g = lane >> 4, c = lane & 15;
-    const int wr = wave & 3, wc = wave >> 2;
+    const int wr = wave & 1, wc = wave >> 1;
     const int lda = a.lda;
 
-    // this thread's 16-byte chunks of a stage: global element offset (without
-    // the K offset), LDS byte offset, and whether the source row exists
-    const unsigned char* src[kPer];
-    int dst[kPer];
-    bool ok[kPer];
+    // wave w fills plane w: its chunk i (1 KB) holds rows 16 i .. 16 i + 15,
+    // lane l the physical slot l % 4 = logical slot ^ slot_swz(row) of row
+    // 16 i + l / 4.  Rows past the padded row count (walks past the padded
+    // walk count) read the last one: their products are never stored.
+    const bool a_side = wave < 2;
+    const int half = wave & 1;   // BF16X3: hi / lo part; FP32: columns 0-15 / 16-31
+    const unsigned char* src[kChunksPerWave];
     const size_t zl = (size_t)a.z_pad * lda;
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const int u = tid + i * kThreads;
-        if (u < kAChunks) {
-            const int plane = u / (kTR * kChunkRow), rem = u - plane * kTR * kChunkRow;
-            const int row = rem / kChunkRow, part = rem - row * kChunkRow;
-            ok[i] = R0 + row < a.m_pad;
-            const size_t off = (size_t)(ok[i] ? R0 + row : 0) * lda + part * F::per16;
-            if (P == kBF16X3)
-                src[i] = (const unsigned char*)((plane ? a.Alo : a.Ahi) + off);
-            else
-                src[i] = (const unsigned char*)(a.A32 + off);
-            dst[i] = (plane * kTR + row) * F::row_bytes + part * 16;
+    for (int i = 0; i < kChunksPerWave; ++i) {
+        const int row = 16 * i + (lane >> 2);
+        const int logical = (lane & 3) ^ slot_swz(row);
+        const unsigned char* base;
+        int grow;
+        if (a_side) {
+            grow = min(R0 + row, a.m_pad - 1);
+            base = P == kBF16X3 ? (const unsigned char*)(half ? a.Alo : a.Ahi)
+                                : (const unsigned char*)a.A32;
         } else {
-            const int v = u - kAChunks;
-            const int plane = v / (kTW * kChunkRow), rem = v - plane * kTW * kChunkRow;
-            const int row = rem / kChunkRow, part = rem - row * kChunkRow;
-            ok[i] = C0 + row < a.z_pad;
-            const size_t off = (size_t)(ok[i] ? C0 + row : 0) * lda + part * F::per16;
-            if (P == kBF16X3)
-                src[i] = (const unsigned char*)((const __bf16*)a.Dop + plane * zl + off);
-            else
-                src[i] = (const unsigned char*)((const float*)a.Dop + off);
-            dst[i] = (F::planes * kTR + plane * kTW + row) * F::row_bytes + part * 16;
+            grow = min(C0 + row, a.z_pad - 1);
+            base = P == kBF16X3 ? (const unsigned char*)((const __bf16*)a.Dop + (half ? zl : 0))
+                                : (const unsigned char*)a.Dop;
         }
+        const int col = P == kBF16X3 ? logical * F::per16 : 16 * half + logical * F::per16;
+        src[i] = base + ((size_t)grow * lda + col) * esz;
     }
-    const int esz = 16 / F::per16;   // bytes per element
     const int nk = lda / kTK;
     // split screening: after the lda columns of A and the direction operand,
     // rk more columns of A P U and eps, stored with the same row stride, so
-    // each chunk's source moves by one byte offset per operand and plane
+    // each source moves by one byte offset per operand and plane
     const int nk_all = SPLIT ? nk + a.rk / kTK : nk;
     auto retarget = [&]() __attribute__((always_inline)) {
-        const size_t mz = (size_t)a.m_pad * lda;
-#pragma unroll
-        for (int i = 0; i < kPer; ++i) {
-            const int u = tid + i * kThreads;   // A chunks first (u < kAChunks), same i for every tid
-            if (u < kAChunks) {
-                const int plane = u / (kTR * kChunkRow);
-                const unsigned char* from = P == kBF16X3
-                    ? (const unsigned char*)(plane ? a.Alo : a.Ahi)
-                    : (const unsigned char*)a.A32;
-                const unsigned char* to = (const unsigned char*)a.AUop + (size_t)plane * mz * esz;
-                src[i] += to - from;
-            } else {
-                // eps and the direction operand share their layout (planes of z_pad x lda)
-                src[i] += (const unsigned char*)a.Eop - (const unsigned char*)a.Dop;
-            }
+        const unsigned char* from;
+        const unsigned char* to;
+        if (a_side) {
+            from = P == kBF16X3 ? (const unsigned char*)(half ? a.Alo : a.Ahi)
+                                : (const unsigned char*)a.A32;
+            to = (const unsigned char*)a.AUop +
+                 (P == kBF16X3 ? (size_t)half * a.m_pad * lda * esz : 0);
+        } else {
+            // eps and the direction operand share their layout (planes of z_pad x lda)
+            from = (const unsigned char*)a.Dop;
+            to = (const unsigned char*)a.Eop;
         }
-    };
-    // K-steps are fetched kDepth ahead into a ring of register buffers (K-step
-    // k in slot k % kDepth) and deposited into the LDS stage the next K-step
-    // reads from, so about kDepth K-steps of compute cover the load latency.
-    constexpr int kDepth = 1;
-    uint4 ring[kDepth][kPer];
-    // K-steps are fetched once each, in increasing order
-    auto fetch = [&](uint4* dst, int k) __attribute__((always_inline)) {
-        if (SPLIT && k == nk && nk_all > nk) retarget();
-        const bool live = k < nk_all;
-        const int kk = k < nk ? k : k - nk;
 #pragma unroll
-        for (int i = 0; i < kPer; ++i)
-            dst[i] = (live && ok[i]) ? *(const uint4*)(src[i] + (size_t)kk * kTK * esz)
-                                     : make_uint4(0, 0, 0, 0);
+        for (int i = 0; i < kChunksPerWave; ++i) src[i] += to - from;
     };
-    auto deposit = [&](const uint4* from, int stage) __attribute__((always_inline)) {
-        unsigned char* base = smem + stage * screen_stage_bytes<P>();
+    // K-step k into a stage; K-steps are issued once each, in increasing order
+    auto issue = [&](int k, unsigned char* stage) __attribute__((always_inline)) {
+        if (SPLIT && k == nk) retarget();
+        const size_t koff = (size_t)(k < nk ? k : k - nk) * kTK * esz;
+        const unsigned dst = (unsigned)(size_t)stage + wave * kPlaneBytes;
 #pragma unroll
-        for (int i = 0; i < kPer; ++i) *(uint4*)(base + dst[i]) = from[i];
+        for (int i = 0; i < kChunksPerWave; ++i) load_to_lds(src[i] + koff, dst + i * 1024);
     };
 
     f32x4 acc[4][4];
@@ -1062,24 +1080,28 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
     const bool wave_rows = R0 + wr * 64 < a.m_pad;
-    auto compute = [&](int stage) __attribute__((always_inline)) {
-        const unsigned char* base = smem + stage * screen_stage_bytes<P>();
-        if (!wave_rows) return;
+    const bool wave_live = wave_rows && C0 + wc * 64 < a.z_pad;
+    // every operand read takes slot g of 16 consecutive rows; slot_swz(16 t + c) = slot_swz(c)
+    const int slot = 16 * (g ^ slot_swz(c));
+    auto compute = [&](const unsigned char* base) __attribute__((always_inline)) {
+        if (!wave_live) return;
+        const unsigned char* A0 = base;
+        const unsigned char* A1 = base + kPlaneBytes;
+        const unsigned char* D0 = base + 2 * kPlaneBytes;
+        const unsigned char* D1 = base + 3 * kPlaneBytes;
         if (P == kBF16X3) {
-            const unsigned char* Ab = base;
-            const unsigned char* Db = base + 2 * kTR * F::row_bytes;
             bf16x8 ah[4], al[4], bh[4], bl[4];
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
                 const int row = wr * 64 + rt * 16 + c;
-                ah[rt] = *(const bf16x8*)(Ab + row * F::row_bytes + 16 * g);
-                al[rt] = *(const bf16x8*)(Ab + (kTR + row) * F::row_bytes + 16 * g);
+                ah[rt] = *(const bf16x8*)(A0 + row * 64 + slot);
+                al[rt] = *(const bf16x8*)(A1 + row * 64 + slot);
             }
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) {
                 const int w = wc * 64 + ct * 16 + c;
-                bh[ct] = *(const bf16x8*)(Db + w * F::row_bytes + 16 * g);
-                bl[ct] = *(const bf16x8*)(Db + (kTW + w) * F::row_bytes + 16 * g);
+                bh[ct] = *(const bf16x8*)(D0 + w * 64 + slot);
+                bl[ct] = *(const bf16x8*)(D1 + w * 64 + slot);
             }
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
@@ -1090,22 +1112,21 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
                     acc[rt][ct] = mma_bf16(ah[rt], bh[ct], acc[rt][ct]);
                 }
         } else {
-            const unsigned char* Ab = base;
-            const unsigned char* Db = base + kTR * F::row_bytes;
             float4 av[4][2], bv[4][2];
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
                 const int row = wr * 64 + rt * 16 + c;
-                av[rt][0] = *(const float4*)(Ab + row * F::row_bytes + 32 * g);
-                av[rt][1] = *(const float4*)(Ab + row * F::row_bytes + 32 * g + 16);
+                av[rt][0] = *(const float4*)(A0 + row * 64 + slot);
+                av[rt][1] = *(const float4*)(A1 + row * 64 + slot);
             }
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) {
                 const int w = wc * 64 + ct * 16 + c;
-                bv[ct][0] = *(const float4*)(Db + w * F::row_bytes + 32 * g);
-                bv[ct][1] = *(const float4*)(Db + w * F::row_bytes + 32 * g + 16);
+                bv[ct][0] = *(const float4*)(D0 + w * 64 + slot);
+                bv[ct][1] = *(const float4*)(D1 + w * 64 + slot);
             }
-            // MFMA e takes K index 8g + e from lane group g, for A and D alike
+            // MFMA e takes column 16 (e >> 2) + 4 g + (e & 3) from lane group g,
+            // for A and D alike
 #pragma unroll
             for (int e = 0; e < 8; ++e)
 #pragma unroll
@@ -1143,22 +1164,22 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     float sv0[2][4][4], gp0[2][4][4];
     load_half(0, sv0, gp0);
 
-#pragma unroll
-    for (int u = 0; u < kDepth; ++u) fetch(ring[u], u);
-    deposit(ring[0], 0);
-    __syncthreads();
-    fetch(ring[0], kDepth);
-    for (int k0 = 0; k0 < nk_all; k0 += kDepth) {
-#pragma unroll
-        for (int u = 0; u < kDepth; ++u) {
-            const int k = k0 + u;   // K-step computed here; slot (u + 1) % kDepth holds k + 1
-            if (k < nk_all) {
-                compute(k & 1);
-                if (k + 1 < nk_all) deposit(ring[(u + 1) % kDepth], (k + 1) & 1);
-                __syncthreads();
-                fetch(ring[(u + 1) % kDepth], k + 1 + kDepth);
-            }
-        }
+    // two stages: K-step k + 1 lands while K-step k is multiplied; K-step
+    // k + 2 is issued into the stage K-step k has left
+    auto kstep = [&](int k, unsigned char* stage) __attribute__((always_inline)) {
+        if (k + 1 < nk_all) wait_vm<kChunksPerWave>();
+        else wait_vm<0>();
+        tile_barrier();   // every wave's loads of K-step k have landed
+        compute(stage);
+        wait_lds();
+        tile_barrier();   // every wave is done reading the stage
+        if (k + 2 < nk_all) issue(k + 2, stage);
+    };
+    issue(0, stage0);
+    if (nk_all > 1) issue(1, stage1);
+    for (int k = 0; k < nk_all; k += 2) {
+        kstep(k, stage0);
+        if (k + 1 < nk_all) kstep(k + 1, stage1);
     }
     if (!wave_rows) return;
 
@@ -1245,30 +1266,30 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
 }
 
 template <int P, bool SPLIT>
-__global__ __launch_bounds__(kThreads) void tiled_screen_kernel(StepArgs a, int pending, int T)
+__global__ __launch_bounds__(kScreenThreads, 2) void tiled_screen_kernel(StepArgs a, int pending, int T)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     const int nrb = (a.m_pad + kTR - 1) / kTR, ncb = (a.z_pad + kTW - 1) / kTW;
     const int t = xcd_tile(blockIdx.x, nrb * ncb);
     if (t >= nrb * ncb) return;
-    screen_tile<P, SPLIT>(a, t / ncb, t % ncb, pending, T, smem);
+    int rb, cb;
+    tile_coords(t, nrb, ncb, rb, cb);
+    screen_tile<P, SPLIT>(a, rb, cb, pending, T);
 }
 
 // Screening tiles of many problems: entry (problem, rb, cb) per workgroup
 // (SPLIT when some problem of the batch has a learned covariance).
 template <int P, bool SPLIT>
-__global__ __launch_bounds__(kThreads) void grouped_screen_kernel(const StepArgs* __restrict__ descs,
-                                                                  const int4* __restrict__ tiles,
-                                                                  int ntiles, int s)
+__global__ __launch_bounds__(kScreenThreads, 2) void grouped_screen_kernel(const StepArgs* __restrict__ descs,
+                                                                           const int4* __restrict__ tiles,
+                                                                           int ntiles, int s)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     if ((int)blockIdx.x >= ntiles) return;
     const int4 e = tiles[blockIdx.x];
     const StepArgs a = descs[e.x];   // a private copy: no aliasing with the stores
     int pending, T;
     bool due;
     sched_at(a, s, pending, T, due);
-    screen_tile<P, SPLIT>(a, e.y, e.z, pending, T, smem);
+    screen_tile<P, SPLIT>(a, e.y, e.z, pending, T);
 }
 
 // Chords of step `step` for one 16-walk tile (do_chords), then the directions
@@ -1895,14 +1916,9 @@ struct TraceScope {
 template <int P>
 static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTrace* trace)
 {
-    const size_t lds_s = 2 * (size_t)screen_stage_bytes<P>();
     const size_t lds_r = 2 * (size_t)kRStage;
-    const void* screen_fn = a.rk > 0 ? (const void*)tiled_screen_kernel<P, true>
-                                     : (const void*)tiled_screen_kernel<P, false>;
-    hipError_t e = hipFuncSetAttribute(screen_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)tiled_recompute_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
+    hipError_t e = hipFuncSetAttribute((const void*)tiled_recompute_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
     if (e != hipSuccess) return e;
     const int ts = ((a.m_pad + kTR - 1) / kTR) * ((a.z_pad + kTW - 1) / kTW);
     const int tr = ((a.m_pad + kRR - 1) / kRR) * ((a.z_pad + kRW - 1) / kRW);
@@ -1935,10 +1951,10 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTr
         {
             TraceScope ts_(trace, stream, kTraceScreen);
             if (a.rk > 0)
-                hipLaunchKernelGGL((tiled_screen_kernel<P, true>), grid_s, dim3(kThreads), lds_s,
+                hipLaunchKernelGGL((tiled_screen_kernel<P, true>), grid_s, dim3(kScreenThreads), 0,
                                    stream, a, pending, T);
             else
-                hipLaunchKernelGGL((tiled_screen_kernel<P, false>), grid_s, dim3(kThreads), lds_s,
+                hipLaunchKernelGGL((tiled_screen_kernel<P, false>), grid_s, dim3(kScreenThreads), 0,
                                    stream, a, pending, T);
         }
         {
@@ -1972,14 +1988,9 @@ static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, in
                                    int steps, int first, const unsigned char* due,
                                    int any_split, hipStream_t stream)
 {
-    const size_t lds_s = 2 * (size_t)screen_stage_bytes<P>();
     const size_t lds_r = 2 * (size_t)kRStage;
-    const void* screen_fn = any_split ? (const void*)grouped_screen_kernel<P, true>
-                                      : (const void*)grouped_screen_kernel<P, false>;
-    hipError_t e = hipFuncSetAttribute(screen_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_s);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)grouped_recompute_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
+    hipError_t e = hipFuncSetAttribute((const void*)grouped_recompute_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
     if (e != hipSuccess) return e;
     if (first)
         hipLaunchKernelGGL(grouped_recompute_kernel, dim3(nrt), dim3(kThreads), lds_r, stream, descs,
@@ -1989,10 +2000,10 @@ static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, in
                            units, nunits, 0, 0, 1);
     for (int s = 0; s < steps; ++s) {
         if (any_split)
-            hipLaunchKernelGGL((grouped_screen_kernel<P, true>), dim3(nst), dim3(kThreads), lds_s,
+            hipLaunchKernelGGL((grouped_screen_kernel<P, true>), dim3(nst), dim3(kScreenThreads), 0,
                                stream, descs, stiles, nst, s);
         else
-            hipLaunchKernelGGL((grouped_screen_kernel<P, false>), dim3(nst), dim3(kThreads), lds_s,
+            hipLaunchKernelGGL((grouped_screen_kernel<P, false>), dim3(nst), dim3(kScreenThreads), 0,
                                stream, descs, stiles, nst, s);
         hipLaunchKernelGGL(grouped_chords_kernel<P>, dim3(nunits), dim3(kThreads), 0, stream, descs,
                            units, nunits, s, 1, (int)(s + 1 < steps));
