@@ -241,6 +241,19 @@ mhar_status_t mhar_sync(mhar_chains_t chains, void* stream, int32_t* any_flags);
 /* Synchronise `stream` and read the diagnostics counters. */
 mhar_status_t mhar_get_stats(mhar_chains_t chains, void* stream, mhar_stats_t* stats);
 
+/* Replay the tiled path's launch sequence from a HIP graph of graph_steps
+ * steps (0: off; else a multiple of the recompute period R).  mhar_step then
+ * runs ordinary launches until the slack schedule restarts (just after an
+ * exact recompute), replays the graph while graph_steps steps remain -- the
+ * step counter lives on the device and the graph's last node advances it --
+ * and runs the rest ordinarily.  The graph is captured (on a private stream)
+ * at the first replay and again after the covariance changes; trajectories
+ * are bitwise those of ordinary launches.  mhar_record, kernel timing
+ * (mhar_trace_enable) and the other paths, whose launches run many steps
+ * each, take ordinary launches.  MHAR_E_INVALID_ARG for a negative count or
+ * one that R does not divide; MHAR_E_HIP if capture fails at mhar_step. */
+mhar_status_t mhar_chains_set_graph(mhar_chains_t chains, int32_t graph_steps);
+
 mhar_status_t mhar_chains_destroy(mhar_chains_t chains);
 
 /* Kernel timing of the tiled path (paper S4.4-S4.5 split over its kernels):

@@ -69,6 +69,12 @@ struct mhar_chains {
     KernelTrace trace{nullptr, nullptr, 0, 0};
     std::vector<hipEvent_t> trace_events;
     std::vector<int> trace_kinds;
+    // graph replays of the tiled path (mhar_chains_set_graph)
+    uint64_t* gstep;                   // device step counter of the replays
+    int graph_steps = 0;               // steps per graph, 0: off
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
+    StepArgs graph_key{};              // the arguments it was captured with
 };
 
 struct mhar_batch {
@@ -222,6 +228,7 @@ size_t carve_chains(const mhar_problem* p, int z_pad, void* ws, mhar_chains* ch)
     q->gL = c.take<unsigned long long>(tiles * 3 * 2 * kChainTile);
     q->gbar = c.take<unsigned>(tiles);
     q->gerr = c.take<int>(64);
+    q->gstep = c.take<uint64_t>(1);
     return c.used;
 }
 
@@ -396,6 +403,57 @@ hipError_t refresh_lowrank(mhar_chains* c, hipStream_t stream)
     return launch_lowrank_setup(c->pc, stream);
 }
 
+// The captured arguments that stay fixed while a graph is valid: everything
+// but the step and slack schedule of the launch, which the graph fixes (step
+// counter on the device, schedule restarting after an exact recompute).
+bool graph_key_matches(const StepArgs& x, const StepArgs& y)
+{
+    return x.r == y.r && x.rk == y.rk && x.U == y.U && x.esig == y.esig && x.AUop == y.AUop &&
+           x.aun == y.aun && x.Eop == y.Eop && x.Hs == y.Hs && x.hn == y.hn && x.en == y.en &&
+           x.F == y.F && x.uF == y.uF && x.eps_g == y.eps_g && x.split == y.split && x.R == y.R &&
+           x.X == y.X && x.S == y.S;
+}
+
+void drop_graph(mhar_chains* c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+}
+
+// Capture graph_steps steps of the tiled path, starting right after an exact
+// recompute, with the step arguments relative to the device counter, and the
+// counter advance as the last node.
+hipError_t capture_graph(mhar_chains* c)
+{
+    drop_graph(c);
+    hipError_t e = hipSuccess;
+    if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    StepArgs a = make_args(c);
+    a.step0 = 0;
+    a.pending0 = 0;
+    a.T0 = 2;
+    a.since0 = 0;
+    a.steps = c->graph_steps;
+    a.recompute_first = 0;
+    a.step_dev = c->gstep;
+    e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    hipError_t el = launch_tiled(c->p->prec, a, c->cap_stream, nullptr);
+    if (el == hipSuccess) el = launch_step_counter(c->gstep, (uint64_t)c->graph_steps, 1, c->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &g);
+    if (el != hipSuccess) e = el;
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->graph_exec = nullptr;
+        return e;
+    }
+    c->graph_key = a;
+    return hipSuccess;
+}
+
 mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, double* rec_out,
                         int64_t stride, int64_t rec_chains, hipStream_t stream)
 {
@@ -420,6 +478,38 @@ mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, doub
         c->T = 2;
         c->since = 0;
         c->recomputes += 1;
+    }
+    // graph replays (tiled path, no recording or kernel timing): ordinary
+    // launches until the slack schedule restarts, then whole graphs
+    const int K = c->graph_steps;
+    if (K > 0 && c->tiled && !rec_out && c->trace.cap == 0 && !(c->lane && c->pc_rank == 0)) {
+        struct Plain {   // ordinary launches for the steps around the replays
+            mhar_chains* c;
+            int K;
+            mhar_status_t run(int64_t n, hipStream_t st)
+            {
+                c->graph_steps = 0;
+                const mhar_status_t r = run_steps(c, n, 0, nullptr, 0, 0, st);
+                c->graph_steps = K;
+                return r;
+            }
+        } plain{c, K};
+        const int64_t lead = std::min<int64_t>(steps, (p->R - c->since) % p->R);
+        mhar_status_t st = plain.run(lead, stream);
+        if (st) return st;
+        const int64_t reps = (steps - lead) / K;
+        if (reps > 0) {
+            const StepArgs now = make_args(c);
+            if (!c->graph_exec || !graph_key_matches(now, c->graph_key))
+                MHAR_HIP(capture_graph(c), "graph capture of the tiled path");
+            MHAR_HIP(launch_step_counter(c->gstep, c->step, 0, stream), "graph step counter");
+            c->last_kernel = MHAR_PATH_TILED;
+            for (int64_t r = 0; r < reps; ++r) {
+                MHAR_HIP(hipGraphLaunch(c->graph_exec, stream), "graph launch");
+                advance_schedule(c, K);
+            }
+        }
+        return plain.run(steps - lead - reps * K, stream);
     }
     while (done < steps) {
         int64_t k = std::min(chunk, steps - done);
@@ -1501,11 +1591,24 @@ mhar_status_t mhar_trace_read(mhar_chains_t c, void* stream, mhar_trace_t* out)
     return MHAR_OK;
 }
 
+mhar_status_t mhar_chains_set_graph(mhar_chains_t c, int32_t graph_steps)
+{
+    if (!c) return fail(MHAR_E_INVALID_ARG, "chains is NULL");
+    if (graph_steps < 0 || (graph_steps > 0 && graph_steps % c->p->R != 0))
+        return fail(MHAR_E_INVALID_ARG, "graph_steps must be 0 or a multiple of the recompute period R = " +
+                                            std::to_string(c->p->R));
+    if (graph_steps != c->graph_steps) drop_graph(c);
+    c->graph_steps = graph_steps;
+    return MHAR_OK;
+}
+
 mhar_status_t mhar_chains_destroy(mhar_chains_t c)
 {
     if (!c) return MHAR_OK;
     c->p->live_chains -= 1;
     trace_release(c);
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return MHAR_OK;
 }

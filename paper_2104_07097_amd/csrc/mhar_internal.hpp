@@ -112,6 +112,9 @@ struct StepArgs {
     int rec_stride;
     int rec_chains;
     int64_t rec_s_base;
+    // graph replays of the tiled path: the step counter at the start of the
+    // launch sequence, added to the (then relative) step arguments; else null
+    const uint64_t* step_dev;
 };
 
 size_t step_lds_bytes(int prec, int lda);
@@ -166,6 +169,8 @@ hipError_t launch_export_states(int n, int lda, int z, const double* X, double* 
 hipError_t launch_eq_residual(int n, int lda, int z, int m_eq, const double* Aeq,
                               const double* beq, const double* X, int* flags,
                               hipStream_t stream);
+// *ctr = value (add = 0) or *ctr += value (add = 1), one thread
+hipError_t launch_step_counter(uint64_t* ctr, uint64_t value, int add, hipStream_t stream);
 hipError_t launch_fill_i32(int* p, int64_t count, int value, hipStream_t stream);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long value,
                            hipStream_t stream);

@@ -1395,9 +1395,17 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
 // directions are bitwise those the chords kernel would make; with one
 // workgroup per walk instead of per 16 walks, small walk counts still fill
 // the device.
+// Step counter of graph replays: set before the first replay, advanced by
+// the last node of each replay.
+__global__ void step_counter_kernel(uint64_t* ctr, uint64_t value, int add)
+{
+    if (threadIdx.x == 0) *ctr = add ? *ctr + value : value;
+}
+
 template <int P>
 __global__ __launch_bounds__(kThreads) void tiled_dirs_kernel(StepArgs a, uint64_t step)
 {
+    if (a.step_dev) step += *a.step_dev;
     __shared__ double y[kMaxMeq];
     __shared__ double dn2;
     const int chain = blockIdx.x;   // < z_pad
@@ -1463,6 +1471,11 @@ __global__ __launch_bounds__(kThreads) void tiled_chords_kernel(StepArgs a, uint
                                                                 int s_rel, int T, int do_chords,
                                                                 int gen_dirs, uint64_t dir_step)
 {
+    if (a.step_dev) {
+        const uint64_t base = *a.step_dev;
+        step += base;
+        dir_step += base;
+    }
     chords_tile<P>(a, blockIdx.x, step, s_rel, T, do_chords, gen_dirs, dir_step);
 }
 
@@ -2126,6 +2139,12 @@ hipError_t launch_eq_residual(int n, int lda, int z, int m_eq, const double* Aeq
 {
     hipLaunchKernelGGL(eq_residual_kernel, dim3((z + 3) / 4), dim3(256), 0, stream, n, lda, z,
                        m_eq, Aeq, beq, X, flags);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_counter(uint64_t* ctr, uint64_t value, int add, hipStream_t stream)
+{
+    hipLaunchKernelGGL(step_counter_kernel, dim3(1), dim3(64), 0, stream, ctr, value, add);
     return hipGetLastError();
 }
 

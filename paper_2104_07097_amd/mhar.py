@@ -119,6 +119,7 @@ SIGNATURES = {
                                        _u64, ctypes.POINTER(Options), _vp, ctypes.c_size_t, _vp,
                                        ctypes.POINTER(_vp)]),
     "mhar_batch_get_chains": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "mhar_chains_set_graph": (_st, [_vp, ctypes.c_int32]),
     "mhar_batch_destroy": (_st, [_vp]),
 }
 
@@ -280,6 +281,9 @@ class Chains:
 
     def step(self, steps: int):
         _check(load().mhar_step(self.handle, int(steps), self.stream))
+
+    def set_graph(self, graph_steps: int):
+        _check(load().mhar_chains_set_graph(self.handle, int(graph_steps)))
 
     def record(self, steps: int, stride: int, chain_count: int):
         out = self.torch.empty((int(steps) // int(stride), int(chain_count), self.problem.n),
