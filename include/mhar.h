@@ -241,6 +241,29 @@ mhar_status_t mhar_sync(mhar_chains_t chains, void* stream, int32_t* any_flags);
 /* Synchronise `stream` and read the diagnostics counters. */
 mhar_status_t mhar_get_stats(mhar_chains_t chains, void* stream, mhar_stats_t* stats);
 
+/* Result of mhar_chains_autotune. */
+typedef struct {
+    int32_t path;              /* the path kept (mhar_path_t) */
+    int32_t reserved;
+    double ms_per_step[5];     /* per mhar_path_t: measured ms per step, -1 if not tried */
+} mhar_tune_t;
+
+/* Choose the kernel path of a chains handle by measurement -- the paper's
+ * study of walks per launch (S6.2) turned into a per-shape choice: every
+ * path the handle can take (general; register-resident; tiled in FP32 or
+ * BF16X3; lane for small n with isotropic directions) runs steps_per_trial
+ * steps of the handle's own walks, timed with HIP events after an exact
+ * recompute, and the fastest is kept for later mhar_step calls and for the
+ * batches the handle joins (a batch runs a resident choice on the tiled
+ * path or the general kernel).  A handle whose covariance was attached off
+ * the tiled path does not try it (the split screening's buffers are sized
+ * at attachment).  The trials are real steps: every path
+ * produces bitwise the same walks, so the walks advance by (paths tried) x
+ * steps_per_trial steps.  Synchronises `stream` once per path.
+ * MHAR_E_INVALID_ARG for steps_per_trial outside [1, 2^20]. */
+mhar_status_t mhar_chains_autotune(mhar_chains_t chains, int64_t steps_per_trial, void* stream,
+                                   mhar_tune_t* out);
+
 /* Replay the tiled path's launch sequence from a HIP graph of graph_steps
  * steps (0: off; else a multiple of the recompute period R).  mhar_step then
  * runs ordinary launches until the slack schedule restarts (just after an

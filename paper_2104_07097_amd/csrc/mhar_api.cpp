@@ -458,6 +458,9 @@ mhar_status_t run_steps(mhar_chains* c, int64_t steps, int recompute_first, doub
                         int64_t stride, int64_t rec_chains, hipStream_t stream)
 {
     const mhar_problem* p = c->p;
+    if (c->tiled && c->pc_rank && c->pc.rk == 0)
+        return fail(MHAR_E_STATE, "the covariance was attached off the tiled path: the split "
+                                  "screening has no buffers");
     MHAR_HIP(refresh_lowrank(c, stream), "low-rank screening operand");
     int64_t chunk = p->steps_per_launch > 0 ? p->steps_per_launch : auto_chunk(p);
     int64_t done = 0;
@@ -1588,6 +1591,78 @@ mhar_status_t mhar_trace_read(mhar_chains_t c, void* stream, mhar_trace_t* out)
         out->ms[k] += ms;
     }
     c->trace.used = 0;
+    return MHAR_OK;
+}
+
+mhar_status_t mhar_chains_autotune(mhar_chains_t c, int64_t steps_per_trial, void* stream_,
+                                   mhar_tune_t* out)
+{
+    if (!c || !out) return fail(MHAR_E_INVALID_ARG, "chains and out must be non-NULL");
+    if (steps_per_trial < 1 || steps_per_trial > (int64_t(1) << 20))
+        return fail(MHAR_E_INVALID_ARG, "steps_per_trial must be in [1, 2^20]");
+    hipStream_t stream = (hipStream_t)stream_;
+    const mhar_problem* p = c->p;
+    struct Cand {
+        int path, split, tiled, lane;
+    };
+    std::vector<Cand> cands;
+    if (p->lda <= kMaxN) cands.push_back({MHAR_PATH_GENERAL, 0, 0, 0});
+    const int rs = resident_split(p->prec, p->lda, p->m_pad, c->z_pad);
+    if (rs > 0 && c->pc_rank == 0) cands.push_back({MHAR_PATH_RESIDENT, rs, 0, 0});
+    // with a covariance the tiled path needs the split screening's buffers,
+    // which are sized when the covariance is attached to a tiled handle
+    if (p->prec != MHAR_FP64 && (c->pc_rank == 0 || c->pc.rk > 0))
+        cands.push_back({MHAR_PATH_TILED, 0, 1, 0});
+    if (lane_fits(p->n, p->m) && c->pc_rank == 0) cands.push_back({MHAR_PATH_LANE, 0, 0, 1});
+    std::memset(out, 0, sizeof(*out));
+    for (int i = 0; i < 5; ++i) out->ms_per_step[i] = -1.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto release = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    if (e != hipSuccess) {
+        release();
+        return hip_fail(e, "autotune events");
+    }
+    const Cand keep{0, c->split, c->tiled, c->lane};
+    int best = -1;
+    double best_ms = 0.0;
+    mhar_status_t st = MHAR_OK;
+    for (size_t i = 0; i < cands.size() && st == MHAR_OK; ++i) {
+        const Cand& k = cands[i];
+        c->split = k.split;
+        c->tiled = k.tiled;
+        c->lane = k.lane;
+        c->force_recompute = 1;
+        // the exact recompute a path switch takes stays outside the timed steps
+        st = run_steps(c, 0, 1, nullptr, 0, 0, stream);
+        if (st) break;
+        e = hipEventRecord(e0, stream);
+        if (e == hipSuccess) st = run_steps(c, steps_per_trial, 0, nullptr, 0, 0, stream);
+        if (e == hipSuccess && st == MHAR_OK) e = hipEventRecord(e1, stream);
+        if (e == hipSuccess && st == MHAR_OK) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess && st == MHAR_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) st = hip_fail(e, "autotune timing");
+        if (st) break;
+        const double per = (double)ms / (double)steps_per_trial;
+        out->ms_per_step[k.path] = per;
+        if (best < 0 || per < best_ms) {
+            best = (int)i;
+            best_ms = per;
+        }
+    }
+    release();
+    const Cand& pick = best >= 0 && st == MHAR_OK ? cands[best] : keep;
+    c->split = pick.split;
+    c->tiled = pick.tiled;
+    c->lane = pick.lane;
+    c->force_recompute = 1;
+    if (st) return st;
+    out->path = cands[best].path;
     return MHAR_OK;
 }
 

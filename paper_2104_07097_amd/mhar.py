@@ -59,6 +59,11 @@ class Trace(ctypes.Structure):
 TRACE_KINDS = ("screen", "chords", "dirs", "recompute")
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms_per_step", ctypes.c_double * 5)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_uint64), ("chain_steps", ctypes.c_uint64),
                 ("exact_rows", ctypes.c_uint64), ("recomputes", ctypes.c_uint64),
@@ -120,6 +125,7 @@ SIGNATURES = {
                                        ctypes.POINTER(_vp)]),
     "mhar_batch_get_chains": (_st, [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "mhar_chains_set_graph": (_st, [_vp, ctypes.c_int32]),
+    "mhar_chains_autotune": (_st, [_vp, _i64, _vp, ctypes.POINTER(Tune)]),
     "mhar_batch_destroy": (_st, [_vp]),
 }
 
@@ -284,6 +290,16 @@ class Chains:
 
     def set_graph(self, graph_steps: int):
         _check(load().mhar_chains_set_graph(self.handle, int(graph_steps)))
+
+    def autotune(self, steps_per_trial: int = 20) -> dict:
+        """Time every kernel path this handle can take and keep the fastest
+        (mhar_chains_autotune); returns the path kept and ms per step by path."""
+        t = Tune()
+        _check(load().mhar_chains_autotune(self.handle, int(steps_per_trial), self.stream,
+                                           ctypes.byref(t)))
+        names = {v: k for k, v in PATHS.items()}
+        return {"path": names[t.path],
+                "ms_per_step": {names[i]: t.ms_per_step[i] for i in range(5) if t.ms_per_step[i] >= 0}}
 
     def record(self, steps: int, stride: int, chain_count: int):
         out = self.torch.empty((int(steps) // int(stride), int(chain_count), self.problem.n),
