@@ -183,25 +183,101 @@ __global__ __launch_bounds__(1024) void dikin_scales_kernel(int n, int N, const 
     }
 }
 
-// C = I + U^T W (r x r), one thread per entry, sequential over the coordinates
-__global__ void dikin_cap_kernel(int n, int r, const double* __restrict__ U,
-                                 const double* __restrict__ W, double* C)
+// C = I + U^T W (r x r, r <= 64) on the FP64 matrix cores, one workgroup
+// of 8 waves: wave w sums a contiguous eighth of the coordinates into all
+// 16 output tiles (f64 16x16x4: lane (g, c) supplies a = U[i0 + g][16 ta + c]
+// and b = W[i0 + g][16 tb + c]), and the eight partial tiles are added in
+// wave order through LDS.
+__global__ __launch_bounds__(512) void dikin_cap_kernel(int n, int r, const double* __restrict__ U,
+                                                        const double* __restrict__ W, double* C)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= r * r) return;
-    const int a = e / r, b = e - a * r;
-    double v = (a == b) ? 1.0 : 0.0;
-    for (int i = 0; i < n; ++i) v = fma(U[(size_t)i * r + a], W[(size_t)i * r + b], v);
-    C[e] = v;
+    __shared__ double acc_lds[64 * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, c = lane & 15;
+    const int per = ((n + 7) / 8 + 3) / 4 * 4;   // coordinates per wave, a multiple of 4
+    const int i_begin = wave * per, i_end = min(n, i_begin + per);
+    f64x4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+    for (int i0 = i_begin; i0 < i_end; i0 += 4) {
+        const int i = i0 + g;
+        double av[4], bv[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int q = 16 * t + c;
+            const bool ok = i < i_end && q < r;
+            av[t] = ok ? U[(size_t)i * r + q] : 0.0;
+            bv[t] = ok ? W[(size_t)i * r + q] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = mma_f64(av[a], bv[b], acc[a][b]);
+    }
+    for (int turn = 0; turn < 8; ++turn) {
+        if (wave == turn) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int e = (16 * a + out_row<true>(g, q)) * 64 + 16 * b + c;
+                        acc_lds[e] = (turn == 0) ? acc[a][b][q] : acc_lds[e] + acc[a][b][q];
+                    }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < r * r; e += 512) {
+        const int a = e / r, b = e - a * r;
+        C[e] = ((a == b) ? 1.0 : 0.0) + acc_lds[a * 64 + b];
+    }
 }
 
-// Per coordinate row i (one wave, lane = rank column):
-//   HU_i = sum_j H_ij U_j,  gU_i = HU_i - W_i C^{-1},
+// HU = H U (n x r) on the FP64 matrix cores: one wave per 16 rows of H,
+// the r <= 64 columns as 4 tiles
+// of 16 (f64 16x16x4: lane (g, c) supplies a = H[row c][k0 + g] and
+// b = U[k0 + g][16 t + c]); out[q] of tile t = row out_row(g, q).
+__global__ __launch_bounds__(64) void dikin_hu_kernel(int n, int N, int r, const double* __restrict__ H,
+                                                      const double* __restrict__ U, double* HU)
+{
+    const int lane = threadIdx.x;
+    const int g = lane >> 4, c = lane & 15;
+    const int row0 = blockIdx.x * 16;   // < N
+    const double* hr = H + (size_t)(row0 + c) * N;
+    f64x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < n; k0 += 4) {
+        const int k = k0 + g;
+        const double av = k < n ? hr[k] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int q = 16 * t + c;
+            acc[t] = mma_f64(av, (k < n && q < r) ? U[(size_t)k * r + q] : 0.0, acc[t]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = row0 + out_row<true>(g, q);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = 16 * t + c;
+            if (row < n && col < r) HU[(size_t)row * r + col] = acc[t][q];
+        }
+    }
+}
+
+// Per coordinate row i (one wave, lane = rank column), with HU = H U:
+//   gU_i = HU_i - W_i C^{-1},
 //   gl_i = exp(2 l_i) (H_ii - (Sigma^{-1})_ii),
 //   (Sigma^{-1})_ii = exp(-2 l_i) - W_i C^{-1} W_i^T,
 //   rowterm_i = 1/2 (H_ii exp(2 l_i) + U_i . HU_i) - l_i  (K = sum rowterm - 1/2 log det C)
 __global__ __launch_bounds__(256) void dikin_grad_kernel(int n, int N, int r,
                                                          const double* __restrict__ H,
+                                                         const double* __restrict__ HU,
                                                          const double* __restrict__ U,
                                                          const double* __restrict__ W,
                                                          const double* __restrict__ Cinv,
@@ -214,7 +290,7 @@ __global__ __launch_bounds__(256) void dikin_grad_kernel(int n, int N, int r,
     const double* hr = H + (size_t)i * N;
     double hu = 0.0, wc = 0.0;
     if (q < r) {
-        for (int j = 0; j < n; ++j) hu = fma(hr[j], U[(size_t)j * r + q], hu);
+        hu = HU[(size_t)i * r + q];
         for (int b = 0; b < r; ++b) wc = fma(W[(size_t)i * r + b], Cinv[b * r + q], wc);
         gU[(size_t)i * r + q] = hu - wc;
     }
@@ -257,62 +333,101 @@ __global__ void dikin_copy_kernel(int64_t count, const double* __restrict__ src,
         dst[e] = src[e];
 }
 
-// factor the diagonal block kb (right-looking, in LDS); a pivot <= 0 sets
-// status bit 1 and is replaced by 1 so that the rest stays finite
+// factor the diagonal block kb (right-looking).  256 threads, thread
+// (ty, tx) holding the 16 entries (ty + 16 a, tx + 16 b) of the block in
+// registers; per column j the owners of column j publish it through LDS,
+// every thread scales what it needs by the reciprocal of the pivot's root
+// and updates its entries below the diagonal.  A pivot <= 0 sets status bit 1 and is
+// replaced by 1 so that the rest stays finite.
 __global__ __launch_bounds__(256) void chol_diag_kernel(int N, int kb, double* L, int* status)
 {
-    __shared__ double T[kNB][kNB + 1];
-    const int tid = threadIdx.x;
+    __shared__ double col[kNB];
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
     const size_t base = (size_t)kb * kNB * N + (size_t)kb * kNB;
-    for (int e = tid; e < kNB * kNB; e += 256) T[e / kNB][e % kNB] = L[base + (size_t)(e / kNB) * N + e % kNB];
-    __syncthreads();
+    double t[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) t[a][b] = L[base + (size_t)(ty + 16 * a) * N + tx + 16 * b];
     for (int j = 0; j < kNB; ++j) {
-        if (tid == 0) {
-            double piv = T[j][j];
-            if (!(piv > 0.0)) {
-                atomicOr(status, 1);
-                piv = 1.0;
+        const int bj = j >> 4;
+        if (tx == (j & 15)) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (b == bj) col[ty + 16 * a] = t[a][b];
+        }
+        __syncthreads();
+        double piv = col[j];
+        if (!(piv > 0.0)) {
+            if (tid == 0) atomicOr(status, 1);
+            piv = 1.0;
+        }
+        const double ljj = sqrt(piv), rj = 1.0 / ljj;
+        double li[4], lk[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = ty + 16 * a;
+            li[a] = i > j ? col[i] * rj : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int k = tx + 16 * b;
+            lk[b] = k > j ? col[k] * rj : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = ty + 16 * a, k = tx + 16 * b;
+                if (k == j) {
+                    if (i == j) t[a][b] = ljj;
+                    else if (i > j) t[a][b] = li[a];
+                } else if (k > j && k <= i) {
+                    t[a][b] -= li[a] * lk[b];
+                }
             }
-            T[j][j] = sqrt(piv);
-        }
-        __syncthreads();
-        const double ljj = T[j][j];
-        for (int i = j + 1 + tid; i < kNB; i += 256) T[i][j] /= ljj;
-        __syncthreads();
-        for (int e = tid; e < (kNB - j - 1) * (kNB - j - 1); e += 256) {
-            const int i = j + 1 + e / (kNB - j - 1), k = j + 1 + e % (kNB - j - 1);
-            if (k <= i) T[i][k] -= T[i][j] * T[k][j];
-        }
         __syncthreads();
     }
-    for (int e = tid; e < kNB * kNB; e += 256) {
-        const int i = e / kNB, k = e % kNB;
-        L[base + (size_t)i * N + k] = (k <= i) ? T[i][k] : 0.0;
-    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 16 * a, k = tx + 16 * b;
+            L[base + (size_t)i * N + k] = (k <= i) ? t[a][b] : 0.0;
+        }
 }
 
-// panel below the diagonal block: L_ib = A_ib L_kk^{-T}, one workgroup per
-// 64-row block ib > kb, one thread per row (forward substitution over 64 columns)
-__global__ __launch_bounds__(64) void chol_panel_kernel(int N, int kb, double* L)
+// panel below the diagonal block: L_ib = A_ib L_kk^{-T} by forward
+// substitution, one workgroup per 64-row block ib > kb, four lanes per row:
+// lane t of a quad keeps the row's columns k = t (mod 4) in registers, the
+// dot product of column c is summed over the quad by shuffles, and the lane
+// owning column c divides.
+__global__ __launch_bounds__(256) void chol_panel_kernel(int N, int kb, double* L)
 {
     __shared__ double D[kNB][kNB + 1];
-    __shared__ double R[kNB][kNB + 1];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, row = tid >> 2, t = tid & 3;
     const int ib = kb + 1 + blockIdx.x;
     const size_t dbase = (size_t)kb * kNB * N + (size_t)kb * kNB;
-    const size_t rbase = (size_t)ib * kNB * N + (size_t)kb * kNB;
-    for (int e = tid; e < kNB * kNB; e += 64) {
-        D[e / kNB][e % kNB] = L[dbase + (size_t)(e / kNB) * N + e % kNB];
-        R[e / kNB][e % kNB] = L[rbase + (size_t)(e / kNB) * N + e % kNB];
-    }
+    const size_t rbase = (size_t)ib * kNB * N + (size_t)kb * kNB + (size_t)row * N;
+    for (int e = tid; e < kNB * kNB; e += 256) D[e / kNB][e % kNB] = L[dbase + (size_t)(e / kNB) * N + e % kNB];
+    double x[kNB / 4];
+#pragma unroll
+    for (int m = 0; m < kNB / 4; ++m) x[m] = L[rbase + 4 * m + t];
     __syncthreads();
+#pragma unroll
     for (int c = 0; c < kNB; ++c) {
-        double v = R[tid][c];
-        for (int k = 0; k < c; ++k) v -= R[tid][k] * D[c][k];
-        R[tid][c] = v / D[c][c];
+        double v = 0.0;
+#pragma unroll
+        for (int m = 0; m < kNB / 4; ++m)
+            if (4 * m + t < c) v = fma(x[m], D[c][4 * m + t], v);
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        if (t == (c & 3)) x[c >> 2] = (x[c >> 2] - v) / D[c][c];
     }
-    __syncthreads();
-    for (int e = tid; e < kNB * kNB; e += 64) L[rbase + (size_t)(e / kNB) * N + e % kNB] = R[e / kNB][e % kNB];
+#pragma unroll
+    for (int m = 0; m < kNB / 4; ++m) L[rbase + 4 * m + t] = x[m];
 }
 
 // trailing update A_ij -= L_ik L_jk^T for kb < jb <= ib (lower block
@@ -357,67 +472,104 @@ __global__ __launch_bounds__(256) void chol_update_kernel(int N, int kb, double*
         }
 }
 
-// Solve H Y = G column by column (one workgroup per rank column a):
-// L z = g forward, then L^T y = z backward; z and y live in LDS.  Rows are
-// processed in 64-row blocks: the four waves sum the contributions of the
-// finished blocks (wave w takes every fourth of them), then wave 0 solves
-// the block's triangle sequentially.
+// Solve H Y = G for kRhs rank columns per workgroup: L z = g forward, then
+// L^T y = z backward; z and y live in LDS (row-major, kRhs per row).  Rows
+// are processed in 64-row blocks: the four waves sum the contributions of
+// the finished blocks (wave w takes every fourth of them; each loaded entry
+// of L serves the kRhs columns), then wave 0 solves the block's triangle
+// sequentially, multiplying by the reciprocals of the diagonal.
+constexpr int kRhs = 1;
 __global__ __launch_bounds__(256) void dikin_solve_kernel(int n, int N, int r,
                                                           const double* __restrict__ L,
                                                           const double* __restrict__ G,
                                                           double* Y)
 {
-    extern __shared__ double zs[];       // N values
-    __shared__ double part[4][kNB];
-    const int a = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    extern __shared__ double zs[];       // N x kRhs values
+    __shared__ double part[4][kNB][kRhs];
+    const int a0 = blockIdx.x * kRhs, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nblk = N / kNB;
-    for (int i = tid; i < N; i += 256) zs[i] = (i < n) ? G[(size_t)i * r + a] : 0.0;
+    for (int e = tid; e < N * kRhs; e += 256) {
+        const int i = e / kRhs, t = e - i * kRhs;
+        zs[e] = (i < n && a0 + t < r) ? G[(size_t)i * r + a0 + t] : 0.0;
+    }
     __syncthreads();
     // forward: lane = row of the block, waves split the finished blocks
     for (int kb = 0; kb < nblk; ++kb) {
         const int i = kb * kNB + lane;
-        double v = 0.0;
+        double v[kRhs] = {};
         for (int jb = wave; jb < kb; jb += 4) {
             const double* lr = L + (size_t)i * N + jb * kNB;
-            for (int j = 0; j < kNB; ++j) v = fma(lr[j], zs[jb * kNB + j], v);
+            for (int j = 0; j < kNB; ++j) {
+                const double l = lr[j];
+#pragma unroll
+                for (int t = 0; t < kRhs; ++t) v[t] = fma(l, zs[(jb * kNB + j) * kRhs + t], v[t]);
+            }
         }
-        part[wave][lane] = v;
+#pragma unroll
+        for (int t = 0; t < kRhs; ++t) part[wave][lane][t] = v[t];
         __syncthreads();
         if (wave == 0) {
-            double rhs = zs[i] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+            double rhs[kRhs];
+#pragma unroll
+            for (int t = 0; t < kRhs; ++t)
+                rhs[t] = zs[i * kRhs + t] - (part[0][lane][t] + part[1][lane][t] + part[2][lane][t] + part[3][lane][t]);
             const double* lr = L + (size_t)i * N + kb * kNB;
+            const double rii = 1.0 / lr[lane];   // reciprocal of this row's diagonal
             for (int c = 0; c < kNB; ++c) {
                 // row c of the block is final once the earlier rows are
-                double zc = __shfl(rhs, c, 64) / __shfl(lr[c], c, 64);
-                if (lane == c) rhs = zc;
-                if (lane > c) rhs -= lr[c] * zc;
+                const double lc = lr[c];
+                const double rc = __shfl(rii, c, 64);
+#pragma unroll
+                for (int t = 0; t < kRhs; ++t) {
+                    const double zc = __shfl(rhs[t], c, 64) * rc;
+                    if (lane == c) rhs[t] = zc;
+                    if (lane > c) rhs[t] -= lc * zc;
+                }
             }
-            zs[i] = rhs;
+#pragma unroll
+            for (int t = 0; t < kRhs; ++t) zs[i * kRhs + t] = rhs[t];
         }
         __syncthreads();
     }
     // backward: L^T y = z, blocks from the last; y overwrites z
     for (int kb = nblk - 1; kb >= 0; --kb) {
         const int i = kb * kNB + lane;
-        double v = 0.0;
+        double v[kRhs] = {};
         for (int jb = kb + 1 + wave; jb < nblk; jb += 4)
-            for (int j = 0; j < kNB; ++j) v = fma(L[(size_t)(jb * kNB + j) * N + i], zs[jb * kNB + j], v);
-        part[wave][lane] = v;
+            for (int j = 0; j < kNB; ++j) {
+                const double l = L[(size_t)(jb * kNB + j) * N + i];
+#pragma unroll
+                for (int t = 0; t < kRhs; ++t) v[t] = fma(l, zs[(jb * kNB + j) * kRhs + t], v[t]);
+            }
+#pragma unroll
+        for (int t = 0; t < kRhs; ++t) part[wave][lane][t] = v[t];
         __syncthreads();
         if (wave == 0) {
-            double rhs = zs[i] - (part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane]);
+            double rhs[kRhs];
+#pragma unroll
+            for (int t = 0; t < kRhs; ++t)
+                rhs[t] = zs[i * kRhs + t] - (part[0][lane][t] + part[1][lane][t] + part[2][lane][t] + part[3][lane][t]);
+            const double rii = 1.0 / L[(size_t)i * N + i];
             for (int c = kNB - 1; c >= 0; --c) {
                 // column c of the block: L[kb*64 + c][kb*64 + lane] for lane < c
                 const double lcl = L[(size_t)(kb * kNB + c) * N + kb * kNB + lane];
-                double yc = __shfl(rhs, c, 64) / __shfl(lcl, c, 64);
-                if (lane == c) rhs = yc;
-                if (lane < c) rhs -= lcl * yc;
+                const double rc = __shfl(rii, c, 64);
+#pragma unroll
+                for (int t = 0; t < kRhs; ++t) {
+                    const double yc = __shfl(rhs[t], c, 64) * rc;
+                    if (lane == c) rhs[t] = yc;
+                    if (lane < c) rhs[t] -= lcl * yc;
+                }
             }
-            zs[i] = rhs;
+#pragma unroll
+            for (int t = 0; t < kRhs; ++t) zs[i * kRhs + t] = rhs[t];
         }
         __syncthreads();
     }
-    for (int i = tid; i < n; i += 256) Y[(size_t)i * r + a] = zs[i];
+    for (int e = tid; e < n * kRhs; e += 256) {
+        const int i = e / kRhs, t = e - i * kRhs;
+        if (a0 + t < r) Y[(size_t)i * r + a0 + t] = zs[e];
+    }
 }
 
 // U <- U - eta Y, V = U / exp(l); skipped when a pivot failed (status != 0)
@@ -467,7 +619,7 @@ size_t dikin_bytes(int n, int r, int m_pad)
     b += 2 * al(N * N * 8);            // H, L
     b += al((size_t)m_pad * 8);        // row weights
     b += 4 * al(N * 8);                // v, y0, y1, dsq
-    b += 2 * al((size_t)n * r * 8);    // HU (spare), Y
+    b += 2 * al((size_t)n * r * 8);    // HU, Y
     b += al(64);                       // lam
     return b;
 }
@@ -518,12 +670,13 @@ static hipError_t dikin_hessian(const PrecondBufs& p, const double* X, hipStream
 // C, its inverse and log det, the gradient rows and K at the current (U, l)
 static hipError_t dikin_gradient(const PrecondBufs& p, hipStream_t stream)
 {
-    hipLaunchKernelGGL(dikin_cap_kernel, dim3((p.r * p.r + 255) / 256), dim3(256), 0, stream,
-                       p.n, p.r, p.U, p.W, p.C);
+    hipLaunchKernelGGL(dikin_cap_kernel, dim3(1), dim3(512), 0, stream, p.n, p.r, p.U, p.W, p.C);
+    hipLaunchKernelGGL(dikin_hu_kernel, dim3(p.N / 16), dim3(64), 0, stream, p.n, p.N, p.r, p.Hm,
+                       p.U, p.HU);
     hipError_t e = launch_precond_capacitance(p, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(dikin_grad_kernel, dim3((p.n + 3) / 4), dim3(256), 0, stream, p.n, p.N,
-                       p.r, p.Hm, p.U, p.W, p.Cinv, p.logsig, p.gU, p.gl, p.rowterm);
+                       p.r, p.Hm, p.HU, p.U, p.W, p.Cinv, p.logsig, p.gU, p.gl, p.rowterm);
     hipLaunchKernelGGL(dikin_value_kernel, dim3(1), dim3(256), 0, stream, p.n, p.rowterm,
                        p.nll + 1, p.nll);
     return hipGetLastError();
@@ -571,13 +724,13 @@ hipError_t launch_dikin_train(const PrecondBufs& p, const double* X, int k_pow, 
         hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, stream, N, kb, p.Lm, p.status);
         const int rest = nblk - kb - 1;
         if (rest > 0) {
-            hipLaunchKernelGGL(chol_panel_kernel, dim3(rest), dim3(64), 0, stream, N, kb, p.Lm);
+            hipLaunchKernelGGL(chol_panel_kernel, dim3(rest), dim3(256), 0, stream, N, kb, p.Lm);
             hipLaunchKernelGGL(chol_update_kernel, dim3(rest * (rest + 1) / 2), dim3(256), 0, stream,
                                N, kb, p.Lm);
         }
     }
-    hipLaunchKernelGGL(dikin_solve_kernel, dim3(p.r), dim3(256), (size_t)N * 8, stream, n, N, p.r,
-                       p.Lm, p.gU, p.Ysol);
+    hipLaunchKernelGGL(dikin_solve_kernel, dim3((p.r + kRhs - 1) / kRhs), dim3(256),
+                       (size_t)N * kRhs * 8, stream, n, N, p.r, p.Lm, p.gU, p.Ysol);
     hipLaunchKernelGGL(dikin_update_kernel, dim3(blocks_for((int64_t)n * p.r, 256)), dim3(256), 0,
                        stream, n, p.r, eta, p.Ysol, p.esig, p.status, p.U, p.V);
     return hipGetLastError();

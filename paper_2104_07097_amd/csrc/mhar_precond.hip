@@ -77,39 +77,64 @@ __global__ void scales_kernel(int n, int r, const double* U, const double* logsi
     }
 }
 
-// column means and (1/z) variances of the states (two passes): one block of
-// 8 waves per 64 coordinates, lane = coordinate, each wave a fixed stripe of
-// the states, partial sums combined in a fixed order
-__global__ __launch_bounds__(512) void mean_sd_kernel(int n, int z, int lda,
-                                                      const double* __restrict__ X, double* mean,
-                                                      double* Sd)
+// column means and (1/z) variances of the states, two passes, each split
+// over kSplitZ stripes of walks so that the whole device takes part: one
+// block of 8 waves per (64 coordinates, stripe), lane = coordinate, partial
+// sums in `part` (stripe-major), combined in a fixed order by the reduce
+// kernels (mean first, then the squared deviations from it).
+constexpr int kSplitZ = 32;
+__global__ __launch_bounds__(512) void moment_part_kernel(int n, int z, int lda,
+                                                          const double* __restrict__ X,
+                                                          const double* __restrict__ mean,
+                                                          double* part)
 {
-    __shared__ double part[8][64];
+    __shared__ double acc[8][64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
+    const int i = blockIdx.x * 64 + lane, y = blockIdx.y;
+    const int per = (z + kSplitZ - 1) / kSplitZ;
+    const int k0 = y * per, k1 = min(z, k0 + per);
     double s = 0.0;
-    if (i < n)
-        for (int k = wave; k < z; k += 8) s += X[(size_t)k * lda + i];
-    part[wave][lane] = s;
-    __syncthreads();
-    double mu = 0.0;
-    for (int w = 0; w < 8; ++w) mu += part[w][lane];
-    mu /= z;
-    __syncthreads();
-    double v = 0.0;
-    if (i < n)
-        for (int k = wave; k < z; k += 8) {
-            const double y = X[(size_t)k * lda + i] - mu;
-            v = fma(y, y, v);
+    if (i < n) {
+        if (mean) {
+            const double mu = mean[i];
+            for (int k = k0 + wave; k < k1; k += 8) {
+                const double d = X[(size_t)k * lda + i] - mu;
+                s = fma(d, d, s);
+            }
+        } else {
+            for (int k = k0 + wave; k < k1; k += 8) s += X[(size_t)k * lda + i];
         }
-    part[wave][lane] = v;
+    }
+    acc[wave][lane] = s;
     __syncthreads();
     if (wave == 0 && i < n) {
-        double vv = 0.0;
-        for (int w = 0; w < 8; ++w) vv += part[w][lane];
-        mean[i] = mu;
-        Sd[i] = vv / z;
+        double t = 0.0;
+        for (int w = 0; w < 8; ++w) t += acc[w][lane];
+        part[(size_t)y * n + i] = t;
     }
+}
+
+// out_i = (sum of the stripes' partial sums, in stripe order) / z
+__global__ void moment_reduce_kernel(int n, int z, const double* __restrict__ part, double* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double t = 0.0;
+    for (int y = 0; y < kSplitZ; ++y) t += part[(size_t)y * n + i];
+    out[i] = t / z;
+}
+
+static void launch_moments(const PrecondBufs& p, const double* X, hipStream_t stream)
+{
+    const dim3 grid((p.n + 63) / 64, kSplitZ);
+    hipLaunchKernelGGL(moment_part_kernel, grid, dim3(512), 0, stream, p.n, p.z, p.lda, X,
+                       (const double*)nullptr, p.part);
+    hipLaunchKernelGGL(moment_reduce_kernel, dim3((p.n + 255) / 256), dim3(256), 0, stream, p.n,
+                       p.z, p.part, p.mean);
+    hipLaunchKernelGGL(moment_part_kernel, grid, dim3(512), 0, stream, p.n, p.z, p.lda, X,
+                       (const double*)p.mean, p.part);
+    hipLaunchKernelGGL(moment_reduce_kernel, dim3((p.n + 255) / 256), dim3(256), 0, stream, p.n,
+                       p.z, p.part, p.Sd);
 }
 
 __global__ void w_kernel(int n, int r, const double* U, const double* logsig, double* W)
@@ -152,6 +177,7 @@ __global__ __launch_bounds__(512) void b_kernel(int n, int r, int z, int lda,
 // states: block (i-group of 8, chunk) has one wave per coordinate, lane = q;
 // the chunks' partial sums are added in chunk order by h_reduce_kernel.
 constexpr int kSplit = 32;
+static_assert(kSplitZ <= kSplit, "the partial-sum buffer holds kSplitZ x n values");
 __global__ __launch_bounds__(512) void h_part_kernel(int n, int r, int z, int lda,
                                                      const double* __restrict__ X,
                                                      const double* __restrict__ mean,
@@ -242,62 +268,123 @@ __global__ void gc_reduce_kernel(int n, int r, int z, const double* __restrict__
     C[e] = c;
 }
 
-// Cholesky of C (r <= 64), log det C, C^{-1}, K = I + C^{-1} G; one wave.
+// Cholesky of C (r <= 64), log det C, C^{-1} and (K non-null) K = I + C^{-1} G;
+// one workgroup of 256 threads.
+constexpr int kLd = kMaxMeq + 1;
 // Right-looking factorisation with lane i owning row i; C^{-1} column q is
 // solved by lane q (forward then backward substitution) in LDS.
-__global__ __launch_bounds__(64) void chol_kernel(int r, const double* C, const double* G,
-                                                  double* Cinv, double* K, double* logdet,
-                                                  int* status)
+__global__ __launch_bounds__(256) void chol_kernel(int r, const double* C, const double* G,
+                                                   double* Cinv, double* K, double* logdet,
+                                                   int* status)
 {
-    __shared__ double L[kMaxMeq * kMaxMeq];
+    __shared__ double L[kMaxMeq * kLd];   // rows padded: lanes walk a column
     __shared__ double Y[kMaxMeq * kMaxMeq];
-    const int lane = threadIdx.x;
-    for (int e = lane; e < r * r; e += 64) L[e] = C[e];
-    __syncthreads();
+    __shared__ double col[kMaxMeq];
+    // right-looking factorisation, thread (ty, tx) holding entries
+    // (ty + 16 a, tx + 16 b) in registers; column j published through LDS
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15, lane = tid;
+    double t[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 16 * a, k = tx + 16 * b;
+            t[a][b] = (i < r && k < r) ? C[i * r + k] : 0.0;
+        }
     int bad = 0;
     double ld = 0.0;
     for (int j = 0; j < r; ++j) {
-        const double piv = L[j * r + j];
+        if (tx == (j & 15)) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    if (b == (j >> 4)) col[ty + 16 * a] = t[a][b];
+        }
+        __syncthreads();
+        const double piv = col[j];
         if (!(piv > 0.0)) {
             bad = 1;
             break;
         }
-        const double ljj = sqrt(piv);
+        const double ljj = sqrt(piv), rj = 1.0 / ljj;
         ld += 2.0 * log(ljj);
-        __syncthreads();
-        if (lane == j) L[j * r + j] = ljj;
-        if (lane > j && lane < r) L[lane * r + j] /= ljj;
-        __syncthreads();
-        if (lane > j && lane < r) {
-            const double lij = L[lane * r + j];
-            for (int k = j + 1; k <= lane; ++k) L[lane * r + k] -= lij * L[k * r + j];
+        double li[4], lk[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int i = ty + 16 * a;
+            li[a] = (i > j && i < r) ? col[i] * rj : 0.0;
         }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int k = tx + 16 * b;
+            lk[b] = (k > j && k < r) ? col[k] * rj : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = ty + 16 * a, k = tx + 16 * b;
+                if (k == j) {
+                    if (i == j) t[a][b] = ljj;
+                    else if (i > j) t[a][b] = li[a];
+                } else if (k > j && k <= i) {
+                    t[a][b] -= li[a] * lk[b];
+                }
+            }
         __syncthreads();
     }
-    if (lane == 0) {
+    if (tid == 0) {
         *logdet = ld;
         if (bad) atomicOr(status, 4);
     }
     if (bad) return;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = ty + 16 * a, k = tx + 16 * b;
+            if (i < r && k <= i) L[i * kLd + k] = t[a][b];
+        }
+    __syncthreads();
     if (lane < r) {
+        // lane q solves column q of C^{-1}, the column held in registers
+        // (loops unrolled over the maximal rank, guarded by r)
         const int q = lane;
-        for (int i = 0; i < r; ++i) {
-            double v = (i == q) ? 1.0 : 0.0;
-            for (int k = 0; k < i; ++k) v -= L[i * r + k] * Y[k * r + q];
-            Y[i * r + q] = v / L[i * r + i];
+        double y[kMaxMeq];
+#pragma unroll
+        for (int i = 0; i < kMaxMeq; ++i) {
+            if (i < r) {
+                double v = (i == q) ? 1.0 : 0.0;
+#pragma unroll
+                for (int k = 0; k < i; ++k) v -= L[i * kLd + k] * y[k];
+                y[i] = v / L[i * kLd + i];
+            }
         }
-        for (int i = r - 1; i >= 0; --i) {
-            double v = Y[i * r + q];
-            for (int k = i + 1; k < r; ++k) v -= L[k * r + i] * Y[k * r + q];
-            Y[i * r + q] = v / L[i * r + i];
+#pragma unroll
+        for (int i = kMaxMeq - 1; i >= 0; --i) {
+            if (i < r) {
+                double v = y[i];
+#pragma unroll
+                for (int k = i + 1; k < kMaxMeq; ++k)
+                    if (k < r) v -= L[k * kLd + i] * y[k];
+                y[i] = v / L[i * kLd + i];
+            }
         }
+#pragma unroll
+        for (int i = 0; i < kMaxMeq; ++i)
+            if (i < r) Y[i * r + q] = y[i];
     }
     __syncthreads();
-    for (int e = lane; e < r * r; e += 64) Cinv[e] = Y[e];
-    for (int e = lane; e < r * r; e += 64) {
+    for (int e = tid; e < r * r; e += 256) Cinv[e] = Y[e];
+    if (!K) return;   // the Dikin fit does not use K
+    // G into the rows of L (no longer needed), then K = I + C^{-1} G
+    for (int e = tid; e < r * r; e += 256) L[(e / r) * kLd + e % r] = G[e];
+    __syncthreads();
+    for (int e = tid; e < r * r; e += 256) {
         const int p = e / r, q = e - p * r;
         double v = (p == q) ? 1.0 : 0.0;
-        for (int k = 0; k < r; ++k) v = fma(Y[p * r + k], G[k * r + q], v);
+        for (int k = 0; k < r; ++k) v = fma(Y[p * r + k], L[k * kLd + q], v);
         K[e] = v;
     }
 }
@@ -446,34 +533,65 @@ __global__ void lowrank_pu_kernel(int n, int lda, int r, int m_eq, const double*
     }
 }
 
-// Row i of A P U (FP64, lane = rank column, sequential over the coordinates),
-// written as the screening operand (the first rk columns of a row of length
-// lda, as A's operand, zero padded) with its norm rounded up; one wave per row
-__global__ __launch_bounds__(256) void lowrank_au_kernel(int n, int lda, int r, int rk, int m_pad,
-                                                         int bf16, const double* __restrict__ A64,
-                                                         const double* __restrict__ PU,
-                                                         void* AUop, float* aun)
+// Rows of A P U on the FP64 matrix cores, written as the screening operand
+// (the first rk columns of a row of length lda, as A's operand, zero padded)
+// with each row's norm rounded up.  One wave per 16 rows, the r <= 64
+// columns as 4 tiles of 16; f64 16x16x4: lane (g, c) supplies a = A[row c][k0 + g] and
+// b = (P U)[k0 + g][16 t + c]; out[q] of tile t = row out_row(g, q), column
+// 16 t + c.
+__global__ __launch_bounds__(64) void lowrank_au_kernel(int n, int lda, int r, int rk, int m_pad,
+                                                        int bf16, const double* __restrict__ A64,
+                                                        const double* __restrict__ PU,
+                                                        void* AUop, float* aun)
 {
-    const int q = threadIdx.x & 63;
-    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (i >= m_pad) return;
-    const double* ar = A64 + (size_t)i * lda;
-    double v = 0.0;
-    if (q < r)
-        for (int j = 0; j < n; ++j) v = fma(ar[j], PU[(size_t)j * r + q], v);
-    const double nrm = sqrt(wave_sum(v * v));
-    if (q < rk) {
-        const size_t o = (size_t)i * lda + q;
-        if (bf16) {
-            __bf16 hi, lo;
-            split_bf16((float)v, hi, lo);
-            ((__bf16*)AUop)[o] = hi;
-            ((__bf16*)AUop)[(size_t)m_pad * lda + o] = lo;
-        } else {
-            ((float*)AUop)[o] = (float)v;
+    const int lane = threadIdx.x;
+    const int g = lane >> 4, c = lane & 15;
+    const int row0 = blockIdx.x * 16;   // m_pad is a multiple of 16
+    const double* ar = A64 + (size_t)(row0 + c) * lda;
+    f64x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f64x4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < n; k0 += 4) {
+        const int k = k0 + g;
+        const double av = k < n ? ar[k] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int q = 16 * t + c;
+            const double bv = (k < n && q < r) ? PU[(size_t)k * r + q] : 0.0;
+            acc[t] = mma_f64(av, bv, acc[t]);
         }
     }
-    if (q == 0) aun[i] = (float)nrm * (1.0f + 0x1.0p-20f);
+    // row norms: the 16 lanes of a lane group hold the 16 columns of a tile
+    double ss[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double v = 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v = fma(acc[t][q], acc[t][q], v);
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 64);
+        ss[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = row0 + out_row<true>(g, q);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int col = 16 * t + c;
+            if (col >= rk) continue;
+            const float v = (float)acc[t][q];   // columns r .. rk - 1 are zero
+            const size_t o = (size_t)row * lda + col;
+            if (bf16) {
+                __bf16 hi, lo;
+                split_bf16(v, hi, lo);
+                ((__bf16*)AUop)[o] = hi;
+                ((__bf16*)AUop)[(size_t)m_pad * lda + o] = lo;
+            } else {
+                ((float*)AUop)[o] = v;
+            }
+        }
+        if (c == 0) aun[row] = (float)sqrt(ss[q]) * (1.0f + 0x1.0p-20f);
+    }
 }
 
 // ||U||_F (one workgroup, fixed-shape tree)
@@ -545,7 +663,7 @@ hipError_t launch_lowrank_setup(const PrecondBufs& p, hipStream_t stream)
                            stream, p.n, p.lda, p.r, p.m_eq, p.Aeq, p.U, p.AeqU);
     hipLaunchKernelGGL(lowrank_pu_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0,
                        stream, p.n, p.lda, p.r, p.m_eq, p.WT, p.AeqU, p.U, p.PU);
-    hipLaunchKernelGGL(lowrank_au_kernel, dim3((p.m_pad + 3) / 4), dim3(256), 0, stream, p.n, p.lda,
+    hipLaunchKernelGGL(lowrank_au_kernel, dim3(p.m_pad / 16), dim3(64), 0, stream, p.n, p.lda,
                        p.r, p.rk, p.m_pad, p.prec == kBF16X3 ? 1 : 0, p.A64, p.PU, p.AUop, p.aun);
     hipLaunchKernelGGL(lowrank_frob_kernel, dim3(1), dim3(256), 0, stream, (int64_t)p.n * p.r, p.U,
                        p.uF);
@@ -566,7 +684,7 @@ size_t precond_bytes(int n, int r, int z, int lda, int objective, int m_pad)
     b += 4 * al(rr * 8);              // G, C, Cinv, K
     b += al(64);                      // nll, logdet
     b += al(64);                      // status
-    b += al((size_t)kSplit * (nr > rr ? nr : rr) * 8);   // split-K partial sums
+    b += al((size_t)kSplit * (nr > rr ? nr : rr) * 8);   // split-K and per-stripe partial sums
     if (objective == 1) b += dikin_bytes(n, r, m_pad);
     return b;
 }
@@ -626,8 +744,7 @@ hipError_t launch_precond_set_scales(const PrecondBufs& p, hipStream_t stream)
 hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_t stream)
 {
     double* rowterm = p.rowterm;
-    hipLaunchKernelGGL(mean_sd_kernel, dim3((p.n + 63) / 64), dim3(512), 0, stream, p.n, p.z,
-                       p.lda, X, p.mean, p.Sd);
+    launch_moments(p, X, stream);
     hipLaunchKernelGGL(w_kernel, dim3(blocks_for((int64_t)p.n * p.r, 256)), dim3(256), 0, stream,
                        p.n, p.r, p.U, p.logsig, p.W);
     hipLaunchKernelGGL(b_kernel, dim3((p.z + 7) / 8), dim3(512), 0, stream, p.n, p.r, p.z, p.lda,
@@ -639,7 +756,7 @@ hipError_t launch_precond_grad(const PrecondBufs& p, const double* X, hipStream_
     hipLaunchKernelGGL(g_part_kernel, dim3(kSplit), dim3(512), 0, stream, p.r, p.z, p.B, p.part);
     hipLaunchKernelGGL(gc_reduce_kernel, dim3(p.r), dim3(64), 0, stream, p.n, p.r, p.z, p.part,
                        p.U, p.W, p.GB, p.C);
-    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, stream, p.r, p.C, p.GB, p.Cinv, p.K,
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, stream, p.r, p.C, p.GB, p.Cinv, p.K,
                        p.nll + 1, p.status);
     hipLaunchKernelGGL(grad_kernel, dim3(p.n), dim3(64), 0, stream, p.n, p.r, p.W, p.H, p.K, p.Cinv,
                        p.GB, p.logsig, p.Sd, p.status, p.gU, p.gl, rowterm);
@@ -657,8 +774,7 @@ hipError_t launch_precond_esig(const PrecondBufs& p, hipStream_t stream)
 
 hipError_t launch_precond_mean(const PrecondBufs& p, const double* X, hipStream_t stream)
 {
-    hipLaunchKernelGGL(mean_sd_kernel, dim3((p.n + 63) / 64), dim3(512), 0, stream, p.n, p.z,
-                       p.lda, X, p.mean, p.Sd);
+    launch_moments(p, X, stream);
     return hipGetLastError();
 }
 
@@ -673,8 +789,8 @@ hipError_t launch_precond_w(const PrecondBufs& p, hipStream_t stream)
 // formed as a by-product and not used)
 hipError_t launch_precond_capacitance(const PrecondBufs& p, hipStream_t stream)
 {
-    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(64), 0, stream, p.r, p.C, p.C, p.Cinv, p.K,
-                       p.nll + 1, p.status);
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(256), 0, stream, p.r, p.C, p.C, p.Cinv,
+                       (double*)nullptr, p.nll + 1, p.status);
     return hipGetLastError();
 }
 
