@@ -557,15 +557,20 @@ def bench_table5(args):
             if prec == "fp64" and n > 1152:
                 continue
             prob, ch = _make(p, prec)
-            ch.step(20)
+            # steady state: the walks leave the start point's neighbourhood
+            # first (exact candidate rows grow as walks reach the faces), the
+            # path autotuner then keeps the fastest kernel for this shape
+            ch.step(args.table5_burnin)
+            tuned = ch.autotune(20)["path"]
             probe = _timed_steps(ch, 20)
-            steps = int(min(20000, max(20, budget / max(probe / 20, 1e-7))))
+            steps = int(min(30000, max(args.table5_min_steps, budget / max(probe / 20, 1e-7))))
             sec = _timed_steps(ch, steps)
             st = ch.stats()
             flags = ch.sync()
             cs = z * steps / sec
             row[prec] = {"chain_steps_per_sec": cs, "ms_per_step": sec * 1e3 / steps, "steps": steps,
-                         "path": KERNEL_PATHS.get(st["kernel"], "?"), "flags": flags}
+                         "burnin": args.table5_burnin, "path": KERNEL_PATHS.get(st["kernel"], "?"),
+                         "autotuned_path": tuned, "flags": flags}
             if best is None or cs > row[best]["chain_steps_per_sec"]:
                 best = prec
             ch.close()
@@ -679,8 +684,12 @@ def main():
     ap.add_argument("--no-secondary", action="store_true",
                     help="rotbox: skip the short random-polytope line")
     ap.add_argument("--fr-sims", type=int, default=3, help="fr: simulations per (figure, n)")
-    ap.add_argument("--table5-seconds", type=float, default=0.25,
+    ap.add_argument("--table5-seconds", type=float, default=0.5,
                     help="table5: timed seconds per (row, precision)")
+    ap.add_argument("--table5-burnin", type=int, default=1000,
+                    help="table5: steps before the timed window (walks away from the start)")
+    ap.add_argument("--table5-min-steps", type=int, default=2000,
+                    help="table5: fewest timed steps per (row, precision)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
