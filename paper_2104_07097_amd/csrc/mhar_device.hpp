@@ -152,11 +152,14 @@ __device__ __forceinline__ void ratio_bounds(float s, float g, float dl, float e
     float s_lo = fmaxf(s - dl, 0.0f);
     float s_hi = s + dl;
     float g_hi = g + e, g_lo = g - e;    // g in [g_lo, g_hi]
-    lo_p = (g_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(g_hi) * kLowShrink : kInf;
-    hi_p = (g_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(g_lo) * kHighGrow : kInf;
-    float n_hi = -g_lo, n_lo = -g_hi;    // -g in [n_lo, n_hi]
-    lo_m = (n_hi > 0.0f) ? s_lo * __builtin_amdgcn_rcpf(n_hi) * kLowShrink : kInf;
-    hi_m = (n_lo > 0.0f) ? s_hi * __builtin_amdgcn_rcpf(n_lo) * kHighGrow : kInf;
+    // two reciprocals serve both signs: 1/(-x) = -(1/x) (the approximation
+    // is odd), within the error the shrink and grow factors cover
+    const float r_hi = __builtin_amdgcn_rcpf(g_hi), r_lo = __builtin_amdgcn_rcpf(g_lo);
+    lo_p = (g_hi > 0.0f) ? s_lo * r_hi * kLowShrink : kInf;
+    hi_p = (g_lo > 0.0f) ? s_hi * r_lo * kHighGrow : kInf;
+    // -g in [-g_hi, -g_lo]
+    lo_m = (g_lo < 0.0f) ? s_lo * -r_lo * kLowShrink : kInf;
+    hi_m = (g_hi < 0.0f) ? s_hi * -r_hi * kHighGrow : kInf;
 }
 
 }  // namespace mhar

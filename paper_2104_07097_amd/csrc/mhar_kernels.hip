@@ -1161,6 +1161,46 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             }
         }
     };
+    // the epilogue's per-row and per-walk terms, once per tile into LDS
+    // (read by every wave and lane that needs them): row norms, |b| and the
+    // split operand's row norms; per walk the product's error coefficients
+    // (ed: |a| part, ed2: |a P U| part), the slack drifts (Ek, Fk) and theta
+    __shared__ float row_na[kTR], row_b[kTR], row_nau[kTR];
+    __shared__ float walk_ed[kTW], walk_ed2[kTW], walk_E[kTW], walk_F[kTW], walk_th[kTW];
+    {
+        const int i = tid & (kTR - 1);
+        if (tid < kTR) {
+            const int row = R0 + i;
+            const bool ok = row < a.m_pad;
+            row_na[i] = ok ? a.rownorm[row] : 0.0f;
+            row_b[i] = ok ? a.absb[row] : 0.0f;
+            row_nau[i] = (SPLIT && a.rk > 0 && ok) ? a.aun[row] : 0.0f;
+        } else {
+            const int chain = C0 + i;
+            const bool ok = chain < a.z_pad, active = chain < a.z;
+            float ed = 0.0f, ed2 = 0.0f, Fk = 0.0f, Ek = 0.0f, th = 0.0f;
+            if (ok) {
+                if (SPLIT && a.rk > 0) {
+                    // |g_hat - g| <= eps_g (|a| |h| + |a P U| |eps|) + |a| dx
+                    const double hn = a.hn[chain], en = a.en[chain];
+                    const double dx = 0x1.0p-36 * (hn + a.dn[chain] + *a.uF * en);
+                    ed = active ? (float)(hn * (double)a.eps_g + dx) * kHighGrow + 1e-30f : 0.0f;
+                    ed2 = active ? (float)(en * (double)a.eps_g) * kHighGrow : 0.0f;
+                    Fk = (float)a.F[chain] * kHighGrow;
+                } else {
+                    ed = active ? (float)(a.dn[chain] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
+                }
+                Ek = (float)a.E[chain] * kHighGrow;
+                th = (float)a.theta[chain];
+            }
+            walk_ed[i] = ed;
+            walk_ed2[i] = ed2;
+            walk_F[i] = Fk;
+            walk_E[i] = Ek;
+            walk_th[i] = th;
+        }
+        wait_lds();   // the main loop's barriers publish them
+    }
     float sv0[2][4][4], gp0[2][4][4];
     load_half(0, sv0, gp0);
 
@@ -1200,22 +1240,11 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             const int ct = 2 * half + h;
             const int cbase = C0 + wc * 64 + ct * 16;
             if (cbase >= a.z_pad) break;
-            const int tile = cbase / kChainTile, chain = cbase + c;
-            const bool active = chain < a.z;
-            float ed, ed2 = 0.0f, Fk = 0.0f;
+            const int tile = cbase / kChainTile;
+            const int lw = wc * 64 + ct * 16 + c;   // walk within the tile
             const bool split = SPLIT && a.rk > 0;
-            if (split) {
-                // |g_hat - g| <= eps_g (|a| |h| + |a P U| |eps|) + |a| dx
-                const double hn = a.hn[chain], en = a.en[chain];
-                const double dx = 0x1.0p-36 * (hn + a.dn[chain] + *a.uF * en);
-                ed = active ? (float)(hn * (double)a.eps_g + dx) * kHighGrow + 1e-30f : 0.0f;
-                ed2 = active ? (float)(en * (double)a.eps_g) * kHighGrow : 0.0f;
-                Fk = (float)a.F[chain] * kHighGrow;
-            } else {
-                ed = active ? (float)(a.dn[chain] * (double)a.eps_g) * kHighGrow + 1e-30f : 0.0f;
-            }
-            const float Ek = (float)a.E[chain] * kHighGrow;
-            const float th = (float)a.theta[chain];
+            const float ed = walk_ed[lw], ed2 = walk_ed2[lw], Fk = walk_F[lw];
+            const float Ek = walk_E[lw], th = walk_th[lw];
             float up = kInf, um = kInf, lp = kInf, lm = kInf;
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
@@ -1223,7 +1252,7 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
-                    const int row = 16 * q + out_row<false>(g, r);
+                    const int lr = wr * 64 + rt * 16 + out_row<false>(g, r);   // row within the tile
                     const float gv = acc[rt][ct][r];
                     float s_ = sv[h][rt][r];
                     if (pending) {
@@ -1231,11 +1260,11 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
                         Sw[idx] = s_;
                     }
                     Gw[idx] = gv;
-                    const float na = a.rownorm[row];
-                    float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
+                    const float na = row_na[lr];
+                    float dl = fmaf(na, Ek, fmaf(bscale, row_b[lr], 1e-30f));
                     float e = na * ed;
                     if (split) {
-                        const float nau = a.aun[row];
+                        const float nau = row_nau[lr];
                         dl = fmaf(nau, Fk, dl);
                         e = fmaf(nau, ed2, e);
                     }
