@@ -34,11 +34,11 @@ constexpr int kNotInterior = 16;  // internal: start point not strictly inside
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-// Slack / screening-product buffers are stored per chain tile in the order
-// the matrix cores produce them: for tile t, 16-row block q, output slot r
-// and lane l (group g = l/16, walk c = l%16), index ((t*Q + q)*4 + r)*64 + l,
-// Q = m_pad / 16.  The row of that entry is 16 q + out_row(g, r), which
-// depends on the product precision (FP64 orders the slots differently).
+// Slack / screening-product buffers: for 16-walk tile t, 64-row group p and
+// walk c of the tile, the group's 64 rows are consecutive:
+// index ((t*(m_pad/64) + p)*16 + c)*64 + (row mod 64).  A walk's rows of one
+// group are one 256-byte run (what the candidate scan reads), and an MFMA
+// output lane's four rows (FP32 and BF16 products) are one 16-byte run.
 
 struct StepArgs {
     // problem

@@ -27,6 +27,7 @@ namespace mhar {
 namespace {
 
 constexpr int kCandCap = 512;   // candidate (row, walk) pairs listed per tile and step
+constexpr int kPairCap = 512;   // flagged (walk, row group) pairs listed per tile and step
 
 struct ChainLds {
     double theta[kChainTile];
@@ -47,6 +48,12 @@ struct ChainLds {
     int cfl[kChainTile];
     int ncand;
     int2 cand[kCandCap];
+    // candidate scan: the flagged (walk, 64-row group) pairs, walk << 16 | group,
+    // and each walk's chord-end bounds and screening error terms
+    int npairs;
+    int pairs[kPairCap];
+    float w_up[kChainTile], w_um[kChainTile], w_ed[kChainTile], w_ed2[kChainTile];
+    float w_F[kChainTile], w_E[kChainTile];
 };
 
 // s_i = b_i - a_i x and g_i = a_i d in FP64 in the order of a sequential sum
@@ -92,11 +99,26 @@ __device__ __forceinline__ void chord_row(ChainLds* cs, int cl, double s, double
         atomicMin(&cs->nlmin_bits[cl], (unsigned long long)__double_as_longlong(-(s / gg)));
 }
 
+// Wait until at most N vector-memory operations of this wave are outstanding
+// (gfx9 s_waitcnt encoding; expcnt and lgkmcnt left at their maxima).
+template <int N>
+__device__ __forceinline__ void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+// Wait for this wave's LDS reads.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
 // Exact evaluation of listed candidates through LDS: batches of `nb_max`
 // candidates, one per thread; for each chunk of C coordinates the workgroup
 // stages the candidates' rows of A and the x and d rows of the 16 walks with
 // coalesced 16-byte loads, then every thread continues its sequential sums
-// from LDS.  Same arithmetic, in the same order, as exact_row.
+// from LDS.  Same arithmetic, in the same order, as exact_row.  A chunk is at
+// most kStagePer 16-byte pieces per thread; they are loaded into registers
+// all at once, and the next chunk's loads are issued before the current
+// chunk's sums, so one load latency per chunk is exposed, not one per piece.
+constexpr int kStagePer = 8;
 __device__ void exact_rows_staged(const StepArgs& a, ChainLds* cs, int c0, int nc, double* stage,
                                   int nb_max, int C)
 {
@@ -112,23 +134,55 @@ __device__ void exact_rows_staged(const StepArgs& a, ChainLds* cs, int c0, int n
             rc = cs->cand[b0 + tid];
             s = a.b64[rc.x];
         }
-        for (int j0 = 0; j0 < n; j0 += C) {
-            const int cw = min(C, lda - j0);      // staged width: whole padded row, even
-            const int halves = cw >> 1;
-            __syncthreads();                      // the previous chunk is consumed
-            for (int e = tid; e < rows * halves; e += kThreads) {
-                const int r = e / halves, h = e - r * halves;
-                const double* src;
-                if (r < nb) {
-                    src = a.A64 + (size_t)cs->cand[b0 + r].x * lda;
-                } else {
-                    const int w = r - nb, cl = w & (kChainTile - 1);
-                    const int chain = min(c0 + cl, a.z_pad - 1);
-                    src = (w < kChainTile ? a.X : a.D) + (size_t)chain * lda;
-                }
-                *(double2*)(stage + r * ld + 2 * h) = *(const double2*)(src + j0 + 2 * h);
+        // b has landed before the chunk loads are issued (else the first sum
+        // would wait for all of them)
+        wait_vm<0>();
+        // the pieces in flight as plain scalars (an array of vector structs
+        // would be placed in LDS by the compiler)
+        double vx[kStagePer], vy[kStagePer];
+        int off[kStagePer];
+        // pass j0 stores the chunk at column j0 (loaded by the previous pass)
+        // into the stage, issues the loads of the next chunk, then continues
+        // the sums over the staged chunk; the first pass only loads
+        for (int j0 = -C; j0 < n; j0 += C) {
+            if (j0 >= 0) {
+                __syncthreads();                  // the previous chunk is consumed
+#pragma unroll
+                for (int u = 0; u < kStagePer; ++u)
+                    if (off[u] >= 0) *(double2*)(stage + off[u]) = make_double2(vx[u], vy[u]);
+                __syncthreads();
             }
-            __syncthreads();
+            const int jn = j0 + C;
+            if (jn < n) {
+                // staged width: the whole padded row, even; off[u] is the
+                // piece's LDS offset, -1 if the thread has no piece u
+                const int halves = min(C, lda - jn) >> 1;
+                // nothing is in flight here (the stores above waited for the
+                // previous chunk); saying so keeps the compiler from waiting
+                // between the pieces below
+                wait_vm<0>();
+#pragma unroll
+                for (int u = 0; u < kStagePer; ++u) {
+                    const int e = u * kThreads + tid;
+                    off[u] = -1;
+                    if (e < rows * halves) {
+                        const int r = e / halves, h = e - r * halves;
+                        const double* src;
+                        if (r < nb) {
+                            src = a.A64 + (size_t)cs->cand[b0 + r].x * lda;
+                        } else {
+                            const int w = r - nb, cl = w & (kChainTile - 1);
+                            const int chain = min(c0 + cl, a.z_pad - 1);
+                            src = (w < kChainTile ? a.X : a.D) + (size_t)chain * lda;
+                        }
+                        const double2 t = *(const double2*)(src + jn + 2 * h);
+                        vx[u] = t.x;
+                        vy[u] = t.y;
+                        off[u] = r * ld + 2 * h;
+                    }
+                }
+            }
+            if (j0 < 0) continue;
             if (tid < nb) {
                 const double* av = stage + tid * ld;
                 const double* xv = stage + (nb + rc.y) * ld;
@@ -182,14 +236,11 @@ template <> struct Op<kBF16X3> {
     static constexpr bool f64 = false;
 };
 
-// index of (row, walk c) in a tile-fragment buffer for a product precision
+// index of (row, walk c of tile) in a slack / product buffer (Q = m_pad / 16)
 template <bool F64>
 __device__ __forceinline__ size_t frag_index(int tile, int Q, int row, int c)
 {
-    int q = row >> 4, w = row & 15;
-    int g = F64 ? (w & 3) : (w >> 2);
-    int r = F64 ? (w >> 2) : (w & 3);
-    return (((size_t)tile * Q + q) * 4 + r) * 64 + g * 16 + c;
+    return (((size_t)tile * (Q >> 2) + (row >> 6)) * kChainTile + c) * 64 + (row & 63);
 }
 
 // ---------------------------------------------------------------------------
@@ -515,8 +566,8 @@ __device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int 
             const int q = (row0 >> 4) + rb;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
                 const int row = 16 * q + out_row<F64>(g, r);
+                const size_t idx = frag_index<F64>(tile, Q, row, c);
                 st_t gv = F64 ? (st_t)acc64[rb][r] : (st_t)acc32[rb][r];
                 st_t sv = S[idx];
                 if (pending) {
@@ -566,7 +617,9 @@ __device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int 
 // ---------------------------------------------------------------------------
 // `stage` (stage_bytes of LDS free during this phase, may be null) carries the
 // candidates' rows through LDS when it holds at least 16 coordinates of them.
-template <int P>
+// B: flagged groups a wave tests at once (their loads in flight together);
+// the register-heavy general kernel takes one at a time.
+template <int P, int B>
 __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, uint64_t step,
                              int64_t s_rel, int T, double* stage, size_t stage_bytes)
 {
@@ -591,73 +644,128 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
     __syncthreads();
 
     // 1. candidate rows of every walk: rows whose lower bound does not exceed
-    //    the certified chord-end bound U.  They are listed in LDS; past the
-    //    list's capacity they are evaluated on the spot.
+    //    the certified chord-end bound U.  (a) Each walk's 64-row groups whose
+    //    least lower bound does not exceed U are listed as (walk, group)
+    //    pairs; (b) all waves take the pairs, three at a time with their
+    //    loads in flight together, and test the groups' rows.  Candidates are
+    //    listed in LDS; past the lists' capacities they are evaluated on the
+    //    spot.
+    if (tid == 0) cs->npairs = 0;
+    __syncthreads();
+    // one group's rows for walk cl: the test and the listing of candidates
+    auto test_rows = [&](int cl, int qq, float s32, float g32, float na, float nau, float ab,
+                         unsigned long long& nex) __attribute__((always_inline)) {
+        const int row = qq * kRowGroup + lane;
+        float dl = fmaf(nau, cs->w_F[cl], fmaf(na, cs->w_E[cl], fmaf(bscale, ab, 1e-30f)));
+        float e = fmaf(nau, cs->w_ed2[cl], na * cs->w_ed[cl]);
+        if (F64) {
+            dl = fmaf(fabsf(s32), 0x1.0p-23f, dl);
+            e = fmaf(fabsf(g32), 0x1.0p-23f, e);
+        }
+        float lo_p, hi_p, lo_m, hi_m;
+        ratio_bounds(s32, g32, dl, e, lo_p, hi_p, lo_m, hi_m);
+        const bool cand = (row < a.m) && ((lo_p <= cs->w_up[cl]) || (lo_m <= cs->w_um[cl]));
+        nex += __popcll(__ballot(cand));
+        if (cand) {
+            const int slot = atomicAdd(&cs->ncand, 1);
+            if (slot < kCandCap) {
+                cs->cand[slot] = make_int2(row, cl);
+            } else {
+                const int chain = c0 + cl;
+                double sx, gg;
+                const double bi = a.b64[row];
+                exact_row(a.A64 + (size_t)row * lda, a.X + (size_t)chain * lda,
+                          a.D + (size_t)chain * lda, bi, n, sx, gg);
+                chord_row(cs, cl, sx, gg, bi);
+            }
+        }
+    };
+    auto load_rows = [&](int cl, int qq, float& s32, float& g32, float& na, float& nau,
+                         float& ab) __attribute__((always_inline)) {
+        const int row = qq * kRowGroup + lane;
+        const size_t idx = frag_index<F64>(tile, Q, row, cl);
+        s32 = (float)S[idx];
+        g32 = (float)Gb[idx];
+        na = a.rownorm[row];
+        nau = a.rk > 0 ? a.aun[row] : 0.0f;
+        ab = a.absb[row];
+    };
+    unsigned long long nex = 0;
     for (int cl = wave; cl < kChainTile; cl += kWaves) {
         const int chain = c0 + cl;
         if (chain >= a.z) continue;
         const float up = __uint_as_float(cs->up[cl]);
         const float um = __uint_as_float(cs->um[cl]);
-        float ed, ed2 = 0.0f, Fk = 0.0f;
-        if (a.rk > 0) {
-            const double hn = cs->hnorm[cl], en = cs->enorm[cl];
-            const double dx = 0x1.0p-36 * (hn + cs->dnorm[cl] + *a.uF * en);
-            ed = (float)(hn * (double)a.eps_g + dx) * kHighGrow + 1e-30f;
-            ed2 = (float)(en * (double)a.eps_g) * kHighGrow;
-            Fk = (float)cs->F[cl] * kHighGrow;
-        } else {
-            ed = (float)(cs->dnorm[cl] * (double)a.eps_g) * kHighGrow + 1e-30f;
+        if (lane == 0) {
+            float ed, ed2 = 0.0f, Fk = 0.0f;
+            if (a.rk > 0) {
+                const double hn = cs->hnorm[cl], en = cs->enorm[cl];
+                const double dx = 0x1.0p-36 * (hn + cs->dnorm[cl] + *a.uF * en);
+                ed = (float)(hn * (double)a.eps_g + dx) * kHighGrow + 1e-30f;
+                ed2 = (float)(en * (double)a.eps_g) * kHighGrow;
+                Fk = (float)cs->F[cl] * kHighGrow;
+            } else {
+                ed = (float)(cs->dnorm[cl] * (double)a.eps_g) * kHighGrow + 1e-30f;
+            }
+            cs->w_up[cl] = up;
+            cs->w_um[cl] = um;
+            cs->w_ed[cl] = ed;
+            cs->w_ed2[cl] = ed2;
+            cs->w_F[cl] = Fk;
+            cs->w_E[cl] = (float)cs->E[cl] * kHighGrow;
         }
-        const float Ek = (float)cs->E[cl] * kHighGrow;
-        unsigned long long nex = 0;
+        unsigned long long over = 0;   // groups past the pair list's capacity
         for (int qb = 0; qb < ngroups; qb += 64) {
             const int q = qb + lane;
             bool need = false;
             if (q < ngroups)
                 need = (Lt[(q * 2 + 0) * kChainTile + cl] <= up) ||
                        (Lt[(q * 2 + 1) * kChainTile + cl] <= um);
-            unsigned long long mask = __ballot(need);
-            while (mask) {
-                const int qq = qb + __ffsll((long long)mask) - 1;
-                mask &= mask - 1;
-                const int row = qq * kRowGroup + lane;
-                const size_t idx = frag_index<F64>(tile, Q, row, cl);
-                const float s32 = (float)S[idx], g32 = (float)Gb[idx];
-                const float na = a.rownorm[row];
-                const float nau = a.rk > 0 ? a.aun[row] : 0.0f;
-                float dl = fmaf(nau, Fk, fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f)));
-                float e = fmaf(nau, ed2, na * ed);
-                if (F64) {
-                    dl = fmaf(fabsf(s32), 0x1.0p-23f, dl);
-                    e = fmaf(fabsf(g32), 0x1.0p-23f, e);
-                }
-                float lo_p, hi_p, lo_m, hi_m;
-                ratio_bounds(s32, g32, dl, e, lo_p, hi_p, lo_m, hi_m);
-                const bool cand = (row < a.m) && ((lo_p <= up) || (lo_m <= um));
-                nex += __popcll(__ballot(cand));
-                if (cand) {
-                    const int slot = atomicAdd(&cs->ncand, 1);
-                    if (slot < kCandCap) {
-                        cs->cand[slot] = make_int2(row, cl);
-                    } else {
-                        double s, gg;
-                        const double bi = a.b64[row];
-                        exact_row(a.A64 + (size_t)row * lda, a.X + (size_t)chain * lda,
-                                  a.D + (size_t)chain * lda, bi, n, s, gg);
-                        chord_row(cs, cl, s, gg, bi);
-                    }
-                }
+            const unsigned long long mask = __ballot(need);
+            if (!mask) continue;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&cs->npairs, __popcll(mask));
+            base = __shfl(base, 0, 64);
+            const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+            if (need && slot < kPairCap) cs->pairs[slot] = (cl << 16) | q;
+            over = __ballot(need && slot >= kPairCap);
+            while (over) {
+                const int qq = qb + __ffsll((long long)over) - 1;
+                over &= over - 1;
+                float s32, g32, na, nau, ab;
+                load_rows(cl, qq, s32, g32, na, nau, ab);
+                test_rows(cl, qq, s32, g32, na, nau, ab, nex);
             }
         }
-        if (lane == 0 && nex) atomicAdd(&cs->exact, nex);
     }
+    __syncthreads();
+    {
+        const int np = min(cs->npairs, kPairCap);
+        for (int p0 = wave; p0 < np; p0 += B * kWaves) {
+            float s32[B], g32[B], na[B], nau[B], ab[B];
+            int cl[B], qq[B];
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                const int p = p0 + k * kWaves;
+                const int pr = p < np ? cs->pairs[p] : -1;
+                cl[k] = pr >> 16;
+                qq[k] = pr & 0xffff;
+                if (pr >= 0) load_rows(cl[k], qq[k], s32[k], g32[k], na[k], nau[k], ab[k]);
+            }
+#pragma unroll
+            for (int k = 0; k < B; ++k)
+                if (p0 + k * kWaves < np) test_rows(cl[k], qq[k], s32[k], g32[k], na[k], nau[k], ab[k], nex);
+        }
+    }
+    if (lane == 0 && nex) atomicAdd(&cs->exact, nex);
     __syncthreads();
 
     // 2. exact FP64 evaluation of the listed rows, all in parallel
     const int nc = min(cs->ncand, kCandCap);
     const int nb_max = 96;
+    // chunk width: what the stage holds, and at most kStagePer pieces per thread
     int C = stage ? (int)(stage_bytes / (sizeof(double) * (nb_max + 2 * kChainTile))) - 2 : 0;
-    C = min(C, 128) & ~15;
+    C = min(C, 2 * kStagePer * kThreads / (nb_max + 2 * kChainTile)) & ~15;
     if (C >= 16) {
         exact_rows_staged(a, cs, c0, nc, stage, nb_max, C);
     } else {
@@ -840,7 +948,7 @@ __device__ void run_tile(const StepArgs& a, unsigned char* smem, int tile)
         stage_operand<P>(a, big, c0);
         screen<P>(a, cs, big, tile, c0, pending, T);
         __syncthreads();
-        exact_chords<P>(a, cs, tile, c0, step, s, T, (double*)big, big_bytes(a.lda));
+        exact_chords<P, 1>(a, cs, tile, c0, step, s, T, (double*)big, big_bytes(a.lda));
         __syncthreads();
         pending = 1;
         T += 1;
@@ -976,16 +1084,6 @@ __device__ __forceinline__ void sched_at(const StepArgs& a, int s, int& pending,
     recompute_after = since + 1 == a.R;
 }
 
-// Wait until at most N vector-memory operations of this wave are outstanding
-// (gfx9 s_waitcnt encoding; expcnt and lgkmcnt left at their maxima).
-template <int N>
-__device__ __forceinline__ void wait_vm()
-{
-    static_assert(N >= 0 && N < 64, "vmcnt range");
-    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-// Wait for this wave's LDS reads.
-__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 // Workgroup barrier that the compiler may not move memory accesses across and
 // that does not itself wait for the stage loads in flight (wait_vm says which
 // loads must have landed).
@@ -1139,8 +1237,7 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     };
 
     // slack and last product of this wave's entries, two walk tiles (a half)
-    // at a time; the first half is loaded before the main loop so that its
-    // latency is hidden behind the GEMM (only this tile writes these entries)
+    // at a time (only this tile writes these entries)
     const float* S = (const float*)a.S;
     const float* Gb = (const float*)a.G;
     const int Q = a.m_pad >> 4;
@@ -1151,13 +1248,19 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             const int tile = min(cbase, a.z_pad - kChainTile) / kChainTile;
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
-                const int q = ((R0 + wr * 64) >> 4) + rt;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
-                    sv[h][rt][r] = wave_rows ? S[idx] : 0.0f;
-                    gp[h][rt][r] = (wave_rows && pending) ? Gb[idx] : 0.0f;
-                }
+                // rows 4g .. 4g + 3 of the 16-row block: one 16-byte run
+                const size_t idx = frag_index<false>(tile, Q, R0 + wr * 64 + rt * 16 + 4 * g, c);
+                const float4 s4 = wave_rows ? *(const float4*)(S + idx) : make_float4(0, 0, 0, 0);
+                const float4 g4 = (wave_rows && pending) ? *(const float4*)(Gb + idx)
+                                                          : make_float4(0, 0, 0, 0);
+                sv[h][rt][0] = s4.x;
+                sv[h][rt][1] = s4.y;
+                sv[h][rt][2] = s4.z;
+                sv[h][rt][3] = s4.w;
+                gp[h][rt][0] = g4.x;
+                gp[h][rt][1] = g4.y;
+                gp[h][rt][2] = g4.z;
+                gp[h][rt][3] = g4.w;
             }
         }
     };
@@ -1201,9 +1304,6 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
         }
         wait_lds();   // the main loop's barriers publish them
     }
-    float sv0[2][4][4], gp0[2][4][4];
-    load_half(0, sv0, gp0);
-
     // two stages: K-step k + 1 lands while K-step k is multiplied; K-step
     // k + 2 is issued into the stage K-step k has left
     auto kstep = [&](int k, unsigned char* stage) __attribute__((always_inline)) {
@@ -1229,8 +1329,11 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     const int ngroups = a.m_pad / kRowGroup;
     const int grp = (R0 + wr * 64) / kRowGroup;
     const float bscale = a.u_s * (float)T * kHighGrow;
-    float sv1[2][4][4], gp1[2][4][4];
-    load_half(1, sv1, gp1);   // all loads of the second half issued before the arithmetic
+    // both halves' loads issued before the arithmetic: the second half's land
+    // while the first is processed
+    float sv0[2][4][4], gp0[2][4][4], sv1[2][4][4], gp1[2][4][4];
+    load_half(0, sv0, gp0);
+    load_half(1, sv1, gp1);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         float (*sv)[4][4] = half ? sv1 : sv0;
@@ -1248,18 +1351,20 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             float up = kInf, um = kInf, lp = kInf, lm = kInf;
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
-                const int q = ((R0 + wr * 64) >> 4) + rt;
+                // this lane's rows 4g .. 4g + 3 of the 16-row block, one 16-byte run
+                const size_t idx = frag_index<false>(tile, Q, R0 + wr * 64 + rt * 16 + 4 * g, c);
+                float snew[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    snew[r] = pending ? fmaf(-th, gp[h][rt][r], sv[h][rt][r]) : sv[h][rt][r];
+                if (pending) *(float4*)(Sw + idx) = make_float4(snew[0], snew[1], snew[2], snew[3]);
+                *(float4*)(Gw + idx) = make_float4(acc[rt][ct][0], acc[rt][ct][1], acc[rt][ct][2],
+                                                   acc[rt][ct][3]);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const size_t idx = (((size_t)tile * Q + q) * 4 + r) * 64 + lane;
                     const int lr = wr * 64 + rt * 16 + out_row<false>(g, r);   // row within the tile
                     const float gv = acc[rt][ct][r];
-                    float s_ = sv[h][rt][r];
-                    if (pending) {
-                        s_ = fmaf(-th, gp[h][rt][r], s_);
-                        Sw[idx] = s_;
-                    }
-                    Gw[idx] = gv;
+                    const float s_ = snew[r];
                     const float na = row_na[lr];
                     float dl = fmaf(na, Ek, fmaf(bscale, row_b[lr], 1e-30f));
                     float e = na * ed;
@@ -1370,7 +1475,7 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
             }
         }
         __syncthreads();
-        exact_chords<P>(a, cs, tile, c0, step, s_rel, T, (double*)stage_lds, kChordStageBytes);
+        exact_chords<P, 3>(a, cs, tile, c0, step, s_rel, T, (double*)stage_lds, kChordStageBytes);
         __syncthreads();
         if (tid < kChainTile) {
             const int chain = c0 + tid;
