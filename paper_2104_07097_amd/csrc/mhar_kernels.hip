@@ -281,31 +281,70 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
             if (2 * p + 1 < a.r) eps[cl * kMaxMeq + 2 * p + 1] = od;
         }
         __syncthreads();
-        // one coordinate per thread: its row of U is loaded once, in blocks of
-        // 8, and applied to the 16 walks, each walk's sum in rank order
-        for (int j = tid; j < n; j += kThreads) {
+        // two coordinates per thread (j and j + kThreads), each walk's sum in
+        // rank order.  U is read in blocks of 8 ranks, the next block's loads
+        // in flight during the current block's arithmetic; the 16 walks' eps
+        // are read two ranks at a time (16-byte LDS reads shared by both
+        // coordinates).
+        for (int j = tid; j < n; j += 2 * kThreads) {
+            const int j2 = j + kThreads;
+            const bool two = j2 < n;
             const double* ur = a.U + (size_t)j * a.r;
-            double v[kChainTile];
+            const double* ur2 = a.U + (size_t)(two ? j2 : j) * a.r;
+            double v[kChainTile], w[kChainTile];
 #pragma unroll
-            for (int cl = 0; cl < kChainTile; ++cl) v[cl] = 0.0;
+            for (int cl = 0; cl < kChainTile; ++cl) {
+                v[cl] = 0.0;
+                w[cl] = 0.0;
+            }
+            const int r8 = a.r & ~7;
+            double un[8], tn[8];
+            if (r8 > 0) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    un[e] = ur[e];
+                    tn[e] = ur2[e];
+                }
+            }
             int q = 0;
-            for (; q + 8 <= a.r; q += 8) {
-                double u8[8];
+            for (; q < r8; q += 8) {
+                wait_vm<0>();   // this block's U has landed
+                double uc[8], tc[8];
 #pragma unroll
-                for (int e = 0; e < 8; ++e) u8[e] = ur[q + e];
+                for (int e = 0; e < 8; ++e) {
+                    uc[e] = un[e];
+                    tc[e] = tn[e];
+                }
+                if (q + 8 < r8) {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
+                    for (int e = 0; e < 8; ++e) {
+                        un[e] = ur[q + 8 + e];
+                        tn[e] = ur2[q + 8 + e];
+                    }
+                }
 #pragma unroll
-                    for (int cl = 0; cl < kChainTile; ++cl)
-                        v[cl] = __dadd_rn(v[cl], __dmul_rn(u8[e], eps[cl * kMaxMeq + q + e]));
+                for (int e = 0; e < 8; e += 2) {
+#pragma unroll
+                    for (int cl = 0; cl < kChainTile; ++cl) {
+                        const double2 ep = *(const double2*)(eps + cl * kMaxMeq + q + e);
+                        v[cl] = __dadd_rn(v[cl], __dmul_rn(uc[e], ep.x));
+                        w[cl] = __dadd_rn(w[cl], __dmul_rn(tc[e], ep.x));
+                        v[cl] = __dadd_rn(v[cl], __dmul_rn(uc[e + 1], ep.y));
+                        w[cl] = __dadd_rn(w[cl], __dmul_rn(tc[e + 1], ep.y));
+                    }
+                }
             }
             for (; q < a.r; ++q) {
-                const double uq = ur[q];
+                const double u0 = ur[q], t0 = ur2[q];
 #pragma unroll
-                for (int cl = 0; cl < kChainTile; ++cl)
-                    v[cl] = __dadd_rn(v[cl], __dmul_rn(uq, eps[cl * kMaxMeq + q]));
+                for (int cl = 0; cl < kChainTile; ++cl) {
+                    const double e = eps[cl * kMaxMeq + q];
+                    v[cl] = __dadd_rn(v[cl], __dmul_rn(u0, e));
+                    w[cl] = __dadd_rn(w[cl], __dmul_rn(t0, e));
+                }
             }
             const double es = a.esig[j];
+            const double es2 = two ? a.esig[j2] : 0.0;
 #pragma unroll
             for (int cl = 0; cl < kChainTile; ++cl) {
                 if (c0 + cl < a.z) {
@@ -313,6 +352,12 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
                     const double hs = __dmul_rn(es, a.D[o]);
                     a.D[o] = __dadd_rn(v[cl], hs);
                     if (a.rk > 0) a.Hs[o] = hs;   // the isotropic part, for the split screening
+                    if (two) {
+                        const size_t o2 = o + kThreads;
+                        const double hs2 = __dmul_rn(es2, a.D[o2]);
+                        a.D[o2] = __dadd_rn(w[cl], hs2);
+                        if (a.rk > 0) a.Hs[o2] = hs2;
+                    }
                 }
             }
         }
