@@ -119,6 +119,8 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F);
 // all at once, and the next chunk's loads are issued before the current
 // chunk's sums, so one load latency per chunk is exposed, not one per piece.
 constexpr int kStagePer = 8;
+constexpr int kUpd = 16;   // coordinates per lane and block in the state update
+static_assert(kThreads == 32 * kChainTile, "32 lanes per walk in the norm pass");
 __device__ void exact_rows_staged(const StepArgs& a, ChainLds* cs, int c0, int nc, double* stage,
                                   int nb_max, int C)
 {
@@ -246,6 +248,11 @@ __device__ __forceinline__ size_t frag_index(int tile, int Q, int row, int c)
 // ---------------------------------------------------------------------------
 // Phase A: directions of the 16 walks of this tile at `step`.
 // ---------------------------------------------------------------------------
+// Wide (the chords kernel): the low-rank product two coordinates per thread
+// with U prefetched, and no norms (the caller computes them with the
+// operand); otherwise one coordinate per thread, fewer registers, and the
+// norms here.  Both sum each walk over the rank in order.
+template <bool Wide>
 __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_t step)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -281,82 +288,129 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
             if (2 * p + 1 < a.r) eps[cl * kMaxMeq + 2 * p + 1] = od;
         }
         __syncthreads();
-        // two coordinates per thread (j and j + kThreads), each walk's sum in
-        // rank order.  U is read in blocks of 8 ranks, the next block's loads
-        // in flight during the current block's arithmetic; the 16 walks' eps
-        // are read two ranks at a time (16-byte LDS reads shared by both
-        // coordinates).
-        for (int j = tid; j < n; j += 2 * kThreads) {
-            const int j2 = j + kThreads;
-            const bool two = j2 < n;
-            const double* ur = a.U + (size_t)j * a.r;
-            const double* ur2 = a.U + (size_t)(two ? j2 : j) * a.r;
-            double v[kChainTile], w[kChainTile];
-#pragma unroll
-            for (int cl = 0; cl < kChainTile; ++cl) {
-                v[cl] = 0.0;
-                w[cl] = 0.0;
-            }
-            const int r8 = a.r & ~7;
-            double un[8], tn[8];
-            if (r8 > 0) {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    un[e] = ur[e];
-                    tn[e] = ur2[e];
-                }
-            }
-            int q = 0;
-            for (; q < r8; q += 8) {
-                wait_vm<0>();   // this block's U has landed
-                double uc[8], tc[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    uc[e] = un[e];
-                    tc[e] = tn[e];
-                }
-                if (q + 8 < r8) {
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        un[e] = ur[q + 8 + e];
-                        tn[e] = ur2[q + 8 + e];
-                    }
-                }
-#pragma unroll
-                for (int e = 0; e < 8; e += 2) {
-#pragma unroll
-                    for (int cl = 0; cl < kChainTile; ++cl) {
-                        const double2 ep = *(const double2*)(eps + cl * kMaxMeq + q + e);
-                        v[cl] = __dadd_rn(v[cl], __dmul_rn(uc[e], ep.x));
-                        w[cl] = __dadd_rn(w[cl], __dmul_rn(tc[e], ep.x));
-                        v[cl] = __dadd_rn(v[cl], __dmul_rn(uc[e + 1], ep.y));
-                        w[cl] = __dadd_rn(w[cl], __dmul_rn(tc[e + 1], ep.y));
-                    }
-                }
-            }
-            for (; q < a.r; ++q) {
-                const double u0 = ur[q], t0 = ur2[q];
+        if constexpr (Wide) {
+            // two coordinates per thread (j and j + kThreads), each walk's sum in
+            // rank order.  U is read in blocks of 8 ranks, the next block's loads
+            // in flight during the current block's arithmetic; the 16 walks' eps
+            // are read two ranks at a time (16-byte LDS reads shared by both
+            // coordinates).
+            for (int j = tid; j < n; j += 2 * kThreads) {
+                const int j2 = j + kThreads;
+                const bool two = j2 < n;
+                const double* ur = a.U + (size_t)j * a.r;
+                const double* ur2 = a.U + (size_t)(two ? j2 : j) * a.r;
+                double v[kChainTile], w[kChainTile];
 #pragma unroll
                 for (int cl = 0; cl < kChainTile; ++cl) {
-                    const double e = eps[cl * kMaxMeq + q];
-                    v[cl] = __dadd_rn(v[cl], __dmul_rn(u0, e));
-                    w[cl] = __dadd_rn(w[cl], __dmul_rn(t0, e));
+                    v[cl] = 0.0;
+                    w[cl] = 0.0;
+                }
+                const int r8 = a.r & ~7;
+                double un[8], tn[8];
+                if (r8 > 0) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        un[e] = ur[e];
+                        tn[e] = ur2[e];
+                    }
+                }
+                int q = 0;
+                for (; q < r8; q += 8) {
+                    wait_vm<0>();   // this block's U has landed
+                    double uc[8], tc[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        uc[e] = un[e];
+                        tc[e] = tn[e];
+                    }
+                    if (q + 8 < r8) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            un[e] = ur[q + 8 + e];
+                            tn[e] = ur2[q + 8 + e];
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < 8; e += 2) {
+#pragma unroll
+                        for (int cl = 0; cl < kChainTile; ++cl) {
+                            const double2 ep = *(const double2*)(eps + cl * kMaxMeq + q + e);
+                            v[cl] = __dadd_rn(v[cl], __dmul_rn(uc[e], ep.x));
+                            w[cl] = __dadd_rn(w[cl], __dmul_rn(tc[e], ep.x));
+                            v[cl] = __dadd_rn(v[cl], __dmul_rn(uc[e + 1], ep.y));
+                            w[cl] = __dadd_rn(w[cl], __dmul_rn(tc[e + 1], ep.y));
+                        }
+                    }
+                }
+                for (; q < a.r; ++q) {
+                    const double u0 = ur[q], t0 = ur2[q];
+#pragma unroll
+                    for (int cl = 0; cl < kChainTile; ++cl) {
+                        const double e = eps[cl * kMaxMeq + q];
+                        v[cl] = __dadd_rn(v[cl], __dmul_rn(u0, e));
+                        w[cl] = __dadd_rn(w[cl], __dmul_rn(t0, e));
+                    }
+                }
+                const double es = a.esig[j];
+                const double es2 = two ? a.esig[j2] : 0.0;
+                // the draws of both coordinates, all loads before the stores
+                double h1[kChainTile], h2[kChainTile];
+#pragma unroll
+                for (int cl = 0; cl < kChainTile; ++cl) {
+                    const size_t o = (size_t)(c0 + cl) * lda + j;
+                    const bool live = c0 + cl < a.z;
+                    h1[cl] = live ? a.D[o] : 0.0;
+                    h2[cl] = (live && two) ? a.D[o + kThreads] : 0.0;
+                }
+#pragma unroll
+                for (int cl = 0; cl < kChainTile; ++cl) {
+                    if (c0 + cl < a.z) {
+                        const size_t o = (size_t)(c0 + cl) * lda + j;
+                        const double hs = __dmul_rn(es, h1[cl]);
+                        a.D[o] = __dadd_rn(v[cl], hs);
+                        if (a.rk > 0) a.Hs[o] = hs;   // the isotropic part, for the split screening
+                        if (two) {
+                            const size_t o2 = o + kThreads;
+                            const double hs2 = __dmul_rn(es2, h2[cl]);
+                            a.D[o2] = __dadd_rn(w[cl], hs2);
+                            if (a.rk > 0) a.Hs[o2] = hs2;
+                        }
+                    }
                 }
             }
-            const double es = a.esig[j];
-            const double es2 = two ? a.esig[j2] : 0.0;
+        } else {
+            // one coordinate per thread: its row of U is loaded once, in blocks of
+            // 8, and applied to the 16 walks
+            for (int j = tid; j < n; j += kThreads) {
+                const double* ur = a.U + (size_t)j * a.r;
+                double v[kChainTile];
 #pragma unroll
-            for (int cl = 0; cl < kChainTile; ++cl) {
-                if (c0 + cl < a.z) {
-                    const size_t o = (size_t)(c0 + cl) * lda + j;
-                    const double hs = __dmul_rn(es, a.D[o]);
-                    a.D[o] = __dadd_rn(v[cl], hs);
-                    if (a.rk > 0) a.Hs[o] = hs;   // the isotropic part, for the split screening
-                    if (two) {
-                        const size_t o2 = o + kThreads;
-                        const double hs2 = __dmul_rn(es2, a.D[o2]);
-                        a.D[o2] = __dadd_rn(w[cl], hs2);
-                        if (a.rk > 0) a.Hs[o2] = hs2;
+                for (int cl = 0; cl < kChainTile; ++cl) v[cl] = 0.0;
+                int q = 0;
+                for (; q + 8 <= a.r; q += 8) {
+                    double u8[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) u8[e] = ur[q + e];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+#pragma unroll
+                        for (int cl = 0; cl < kChainTile; ++cl)
+                            v[cl] = __dadd_rn(v[cl], __dmul_rn(u8[e], eps[cl * kMaxMeq + q + e]));
+                }
+                for (; q < a.r; ++q) {
+                    const double uq = ur[q];
+#pragma unroll
+                    for (int cl = 0; cl < kChainTile; ++cl)
+                        v[cl] = __dadd_rn(v[cl], __dmul_rn(uq, eps[cl * kMaxMeq + q]));
+                }
+                const double es = a.esig[j];
+#pragma unroll
+                for (int cl = 0; cl < kChainTile; ++cl) {
+                    if (c0 + cl < a.z) {
+                        const size_t o = (size_t)(c0 + cl) * lda + j;
+                        const double hs = __dmul_rn(es, a.D[o]);
+                        a.D[o] = __dadd_rn(v[cl], hs);
+                        if (a.rk > 0) a.Hs[o] = hs;   // the isotropic part, for the split screening
                     }
                 }
             }
@@ -418,6 +472,7 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
             *dp = v;
         }
     }
+    if (Wide) return;
     __syncthreads();
     // norms of d (wave per walk), and of the isotropic part
     for (int cl = wave; cl < kChainTile; cl += kWaves) {
@@ -855,14 +910,30 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
         double* rp = rec ? a.rec_out + ((size_t)((a.rec_s_base + s_rel + 1) / a.rec_stride - 1) *
                                             a.rec_chains + chain) * n
                          : nullptr;
-        for (int j = lane; j < n; j += 64) {
-            double xv = xw[j];
-            double xnew = __dadd_rn(xv, __dmul_rn(th, dr[j]));
-            xw[j] = xnew;
-            if (rec) rp[j] = xnew;
-            xo = fma(xv, xv, xo);
-            xn2 = fma(xnew, xnew, xn2);
-            finite = finite && isfinite(xnew);
+        // blocks of U coordinates per lane: all loads of a block are issued
+        // before its stores (one load latency per block); one per block in
+        // the single-kernel path, whose registers are spoken for
+        constexpr int U = B > 1 ? kUpd : 1;
+        for (int jb = 0; jb < n; jb += 64 * U) {
+            double xv[U], dv[U];
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const int j = jb + lane + 64 * e;
+                xv[e] = j < n ? xw[j] : 0.0;
+                dv[e] = j < n ? dr[j] : 0.0;
+            }
+#pragma unroll
+            for (int e = 0; e < U; ++e) {
+                const int j = jb + lane + 64 * e;
+                if (j < n) {
+                    const double xnew = __dadd_rn(xv[e], __dmul_rn(th, dv[e]));
+                    xw[j] = xnew;
+                    if (rec) rp[j] = xnew;
+                    xo = fma(xv[e], xv[e], xo);
+                    xn2 = fma(xnew, xnew, xn2);
+                    finite = finite && isfinite(xnew);
+                }
+            }
         }
         xo = wave_sum(xo);
         xn2 = wave_sum(xn2);
@@ -989,7 +1060,7 @@ __device__ void run_tile(const StepArgs& a, unsigned char* smem, int tile)
             cs->up[tid] = __float_as_uint(kInf);
             cs->um[tid] = __float_as_uint(kInf);
         }
-        make_directions(a, cs, c0, step);
+        make_directions<false>(a, cs, c0, step);
         stage_operand<P>(a, big, c0);
         screen<P>(a, cs, big, tile, c0, pending, T);
         __syncthreads();
@@ -1533,7 +1604,58 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
         __syncthreads();
     }
     if (!gen_dirs) return;
-    make_directions(a, cs, c0, dir_step);
+    make_directions<true>(a, cs, c0, dir_step);
+    __syncthreads();
+    // norms and the screening operand in one pass, 32 lanes per walk: the
+    // operand is the direction, or with the split screening its isotropic
+    // part (the low-rank part's operand was written with the draws)
+    {
+        const int cl = tid >> 5, t = tid & 31, chain = c0 + cl;
+        const bool live = chain < a.z, split = a.rk > 0;
+        const double* dr = a.D + (size_t)chain * lda;
+        const double* hr = split ? a.Hs + (size_t)chain * lda : dr;
+        double v = 0.0, w = 0.0;
+        for (int jb = 0; jb < lda; jb += 32 * kUpd) {
+            double dv[kUpd], hv[kUpd];
+#pragma unroll
+            for (int e = 0; e < kUpd; ++e) {
+                const int j = jb + t + 32 * e;
+                const bool in = live && j < n;
+                dv[e] = in ? dr[j] : 0.0;
+                hv[e] = (in && split) ? hr[j] : dv[e];
+            }
+#pragma unroll
+            for (int e = 0; e < kUpd; ++e) {
+                v = fma(dv[e], dv[e], v);
+                if (split) w = fma(hv[e], hv[e], w);
+            }
+#pragma unroll
+            for (int e = 0; e < kUpd; ++e) {
+                const int j = jb + t + 32 * e;
+                if (j < lda) {
+                    const size_t o = (size_t)chain * lda + j;
+                    const float op = (float)hv[e];   // zero past n and for idle walks
+                    if (P == kBF16X3) {
+                        __bf16 hi, lo;
+                        split_bf16(op, hi, lo);
+                        ((__bf16*)a.Dop)[o] = hi;
+                        ((__bf16*)a.Dop)[(size_t)a.z_pad * lda + o] = lo;
+                    } else {
+                        ((float*)a.Dop)[o] = op;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) {
+            v += __shfl_xor(v, off, 64);
+            w += __shfl_xor(w, off, 64);
+        }
+        if (t == 0) {
+            cs->dnorm[cl] = sqrt(v);
+            cs->hnorm[cl] = sqrt(w);
+        }
+    }
     __syncthreads();
     if (tid < kChainTile) {
         a.dn[c0 + tid] = cs->dnorm[tid];
@@ -1542,38 +1664,8 @@ __device__ void chords_tile(const StepArgs& a, int tile, uint64_t step, int s_re
             a.en[c0 + tid] = cs->enorm[tid];
         }
     }
-    // the screening operand: the direction, or with the split screening its
-    // isotropic part (the low-rank part's operand was written with the draws)
-    const double* Dsrc = a.rk > 0 ? a.Hs : a.D;
-    if (P == kBF16X3) {
-        __bf16* Dh = (__bf16*)a.Dop;
-        __bf16* Dl = Dh + (size_t)a.z_pad * lda;
-        for (int item = tid; item < kChainTile * lda; item += kThreads) {
-            const int cl = item / lda, j = item - cl * lda, chain = c0 + cl;
-            const size_t o = (size_t)chain * lda + j;
-            const float v = (chain < a.z && j < n) ? (float)Dsrc[o] : 0.0f;
-            __bf16 hi, lo;
-            split_bf16(v, hi, lo);
-            Dh[o] = hi;
-            Dl[o] = lo;
-        }
-    } else {
-        float* Df = (float*)a.Dop;
-        for (int item = tid; item < kChainTile * lda; item += kThreads) {
-            const int cl = item / lda, j = item - cl * lda, chain = c0 + cl;
-            const size_t o = (size_t)chain * lda + j;
-            Df[o] = (chain < a.z && j < n) ? (float)Dsrc[o] : 0.0f;
-        }
-    }
 }
 
-// Directions of global step `step` for the tiled path, one workgroup per
-// walk (isotropic directions): draws, projection, norm and the operand row,
-// each in the operation order of make_directions (the projection's A_eq h
-// and the norm as lane-strided FMA chains and a wave reduction), so the
-// directions are bitwise those the chords kernel would make; with one
-// workgroup per walk instead of per 16 walks, small walk counts still fill
-// the device.
 // Step counter of graph replays: set before the first replay, advanced by
 // the last node of each replay.
 __global__ void step_counter_kernel(uint64_t* ctr, uint64_t value, int add)
@@ -1581,30 +1673,65 @@ __global__ void step_counter_kernel(uint64_t* ctr, uint64_t value, int add)
     if (threadIdx.x == 0) *ctr = add ? *ctr + value : value;
 }
 
+// Directions of global step `step` for the tiled path, one workgroup of 4
+// waves per walk (isotropic directions): draws, projection, norm and the
+// operand row.  Draws and projection follow the operation order of
+// make_directions (the projection's A_eq h as lane-strided FMA chains and a
+// wave reduction), so the directions are bitwise those the chords kernel
+// would make (the norm, which only scales certified error terms, may differ
+// in its last bits).  With one workgroup per walk instead of per 16 walks,
+// small walk counts still fill the device.
+constexpr int kDirThreads = 256;
 template <int P>
-__global__ __launch_bounds__(kThreads) void tiled_dirs_kernel(StepArgs a, uint64_t step)
+__global__ __launch_bounds__(kDirThreads) void tiled_dirs_kernel(StepArgs a, uint64_t step)
 {
+    constexpr int kDW = kDirThreads / 64;
     if (a.step_dev) step += *a.step_dev;
     __shared__ double y[kMaxMeq];
-    __shared__ double dn2;
+    __shared__ double part[kDW];
     const int chain = blockIdx.x;   // < z_pad
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = a.n, lda = a.lda;
     const bool live = chain < a.z;
     double* drow = a.D + (size_t)chain * lda;
+    const size_t o0 = (size_t)chain * lda;
+    // operand element j of this walk
+    auto put_op = [&](int j, double v) __attribute__((always_inline)) {
+        if (P == kBF16X3) {
+            __bf16 hi, lo;
+            split_bf16((float)v, hi, lo);
+            ((__bf16*)a.Dop)[o0 + j] = hi;
+            ((__bf16*)a.Dop)[(size_t)a.z_pad * lda + o0 + j] = lo;
+        } else {
+            ((float*)a.Dop)[o0 + j] = (float)v;
+        }
+    };
+    // without equalities the draws are the direction: the row, its operand
+    // and its squared norm come straight from registers
+    const bool direct = a.m_eq == 0;
+    double v2 = 0.0;
     if (live) {
         const int npairs = (n + 1) >> 1;
-        for (int p = tid; p < npairs; p += kThreads) {
+        for (int p = tid; p < npairs; p += kDirThreads) {
             Block4 w = stream_block(a.seed, kTagDir, a.chain_offset + (uint32_t)chain, step, (uint32_t)p);
             double ev, od;
             gauss_pair(w, ev, od);
+            const bool has_od = 2 * p + 1 < n;
             drow[2 * p] = ev;
-            if (2 * p + 1 < n) drow[2 * p + 1] = od;
+            if (has_od) drow[2 * p + 1] = od;
+            if (direct) {
+                v2 = fma(ev, ev, v2);
+                put_op(2 * p, ev);
+                if (has_od) {
+                    v2 = fma(od, od, v2);
+                    put_op(2 * p + 1, od);
+                }
+            }
         }
     }
-    if (live && a.m_eq > 0) {
+    if (live && !direct) {
         __syncthreads();
-        for (int p = wave; p < a.m_eq; p += kWaves) {
+        for (int p = wave; p < a.m_eq; p += kDW) {
             const double* er = a.Aeq + (size_t)p * lda;
             double v = 0.0;
             for (int j = lane; j < n; j += 64) v = fma(er[j], drow[j], v);
@@ -1612,37 +1739,24 @@ __global__ __launch_bounds__(kThreads) void tiled_dirs_kernel(StepArgs a, uint64
             if (lane == 0) y[p] = v;
         }
         __syncthreads();
-        for (int j = tid; j < n; j += kThreads) {
+        for (int j = tid; j < n; j += kDirThreads) {
             double v = drow[j];
             for (int p = 0; p < a.m_eq; ++p) v = fma(-a.WT[(size_t)p * lda + j], y[p], v);
             drow[j] = v;
+            v2 = fma(v, v, v2);
+            put_op(j, v);
         }
     }
+    // operand padding past n, and the whole row of an idle walk
+    for (int j = (live ? n : 0) + tid; j < lda; j += kDirThreads) put_op(j, 0.0);
+    v2 = wave_sum(v2);
+    if (lane == 0) part[wave] = v2;
     __syncthreads();
-    if (wave == 0) {
-        double v = 0.0;
-        if (live)
-            for (int j = lane; j < n; j += 64) v = fma(drow[j], drow[j], v);
-        v = wave_sum(v);
-        if (lane == 0) dn2 = v;
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kDW; ++w) t += part[w];
+        a.dn[chain] = sqrt(t);
     }
-    const size_t o0 = (size_t)chain * lda;
-    if (P == kBF16X3) {
-        __bf16* Dh = (__bf16*)a.Dop;
-        __bf16* Dl = Dh + (size_t)a.z_pad * lda;
-        for (int j = tid; j < lda; j += kThreads) {
-            const float v = (live && j < n) ? (float)drow[j] : 0.0f;
-            __bf16 hi, lo;
-            split_bf16(v, hi, lo);
-            Dh[o0 + j] = hi;
-            Dl[o0 + j] = lo;
-        }
-    } else {
-        float* Df = (float*)a.Dop;
-        for (int j = tid; j < lda; j += kThreads) Df[o0 + j] = (live && j < n) ? (float)drow[j] : 0.0f;
-    }
-    __syncthreads();
-    if (tid == 0) a.dn[chain] = sqrt(dn2);
 }
 
 template <int P>
@@ -2130,7 +2244,7 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTr
     if (a.steps > 0) {
         if (own_dirs) {
             TraceScope ts_(trace, stream, kTraceDirs);
-            hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kThreads), 0, stream, a, a.step0);
+            hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kDirThreads), 0, stream, a, a.step0);
         } else {
             TraceScope ts_(trace, stream, kTraceChords);
             hipLaunchKernelGGL(tiled_chords_kernel<P>, grid_c, dim3(kThreads), 0, stream, a,
@@ -2156,7 +2270,7 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTr
         }
         if (more && own_dirs) {
             TraceScope ts_(trace, stream, kTraceDirs);
-            hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kThreads), 0, stream, a, step + 1);
+            hipLaunchKernelGGL(tiled_dirs_kernel<P>, grid_d, dim3(kDirThreads), 0, stream, a, step + 1);
         }
         pending = 1;
         T += 1;
