@@ -1445,13 +1445,15 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     const int ngroups = a.m_pad / kRowGroup;
     const int grp = (R0 + wr * 64) / kRowGroup;
     const float bscale = a.u_s * (float)T * kHighGrow;
-    // both halves' loads issued before the arithmetic: the second half's land
-    // while the first is processed
+    // the isotropic kernel issues both halves' loads before the arithmetic
+    // (the second half's land while the first is processed); the split
+    // kernel, short of registers, loads the second half after the first
     float sv0[2][4][4], gp0[2][4][4], sv1[2][4][4], gp1[2][4][4];
     load_half(0, sv0, gp0);
-    load_half(1, sv1, gp1);
+    if (!SPLIT) load_half(1, sv1, gp1);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
+        if (SPLIT && half == 1) load_half(1, sv1, gp1);
         float (*sv)[4][4] = half ? sv1 : sv0;
         float (*gp)[4][4] = half ? gp1 : gp0;
 #pragma unroll
@@ -1465,22 +1467,35 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             const float ed = walk_ed[lw], ed2 = walk_ed2[lw], Fk = walk_F[lw];
             const float Ek = walk_E[lw], th = walk_th[lw];
             float up = kInf, um = kInf, lp = kInf, lm = kInf;
+            // the updated slack in place; then the stores of this walk
+            // tile's 64 rows back to back, so that each walk's 256-byte run of
+            // S and of G reaches the cache whole (no partial lines)
 #pragma unroll
-            for (int rt = 0; rt < 4; ++rt) {
-                // this lane's rows 4g .. 4g + 3 of the 16-row block, one 16-byte run
-                const size_t idx = frag_index<false>(tile, Q, R0 + wr * 64 + rt * 16 + 4 * g, c);
-                float snew[4];
+            for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    snew[r] = pending ? fmaf(-th, gp[h][rt][r], sv[h][rt][r]) : sv[h][rt][r];
-                if (pending) *(float4*)(Sw + idx) = make_float4(snew[0], snew[1], snew[2], snew[3]);
+                    if (pending) sv[h][rt][r] = fmaf(-th, gp[h][rt][r], sv[h][rt][r]);
+            if (pending) {
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const size_t idx = frag_index<false>(tile, Q, R0 + wr * 64 + rt * 16 + 4 * g, c);
+                    *(float4*)(Sw + idx) = make_float4(sv[h][rt][0], sv[h][rt][1], sv[h][rt][2],
+                                                       sv[h][rt][3]);
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const size_t idx = frag_index<false>(tile, Q, R0 + wr * 64 + rt * 16 + 4 * g, c);
                 *(float4*)(Gw + idx) = make_float4(acc[rt][ct][0], acc[rt][ct][1], acc[rt][ct][2],
                                                    acc[rt][ct][3]);
+            }
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int lr = wr * 64 + rt * 16 + out_row<false>(g, r);   // row within the tile
                     const float gv = acc[rt][ct][r];
-                    const float s_ = snew[r];
+                    const float s_ = sv[h][rt][r];
                     const float na = row_na[lr];
                     float dl = fmaf(na, Ek, fmaf(bscale, row_b[lr], 1e-30f));
                     float e = na * ed;
