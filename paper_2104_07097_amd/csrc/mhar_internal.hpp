@@ -18,8 +18,8 @@ constexpr int kMaxNResident = 256;  // longest padded row of the register-reside
 constexpr int kMaxNTiled = 8192; // the tiled path keeps no row of length n in LDS
 constexpr int kScreenRows = 128; // tiled path: rows x walks of a screening tile
 constexpr int kScreenWalks = 128;
-constexpr int kRecRows = 256;    // tiled path: rows x walks of a recompute tile
-constexpr int kRecWalks = 64;
+constexpr int kRecRows = 128;    // tiled path: rows x walks of a recompute tile
+constexpr int kRecWalks = 128;
 constexpr int kMaxMeq = 64;
 constexpr int kMaxNDikin = 4096; // the Dikin covariance fit keeps two n x n FP64 matrices
 

@@ -1804,10 +1804,12 @@ __global__ __launch_bounds__(kThreads) void grouped_chords_kernel(const StepArgs
     chords_tile<P>(a, u.y, step, s, T, do_chords, gen_dirs, do_chords ? step + 1 : step);
 }
 
-// Exact FP64 slack s = b - A X over (256-row x 64-walk) tiles on the FP64
+// Exact FP64 slack s = b - A X over (128-row x 128-walk) tiles on the FP64
 // matrix cores, stored in the screening layout; workgroups of the first row
 // block also reset the drift coefficient of their walks.
 constexpr int kRR = kRecRows, kRW = kRecWalks, kRK = 16;
+constexpr int kRecThreads = 256;   // 4 waves, each 64 rows x 64 walks; two workgroups per CU
+constexpr int kRecWaves = kRecThreads / 64;
 constexpr int kRRowBytes = kRK * 8 + 16;
 constexpr int kRStage = (kRR + kRW) * kRRowBytes;
 
@@ -1815,23 +1817,31 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
 {
     constexpr int kChunkRow = kRK * 8 / 16;                 // 8
     constexpr int kAChunks = kRR * kChunkRow;               // 2048
-    constexpr int kPer = (kRR + kRW) * kChunkRow / kThreads;  // 5
-    static_assert((kRR + kRW) * kChunkRow % kThreads == 0, "chunk split");
+    constexpr int kPer = (kRR + kRW) * kChunkRow / kRecThreads;  // 8
+    static_assert((kRR + kRW) * kChunkRow % kRecThreads == 0, "chunk split");
+    static_assert(kRR == 128 && kRW == 128, "wave layout: 2 x 2 waves of 64 rows x 64 walks");
     const int R0 = rb * kRR, C0 = cb * kRW;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, c = lane & 15;
-    const int wr = wave & 3, wc = wave >> 2;   // 64 rows x 32 walks per wave
+    const int wr = wave & 1, wc = wave >> 1;   // 64 rows x 64 walks per wave
     const int lda = a.lda, n = a.n;
 
     if (rb == 0) {
         // drift coefficient after an exact recompute (one wave per walk)
-        for (int w = wave; w < kRW; w += kWaves) {
+        for (int w = wave; w < kRW; w += kRecWaves) {
             const int chain = C0 + w;
             if (chain >= a.z_pad) break;
             double v = 0.0;
-            for (int j = lane; j < n; j += 64) {
-                const double x = a.X[(size_t)chain * lda + j];
-                v = fma(x, x, v);
+            // blocks of 16 coordinates per lane, all loads of a block in flight
+            for (int jb = 0; jb < n; jb += 64 * 16) {
+                double x[16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int j = jb + lane + 64 * e;
+                    x[e] = j < n ? a.X[(size_t)chain * lda + j] : 0.0;
+                }
+#pragma unroll
+                for (int e = 0; e < 16; ++e) v = fma(x[e], x[e], v);
             }
             v = wave_sum(v);
             if (lane == 0) {
@@ -1846,7 +1856,7 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
     bool ok[kPer];
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
-        const int u = tid + i * kThreads;
+        const int u = tid + i * kRecThreads;
         if (u < kAChunks) {
             const int row = u / kChunkRow, part = u - row * kChunkRow;
             ok[i] = R0 + row < a.m_pad;
@@ -1872,11 +1882,11 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
         for (int i = 0; i < kPer; ++i) *(uint4*)(base + dst[i]) = buf[i];
     };
 
-    f64x4 acc[4][2];
+    f64x4 acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
+        for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
     const bool wave_rows = R0 + wr * 64 < a.m_pad;
     const int nk = lda / kRK;
     fetch(0);
@@ -1886,7 +1896,7 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
         if (kt + 1 < nk) fetch((kt + 1) * kRK);
         const unsigned char* base = smem + (kt & 1) * kRStage;
         if (wave_rows) {
-            double2 av[4][2], bv[2][2];
+            double2 av[4][2], bv[4][2];
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt) {
                 const unsigned char* p = base + (wr * 64 + rt * 16 + c) * kRRowBytes + 32 * g;
@@ -1894,8 +1904,8 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
                 av[rt][1] = *(const double2*)(p + 16);
             }
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
-                const unsigned char* p = base + (kRR + wc * 32 + ct * 16 + c) * kRRowBytes + 32 * g;
+            for (int ct = 0; ct < 4; ++ct) {
+                const unsigned char* p = base + (kRR + wc * 64 + ct * 16 + c) * kRRowBytes + 32 * g;
                 bv[ct][0] = *(const double2*)p;
                 bv[ct][1] = *(const double2*)(p + 16);
             }
@@ -1905,7 +1915,7 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
 #pragma unroll
                 for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-                    for (int ct = 0; ct < 2; ++ct)
+                    for (int ct = 0; ct < 4; ++ct)
                         acc[rt][ct] = mma_f64((&av[rt][i >> 1].x)[i & 1],
                                               (&bv[ct][i >> 1].x)[i & 1], acc[rt][ct]);
         }
@@ -1916,8 +1926,8 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
     float* S = (float*)a.S;
     const int Q = a.m_pad >> 4;
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-        const int cbase = C0 + wc * 32 + ct * 16;
+    for (int ct = 0; ct < 4; ++ct) {
+        const int cbase = C0 + wc * 64 + ct * 16;
         if (cbase >= a.z_pad) break;
         const int tile = cbase / kChainTile, chain = cbase + c;
         const bool active = chain < a.z;
@@ -1942,7 +1952,7 @@ __device__ void recompute_tile(const StepArgs& a, int rb, int cb, unsigned char*
     }
 }
 
-__global__ __launch_bounds__(kThreads) void tiled_recompute_kernel(StepArgs a)
+__global__ __launch_bounds__(kRecThreads, 2) void tiled_recompute_kernel(StepArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nrb = (a.m_pad + kRR - 1) / kRR, ncb = (a.z_pad + kRW - 1) / kRW;
@@ -1954,7 +1964,7 @@ __global__ __launch_bounds__(kThreads) void tiled_recompute_kernel(StepArgs a)
 // Recompute tiles of many problems: entry (problem, rb, cb).  first != 0: the
 // problems flagged recompute_first, before the launch's first step; else the
 // problems whose schedule has a recompute after step s.
-__global__ __launch_bounds__(kThreads) void grouped_recompute_kernel(const StepArgs* __restrict__ descs,
+__global__ __launch_bounds__(kRecThreads, 2) void grouped_recompute_kernel(const StepArgs* __restrict__ descs,
                                                                      const int4* __restrict__ tiles,
                                                                      int ntiles, int s, int first)
 {
@@ -2247,7 +2257,7 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTr
     int pending = a.pending0, T = a.T0, since = a.since0;
     if (a.recompute_first) {
         TraceScope ts_(trace, stream, kTraceRecompute);
-        hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kThreads), lds_r, stream, a);
+        hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kRecThreads), lds_r, stream, a);
         pending = 0;
         T = 2;
         since = 0;
@@ -2292,7 +2302,7 @@ static hipError_t launch_tiled_t(const StepArgs& a, hipStream_t stream, KernelTr
         since += 1;
         if (since >= a.R) {
             TraceScope ts_(trace, stream, kTraceRecompute);
-            hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kThreads), lds_r, stream, a);
+            hipLaunchKernelGGL(tiled_recompute_kernel, grid_r, dim3(kRecThreads), lds_r, stream, a);
             pending = 0;
             T = 2;
             since = 0;
@@ -2314,7 +2324,7 @@ static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, in
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_r);
     if (e != hipSuccess) return e;
     if (first)
-        hipLaunchKernelGGL(grouped_recompute_kernel, dim3(nrt), dim3(kThreads), lds_r, stream, descs,
+        hipLaunchKernelGGL(grouped_recompute_kernel, dim3(nrt), dim3(kRecThreads), lds_r, stream, descs,
                            rtiles, nrt, 0, 1);
     if (steps > 0)
         hipLaunchKernelGGL(grouped_chords_kernel<P>, dim3(nunits), dim3(kThreads), 0, stream, descs,
@@ -2329,7 +2339,7 @@ static hipError_t launch_grouped_t(const StepArgs* descs, const int4* stiles, in
         hipLaunchKernelGGL(grouped_chords_kernel<P>, dim3(nunits), dim3(kThreads), 0, stream, descs,
                            units, nunits, s, 1, (int)(s + 1 < steps));
         if (due[s])
-            hipLaunchKernelGGL(grouped_recompute_kernel, dim3(nrt), dim3(kThreads), lds_r, stream,
+            hipLaunchKernelGGL(grouped_recompute_kernel, dim3(nrt), dim3(kRecThreads), lds_r, stream,
                                descs, rtiles, nrt, s, 0);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
