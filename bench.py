@@ -46,8 +46,8 @@ MFMA_PER_FLOP = {"fp32": 1, "bf16x3": 3, "fp64": 1}   # matrix-core products per
 # was measured on: reported as null once any of them differs.
 TRAFFIC = {
     "precision": "bf16x3", "steps_per_launch": 500,
-    "sources_sha256": "6f5315e4df38bca4baa94c2b3697826b3c30a99e02da5887be119c81cd59dbe7",
-    "fetch_kib": 25597.44, "fetch_scale": 262144.0 / 131096.69,
+    "sources_sha256": "1dc841d2bf34b73bc441e65eb111bcb98459693a6f3e030a178795d5da5512d0",
+    "fetch_kib": 25222.6, "fetch_scale": 262144.0 / 131095.4375,
     "write_kib": 46360.0, "write_scale": 262144.0 / 262144.0,
 }
 
@@ -89,9 +89,9 @@ def measured_traffic(precision, launch_steps):
 # same run; None until measured, and null once the kernel's sources change.
 TRAFFIC_ROTBOX = {
     "precision": "bf16x3",
-    "sources_sha256": "403d66b8788f7356ddfd3662971e56eba84d66dc7c8ef261c184d334f825fd26",
-    "fetch_kib": 890631.67, "fetch_scale": 262144.0 / 131088.6875,
-    "write_kib": 656326.81, "write_scale": 262144.0 / 262144.0,
+    "sources_sha256": "e1cc93391cffa6c1c246ed942a623f73c1ff089e49de75cb032ed8b5d3461203",
+    "fetch_kib": 881399.1, "fetch_scale": 262144.0 / 131089.375,
+    "write_kib": 654336.4, "write_scale": 262144.0 / 262144.0,
 }
 TRAFFIC_ROTBOX_SOURCES = ["paper_2104_07097_amd/csrc/mhar_kernels.hip",
                           "paper_2104_07097_amd/csrc/mhar_device.hpp",

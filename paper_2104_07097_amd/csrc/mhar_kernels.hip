@@ -664,17 +664,32 @@ __device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int 
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
             const int q = (row0 >> 4) + rb;
+            // FP32 state: this lane's rows 4g .. 4g + 3 are one 16-byte run
+            float4 s4 = make_float4(0, 0, 0, 0), g4 = make_float4(0, 0, 0, 0);
+            size_t idx4 = 0;
+            if (!F64) {
+                idx4 = frag_index<false>(tile, Q, 16 * q + 4 * g, c);
+                s4 = *(const float4*)((const float*)S + idx4);
+                if (pending) g4 = *(const float4*)((const float*)Gb + idx4);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * q + out_row<F64>(g, r);
                 const size_t idx = frag_index<F64>(tile, Q, row, c);
                 st_t gv = F64 ? (st_t)acc64[rb][r] : (st_t)acc32[rb][r];
-                st_t sv = S[idx];
-                if (pending) {
-                    sv = fma(-th, Gb[idx], sv);
-                    S[idx] = sv;
+                st_t sv;
+                if (F64) {
+                    sv = S[idx];
+                    if (pending) {
+                        sv = fma(-th, Gb[idx], sv);
+                        S[idx] = sv;
+                    }
+                    Gb[idx] = gv;
+                } else {
+                    sv = (&s4.x)[r];
+                    if (pending) sv = fma(-th, (st_t)(&g4.x)[r], sv);
+                    (&s4.x)[r] = (float)sv;
                 }
-                Gb[idx] = gv;
                 const float na = a.rownorm[row];
                 float dl = fmaf(na, Ek, fmaf(bscale, a.absb[row], 1e-30f));
                 float e = na * ed;
@@ -689,6 +704,11 @@ __device__ void screen(const StepArgs& a, ChainLds* cs, unsigned char* big, int 
                 um = fminf(um, hi_m);
                 lp = fminf(lp, lo_p);
                 lm = fminf(lm, lo_m);
+            }
+            if (!F64) {
+                if (pending) *(float4*)((float*)S + idx4) = s4;
+                *(float4*)((float*)Gb + idx4) = make_float4(acc32[rb][0], acc32[rb][1], acc32[rb][2],
+                                                            acc32[rb][3]);
             }
         }
         // per-group least lower bounds, one value per walk
