@@ -248,6 +248,27 @@ __device__ __forceinline__ size_t frag_index(int tile, int Q, int row, int c)
 // ---------------------------------------------------------------------------
 // Phase A: directions of the 16 walks of this tile at `step`.
 // ---------------------------------------------------------------------------
+// sum over j = lane + 64 k of a[j] b[j] as one FMA chain per lane in
+// increasing k (before a wave reduction); the loads of 8 coordinates per lane
+// are in flight together
+__device__ __forceinline__ double lane_dot(const double* a, const double* b, int n, int lane)
+{
+    double v = 0.0;
+    for (int jb = 0; jb < n; jb += 64 * 8) {
+        double x[8], y[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int j = jb + lane + 64 * e;
+            x[e] = j < n ? a[j] : 0.0;
+            y[e] = j < n ? b[j] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (jb + lane + 64 * e < n) v = fma(x[e], y[e], v);
+    }
+    return v;
+}
+
 // Wide (the chords kernel): the low-rank product two coordinates per thread
 // with U prefetched, and no norms (the caller computes them with the
 // operand); otherwise one coordinate per thread, fewer registers, and the
@@ -453,9 +474,7 @@ __device__ void make_directions(const StepArgs& a, ChainLds* cs, int c0, uint64_
             int chain = c0 + cl;
             double v = 0.0;
             if (chain < a.z) {
-                const double* er = a.Aeq + (size_t)p * lda;
-                const double* hr = base + (size_t)chain * lda;
-                for (int j = lane; j < n; j += 64) v = fma(er[j], hr[j], v);
+                v = lane_dot(a.Aeq + (size_t)p * lda, base + (size_t)chain * lda, n, lane);
             }
             v = wave_sum(v);
             if (lane == 0) cs->y[cl * kMaxMeq + p] = v;
@@ -1767,9 +1786,7 @@ __global__ __launch_bounds__(kDirThreads) void tiled_dirs_kernel(StepArgs a, uin
     if (live && !direct) {
         __syncthreads();
         for (int p = wave; p < a.m_eq; p += kDW) {
-            const double* er = a.Aeq + (size_t)p * lda;
-            double v = 0.0;
-            for (int j = lane; j < n; j += 64) v = fma(er[j], drow[j], v);
+            double v = lane_dot(a.Aeq + (size_t)p * lda, drow, n, lane);
             v = wave_sum(v);
             if (lane == 0) y[p] = v;
         }
