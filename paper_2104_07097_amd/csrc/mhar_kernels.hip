@@ -1419,6 +1419,32 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
             }
         }
     };
+    // half 0 of this wave's slack and last product, issued right after the
+    // last stage load so that it lands during the last two K-steps: exactly
+    // 16 load instructions (rows clamped, G read even without a pending
+    // update), which the waits of those K-steps count
+    auto load_early = [&](float (*sv)[4][4], float (*gp)[4][4]) __attribute__((always_inline)) {
+        const int rbase = min(R0 + wr * 64, a.m_pad - 64);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int cbase = C0 + wc * 64 + h * 16;
+            const int tile = min(cbase, a.z_pad - kChainTile) / kChainTile;
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+                const size_t idx = frag_index<false>(tile, Q, rbase + rt * 16 + 4 * g, c);
+                const float4 s4 = *(const float4*)(S + idx);
+                const float4 g4 = *(const float4*)(Gb + idx);
+                sv[h][rt][0] = s4.x;
+                sv[h][rt][1] = s4.y;
+                sv[h][rt][2] = s4.z;
+                sv[h][rt][3] = s4.w;
+                gp[h][rt][0] = g4.x;
+                gp[h][rt][1] = g4.y;
+                gp[h][rt][2] = g4.z;
+                gp[h][rt][3] = g4.w;
+            }
+        }
+    };
     // the epilogue's per-row and per-walk terms, once per tile into LDS
     // (read by every wave and lane that needs them): row norms, |b| and the
     // split operand's row norms; per walk the product's error coefficients
@@ -1461,17 +1487,26 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     }
     // two stages: K-step k + 1 lands while K-step k is multiplied; K-step
     // k + 2 is issued into the stage K-step k has left
+    float sv0[2][4][4], gp0[2][4][4];
+    const int k_sg = nk_all - 3;   // the K-step whose stage issue is the last
     auto kstep = [&](int k, unsigned char* stage) __attribute__((always_inline)) {
-        if (k + 1 < nk_all) wait_vm<kChunksPerWave>();
-        else wait_vm<0>();
+        if (k > k_sg) {   // the 16 early loads are younger than this K-step's stage loads
+            if (k + 1 < nk_all) wait_vm<kChunksPerWave + 16>();
+            else wait_vm<16>();
+        } else {
+            if (k + 1 < nk_all) wait_vm<kChunksPerWave>();
+            else wait_vm<0>();
+        }
         tile_barrier();   // every wave's loads of K-step k have landed
         compute(stage);
         wait_lds();
         tile_barrier();   // every wave is done reading the stage
         if (k + 2 < nk_all) issue(k + 2, stage);
+        if (k == k_sg) load_early(sv0, gp0);
     };
     issue(0, stage0);
     if (nk_all > 1) issue(1, stage1);
+    if (k_sg < 0) load_early(sv0, gp0);
     for (int k = 0; k < nk_all; k += 2) {
         kstep(k, stage0);
         if (k + 1 < nk_all) kstep(k + 1, stage1);
@@ -1484,11 +1519,10 @@ __device__ void screen_tile(const StepArgs& a, int rb, int cb, int pending, int 
     const int ngroups = a.m_pad / kRowGroup;
     const int grp = (R0 + wr * 64) / kRowGroup;
     const float bscale = a.u_s * (float)T * kHighGrow;
-    // the isotropic kernel issues both halves' loads before the arithmetic
-    // (the second half's land while the first is processed); the split
-    // kernel, short of registers, loads the second half after the first
-    float sv0[2][4][4], gp0[2][4][4], sv1[2][4][4], gp1[2][4][4];
-    load_half(0, sv0, gp0);
+    // half 0 was loaded during the last K-steps; the isotropic kernel issues
+    // half 1's loads before the arithmetic (they land while half 0 is
+    // processed), the split kernel, short of registers, after half 0
+    float sv1[2][4][4], gp1[2][4][4];
     if (!SPLIT) load_half(1, sv1, gp1);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
