@@ -118,9 +118,9 @@ __device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F);
 // most kStagePer 16-byte pieces per thread; they are loaded into registers
 // all at once, and the next chunk's loads are issued before the current
 // chunk's sums, so one load latency per chunk is exposed, not one per piece.
-constexpr int kStagePer = 8;
 constexpr int kUpd = 16;   // coordinates per lane and block in the state update
 static_assert(kThreads == 32 * kChainTile, "32 lanes per walk in the norm pass");
+template <int kStagePer>
 __device__ void exact_rows_staged(const StepArgs& a, ChainLds* cs, int c0, int nc, double* stage,
                                   int nb_max, int C)
 {
@@ -904,9 +904,12 @@ __device__ void exact_chords(const StepArgs& a, ChainLds* cs, int tile, int c0, 
     const int nb_max = 96;
     // chunk width: what the stage holds, and at most kStagePer pieces per thread
     int C = stage ? (int)(stage_bytes / (sizeof(double) * (nb_max + 2 * kChainTile))) - 2 : 0;
+    // (the chords kernel: 16 pieces and 128 columns per chunk, in a stage of
+    // its own; the single-kernel path, short of registers: 8 pieces)
+    constexpr int kStagePer = B > 1 ? 16 : 8;
     C = min(C, 2 * kStagePer * kThreads / (nb_max + 2 * kChainTile)) & ~15;
     if (C >= 16) {
-        exact_rows_staged(a, cs, c0, nc, stage, nb_max, C);
+        exact_rows_staged<kStagePer>(a, cs, c0, nc, stage, nb_max, C);
     } else {
         for (int t = tid; t < nc; t += kThreads) {
             const int2 rc = cs->cand[t];
@@ -1177,8 +1180,8 @@ __global__ __launch_bounds__(kThreads) void mhar_batch_kernel(const StepArgs* __
 // update) is the same code as the single-kernel path, so trajectories agree.
 // ---------------------------------------------------------------------------
 // LDS the chords kernel lends to the exact evaluation: 96 candidates and the
-// x and d rows of 16 walks, 64 coordinates at a time
-constexpr int kChordStageBytes = (96 + 2 * kChainTile) * (64 + 2) * 8;
+// x and d rows of 16 walks, 128 coordinates at a time
+constexpr int kChordStageBytes = (96 + 2 * kChainTile) * (128 + 2) * 8;
 constexpr int kTR = kScreenRows;   // rows per screening tile
 constexpr int kTW = kScreenWalks;  // walks per screening tile
 constexpr int kTK = 32;    // K per LDS stage
