@@ -165,3 +165,34 @@ def test_unbounded_flag_tiled():
     X, st = gu.state(ch)
     assert np.all(st & mhar.CHAIN_UNBOUNDED)
     assert np.all(X == 0.0)
+
+
+@pytest.mark.parametrize("path,prec", [("tiled", "bf16x3"), ("general", "fp64")])
+def test_repeated_facets_overflow_the_candidate_lists(path, prec):
+    """Every facet of the cube [-1,1]^n written k times: the copies of a facet
+    tie, so each walk has at least 2k exact candidate rows and a 16-walk tile
+    more than 32k, past the staged batch of 96 candidates and the tile's list
+    of 512 (the rest is evaluated where it is found); the copies of a facet
+    lie in every 64-row group, so the tile also flags more (walk, group)
+    pairs than its list of 512 holds.  One step and five steps must still
+    be the oracle's, and every walk must evaluate its 2k tied rows."""
+    n, k, z = 40, 48, 32
+    eye = np.eye(n)
+    A = np.vstack([np.tile(eye, (k, 1)), np.tile(-eye, (k, 1))])
+    X0 = np.random.default_rng(9).uniform(-0.5, 0.5, size=(z, n))
+    p = inst.Polytope("repeated_cube", A, np.ones(2 * n * k), X0)
+    orc = Oracle()
+    gu.announce("repeated facets", path, prec, "m", p.m)
+    _, ch = gu.make(p, prec, recompute_every=4, path=path)
+    ch.step(1)
+    got, st = gu.state(ch)
+    want, wst, _ = orc.run(p.A, p.b, X0, 1, seed=0)
+    assert not st.any() and not wst.any()
+    assert gu.rel_err(got, want) <= 1e-11
+    assert ch.stats()["exact_rows"] >= 2 * k * z
+    ch.step(4)
+    got5, st = gu.state(ch)
+    want5, _, _ = orc.run(p.A, p.b, X0, 5, seed=0)
+    assert not st.any()
+    assert gu.rel_err(got5, want5) <= 1e-10
+    assert gu.feasible(p, got5)
