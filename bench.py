@@ -46,8 +46,8 @@ MFMA_PER_FLOP = {"fp32": 1, "bf16x3": 3, "fp64": 1}   # matrix-core products per
 # was measured on: reported as null once any of them differs.
 TRAFFIC = {
     "precision": "bf16x3", "steps_per_launch": 500,
-    "sources_sha256": "1dc841d2bf34b73bc441e65eb111bcb98459693a6f3e030a178795d5da5512d0",
-    "fetch_kib": 25222.6, "fetch_scale": 262144.0 / 131095.4375,
+    "sources_sha256": "ba25c16e15e1176bf882ecd3115ad6940d023c1e156b859af98f3e3bb2464376",
+    "fetch_kib": 24949.6, "fetch_scale": 262144.0 / 131095.6875,
     "write_kib": 46360.0, "write_scale": 262144.0 / 262144.0,
 }
 

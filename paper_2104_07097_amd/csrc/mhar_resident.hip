@@ -169,6 +169,15 @@ __device__ __forceinline__ void wave_sum4(double* q) { wave_sums<4>(q); }
 
 static_assert(kChainTile == 2 * kWaves, "each wave owns two walks of the tile");
 
+// 16 bytes from global memory to LDS byte address lds + 16 * lane (the LDS
+// base is wave-uniform, in M0); counted by vmcnt, returns no registers.
+__device__ __forceinline__ void row_to_lds(const void* src, unsigned lds)
+{
+    asm volatile("global_load_lds_dwordx4 %0, off" :: "v"(src), "{m0}"(lds) : "memory");
+}
+// Wait until no vector-memory operation of this wave is outstanding.
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0 | (7 << 4) | (15 << 8)); }
+
 template <int P, int NK>
 __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
 {
@@ -557,35 +566,22 @@ __global__ __launch_bounds__(kThreads) void resident_kernel(StepArgs a)
                     cc = cs->cand_chain[wave][lane];
                     bi = a.b64[rr];
                 }
-                // stage the rows, four at a time: the four loads are issued
-                // before the first store (a missing candidate repeats the
-                // last one, so the loads need no branch)
+                // stage the rows straight from global memory into LDS, one
+                // instruction per 128 coordinates of a row, all in flight at
+                // once (no registers held; the wave reads only its own rows)
 #pragma unroll
-                for (int q0 = 0; q0 < kCandBatch; q0 += 4) {
-                    if (q0 < cnt) {
-                        double2 rv[4][kPer];
+                for (int q = 0; q < kCandBatch; ++q) {
+                    if (q < cnt) {
+                        const double* ar = a.A64 + (size_t)cs->cand_row[wave][q] * a.lda;
+                        const unsigned dst = (unsigned)(size_t)(cb + q * cld);
 #pragma unroll
-                        for (int qq = 0; qq < 4; ++qq) {
-                            const int q = min(q0 + qq, cnt - 1);
-                            const double* ar = a.A64 + (size_t)cs->cand_row[wave][q] * a.lda;
-#pragma unroll
-                            for (int t = 0; t < kPer; ++t) {
-                                const int j = min(2 * lane + 128 * t, lda - 2);
-                                rv[qq][t] = *(const double2*)(ar + j);
-                            }
-                        }
-#pragma unroll
-                        for (int qq = 0; qq < 4; ++qq) {
-                            if (q0 + qq < cnt) {
-#pragma unroll
-                                for (int t = 0; t < kPer; ++t) {
-                                    const int j = 2 * lane + 128 * t;
-                                    if (j < lda) *(double2*)(cb + (q0 + qq) * cld + j) = rv[qq][t];
-                                }
-                            }
+                        for (int t = 0; t < kPer; ++t) {
+                            const int j = 2 * lane + 128 * t;
+                            if (j < lda) row_to_lds(ar + j, dst + 1024u * t);
                         }
                     }
                 }
+                wait_vm_all();
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 // the line-set formula of S4.4 in the operation order of a
