@@ -46,8 +46,8 @@ MFMA_PER_FLOP = {"fp32": 1, "bf16x3": 3, "fp64": 1}   # matrix-core products per
 # was measured on: reported as null once any of them differs.
 TRAFFIC = {
     "precision": "bf16x3", "steps_per_launch": 500,
-    "sources_sha256": "ba25c16e15e1176bf882ecd3115ad6940d023c1e156b859af98f3e3bb2464376",
-    "fetch_kib": 24949.6, "fetch_scale": 262144.0 / 131095.6875,
+    "sources_sha256": "3d64313158de760fb0bbb57f9929095e2c2028d64eb10d55ca8742db40c00f1f",
+    "fetch_kib": 25411.8, "fetch_scale": 262144.0 / 131095.3125,
     "write_kib": 46360.0, "write_scale": 262144.0 / 262144.0,
 }
 
@@ -89,9 +89,9 @@ def measured_traffic(precision, launch_steps):
 # same run; None until measured, and null once the kernel's sources change.
 TRAFFIC_ROTBOX = {
     "precision": "bf16x3",
-    "sources_sha256": "880ca4757eec6b1ff420d501cab3b024a7cd5de68f426e2c70d319d6b49122c0",
-    "fetch_kib": 885280.7, "fetch_scale": 262144.0 / 131089.75,
-    "write_kib": 654333.4, "write_scale": 262144.0 / 262144.0,
+    "sources_sha256": "832abf253cf965f59a2c4bb43aa09c2826394f251e4889aa3c13b39dab19e565",
+    "fetch_kib": 888376.2, "fetch_scale": 262144.0 / 131089.125,
+    "write_kib": 654349.5, "write_scale": 262144.0 / 262144.0,
 }
 TRAFFIC_ROTBOX_SOURCES = ["paper_2104_07097_amd/csrc/mhar_kernels.hip",
                           "paper_2104_07097_amd/csrc/mhar_device.hpp",

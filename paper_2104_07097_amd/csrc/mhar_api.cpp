@@ -52,7 +52,6 @@ struct mhar_chains {
     double* dn;
     int* flags;
     unsigned long long* counters;
-    float* gU;
     unsigned long long* gL;
     unsigned* gbar;
     int* gerr;
@@ -224,7 +223,6 @@ size_t carve_chains(const mhar_problem* p, int z_pad, void* ws, mhar_chains* ch)
     q->flags = c.take<int>(z_pad);
     q->counters = c.take<unsigned long long>(8);
     const size_t tiles = (size_t)z_pad / kChainTile;
-    q->gU = c.take<float>(tiles * 3 * 2 * kChainTile);
     q->gL = c.take<unsigned long long>(tiles * 3 * 2 * kChainTile);
     q->gbar = c.take<unsigned>(tiles);
     q->gerr = c.take<int>(64);
@@ -321,7 +319,6 @@ StepArgs make_args(const mhar_chains* c)
         a.uF = c->pc.uF;
         a.eps_g = c->pc_eps_g;
     }
-    a.gU = c->gU;
     a.gL = c->gL;
     a.gbar = c->gbar;
     a.gerr = c->gerr;
@@ -384,9 +381,7 @@ hipError_t launch_any(mhar_chains* c, const StepArgs& a, hipStream_t stream)
     if (c->split > 1) {
         // fresh exchange slots and arrival counters for this launch
         const int64_t tiles = c->z_pad / kChainTile;
-        hipError_t e = launch_fill_i32((int*)c->gU, tiles * 3 * 2 * kChainTile, 0x7f800000, stream);
-        if (e == hipSuccess)
-            e = launch_fill_u64(c->gL, tiles * 3 * 2 * kChainTile, 0x7FF0000000000000ull, stream);
+        hipError_t e = launch_fill_u64(c->gL, tiles * 3 * 2 * kChainTile, 0x7FF0000000000000ull, stream);
         if (e == hipSuccess) e = launch_fill_i32((int*)c->gbar, tiles, 0, stream);
         if (e != hipSuccess) return e;
     }

@@ -103,7 +103,6 @@ struct StepArgs {
     // row split of the resident kernel (workgroups per walk tile) and the
     // device-scope exchange buffers of a split launch
     int split;
-    float* gU;                     // per tile: 3 slots x 2 x 16 bound bits
     unsigned long long* gL;        // per tile: 3 slots x 2 x 16 exact chord-end bits
     unsigned* gbar;                // per tile: arrival counter
     int* gerr;                     // set when a group wait timed out
