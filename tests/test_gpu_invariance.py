@@ -1,4 +1,5 @@
-"""Launch length does not change the samples.
+"""The samples do not depend on how the work is cut: into launches, or into
+handles of fewer walks.
 
 The chord of every step is the exact FP64 chord of a certified candidate set
 (S4.4), and the random numbers of a step are keyed by (walk, step) alone, so
@@ -56,3 +57,37 @@ def test_short_launches_give_the_same_states(case):
     assert np.array_equal(Xs, Xl)
     assert not np.array_equal(Xs, p.X0)          # the walks moved
     assert gu.feasible(p, Xs)
+
+
+def _run_walks(p, prec, path, X0, offset, steps):
+    import torch
+    from paper_2104_07097_amd import mhar
+    dev = gu.device()
+    t = lambda a: None if a is None else torch.tensor(a, device=dev, dtype=torch.float64)
+    prob = mhar.Problem(t(p.A), t(p.b), t(p.A_eq), t(p.b_eq), precision=prec, recompute_every=6,
+                        path=path)
+    ch = mhar.Chains(prob, t(X0), seed=3, chain_offset=offset)
+    ch.step(steps)
+    X, st = gu.state(ch)
+    kernel = ch.stats()["kernel"]
+    ch.close()
+    prob.close()
+    return X, st, kernel
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_walks_do_not_depend_on_their_neighbours(case):
+    """A walk's draws are keyed by its global index (the handle's chain offset
+    plus its position), so a contiguous subset of the walks, run alone in a
+    handle of its own, follows bitwise the same trajectories as inside the
+    whole set, although tiles, workgroups and padding differ."""
+    make, path, prec = CASES[case]
+    p = make()
+    z = p.X0.shape[0]
+    k0, zs = z // 4 + 1, z // 2 - 1
+    gu.announce("walk subset", case, f"z={z}", f"walks {k0}..{k0 + zs - 1}", prec)
+    Xf, sf, kf = _run_walks(p, prec, path, p.X0, 0, 23)
+    Xs, ss, ks = _run_walks(p, prec, path, p.X0[k0:k0 + zs], k0, 23)
+    assert kf == ks == KERNEL[path]
+    assert not sf.any() and not ss.any()
+    assert np.array_equal(Xs, Xf[k0:k0 + zs])
