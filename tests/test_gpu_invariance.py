@@ -29,14 +29,16 @@ CASES = {
 }
 
 
-def _run(p, prec, path, steps_per_launch, steps):
+def _run(p, prec, path, steps, steps_per_launch=0, X0=None, offset=0):
+    """States, status bits and kernel path after `steps` steps of walks X0
+    (default: all of p's) whose global indices start at `offset`."""
     import torch
     from paper_2104_07097_amd import mhar
     dev = gu.device()
     t = lambda a: None if a is None else torch.tensor(a, device=dev, dtype=torch.float64)
     prob = mhar.Problem(t(p.A), t(p.b), t(p.A_eq), t(p.b_eq), precision=prec, recompute_every=6,
                         steps_per_launch=steps_per_launch, path=path)
-    ch = mhar.Chains(prob, t(p.X0), seed=3)
+    ch = mhar.Chains(prob, t(p.X0 if X0 is None else X0), seed=3, chain_offset=offset)
     ch.step(steps)
     X, st = gu.state(ch)
     kernel = ch.stats()["kernel"]
@@ -50,29 +52,13 @@ def test_short_launches_give_the_same_states(case):
     make, path, prec = CASES[case]
     p = make()
     gu.announce("launch length", case, f"n={p.A.shape[1]}", f"m={p.A.shape[0]}", prec)
-    Xs, ss, ks = _run(p, prec, path, 5, 37)     # 7 launches of 5 steps and one of 2
-    Xl, sl, kl = _run(p, prec, path, 37, 37)    # one launch
+    Xs, ss, ks = _run(p, prec, path, 37, steps_per_launch=5)    # 7 launches of 5 steps and one of 2
+    Xl, sl, kl = _run(p, prec, path, 37, steps_per_launch=37)   # one launch
     assert ks == kl == KERNEL[path]
     assert not ss.any() and not sl.any()
     assert np.array_equal(Xs, Xl)
     assert not np.array_equal(Xs, p.X0)          # the walks moved
     assert gu.feasible(p, Xs)
-
-
-def _run_walks(p, prec, path, X0, offset, steps):
-    import torch
-    from paper_2104_07097_amd import mhar
-    dev = gu.device()
-    t = lambda a: None if a is None else torch.tensor(a, device=dev, dtype=torch.float64)
-    prob = mhar.Problem(t(p.A), t(p.b), t(p.A_eq), t(p.b_eq), precision=prec, recompute_every=6,
-                        path=path)
-    ch = mhar.Chains(prob, t(X0), seed=3, chain_offset=offset)
-    ch.step(steps)
-    X, st = gu.state(ch)
-    kernel = ch.stats()["kernel"]
-    ch.close()
-    prob.close()
-    return X, st, kernel
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
@@ -86,8 +72,8 @@ def test_walks_do_not_depend_on_their_neighbours(case):
     z = p.X0.shape[0]
     k0, zs = z // 4 + 1, z // 2 - 1
     gu.announce("walk subset", case, f"z={z}", f"walks {k0}..{k0 + zs - 1}", prec)
-    Xf, sf, kf = _run_walks(p, prec, path, p.X0, 0, 23)
-    Xs, ss, ks = _run_walks(p, prec, path, p.X0[k0:k0 + zs], k0, 23)
+    Xf, sf, kf = _run(p, prec, path, 23)
+    Xs, ss, ks = _run(p, prec, path, 23, X0=p.X0[k0:k0 + zs], offset=k0)
     assert kf == ks == KERNEL[path]
     assert not sf.any() and not ss.any()
     assert np.array_equal(Xs, Xf[k0:k0 + zs])
